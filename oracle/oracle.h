@@ -1,0 +1,90 @@
+/* oracle.h -- plain FP64 CPU oracle of the lifted primal-dual iteration of
+ * Moellenhoff, Laude, Moeller, Lellmann, Cremers, "Sublabel-Accurate Relaxation of
+ * Nonconvex Energies" (CVPR 2016).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library may include, link or call
+ * this code; it exists so that tests, the smoke check and the CPU baseline of the
+ * benchmark can compare the HIP path against a slow, obviously correct reference.
+ * It shares no code, header or table with the HIP path.
+ *
+ * All arithmetic is IEEE double except one documented decision taken in float (the
+ * classification of truncated-quadratic intervals, see or_desc.rho), which the HIP
+ * path takes in the same precision.
+ */
+#ifndef SUBLABEL_ORACLE_H
+#define SUBLABEL_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_QUAD = 0, OR_TRUNC_QUAD = 1, OR_SAMPLED = 2 };
+enum { OR_PIECE_QUAD = 0, OR_PIECE_PL = 1 };
+
+typedef struct {
+  int32_t H, W, L;          /* image size, number of labels (L >= 2)                 */
+  const double *gamma;      /* [L] strictly increasing labels                          */
+  int32_t rho;              /* OR_QUAD, OR_TRUNC_QUAD or OR_SAMPLED                    */
+  const float *f;           /* [H*W] data image (QUAD / TRUNC_QUAD)                    */
+  double a, nu;             /* rho = a/2 (t-f)^2, truncated at nu (TRUNC_QUAD)          */
+  int32_t M;                /* number of sample positions                              */
+  const double *tau;        /* [M] sample positions; every label must be one of them   */
+  const float *samples;     /* [M][H*W]: SAMPLED costs, or (QUAD/TRUNC, M == L)
+                               per-label additive values w                              */
+  double lambda;            /* TV weight                                               */
+  int32_t normalize;        /* 1: iterate on labels mapped affinely onto [0,1]         */
+  int32_t n_sub;            /* samples per straddling truncated-quadratic interval     */
+} or_desc;
+
+typedef struct {
+  double primal;      /* repaired primal value at the current iterate (upper bound)   */
+  double dual;        /* dual value at the current iterate (lower bound)              */
+  double best_primal, best_dual;
+  double gap, best_gap, rel_gap;
+  double e_nc;        /* nonconvex energy of the back-projected u, true data term     */
+  int64_t iters;
+} or_report;
+
+typedef struct or_problem or_problem;
+
+const char *or_last_error(void);
+or_problem *or_create(const or_desc *d);
+void or_destroy(or_problem *P);
+int or_num_threads(int n);                 /* sets OpenMP threads if n > 0; returns count */
+
+void or_run(or_problem *P, int iters);
+void or_monitor(or_problem *P, or_report *out);
+int64_t or_state_size(const or_problem *P);       /* doubles in the packed state        */
+void or_get_state(const or_problem *P, double *out);
+void or_set_state(or_problem *P, const double *in);
+void or_read_u(const or_problem *P, double *u_lifted, double *u);
+void or_normalized(const or_problem *P, double *gam, double *lam, double *shift, double *scale);
+
+/* operator and steps of the saddle-point problem */
+void or_apply_K(const or_problem *P, const double *u, const double *s, double *Kv,
+                double *Kq, double *Kpx, double *Kpy, double *Kz);
+void or_apply_KT(const or_problem *P, const double *v, const double *q, const double *px,
+                 const double *py, const double *z, double *Ku, double *Ks);
+void or_steps(const or_problem *P, double *sigma_p, double *sigma_vz, double *sigma_q,
+              double *tau_u, double *tau_s);
+void or_piece(const or_problem *P, int64_t x, int i, int *kind, double *acd, int *n,
+              double *t, double *r);
+
+/* primitives */
+void or_grad(int H, int W, const double *u, double *gx, double *gy);
+void or_div(int H, int W, const double *px, const double *py, double *d);
+double or_conj_quad(double a, double c, double d, double g0, double g1, double y);
+void or_proj_epi_quad(double a, double c, double d, double g0, double g1, double *y,
+                      double *w);
+double or_conj_pl(int n, const double *t, const double *r, double y);
+void or_proj_epi_pl(int n, const double *t, const double *r, double *y, double *w);
+int or_lower_hull(int n, const double *t, const double *r, int *idx);
+void or_proj_simplex(int n, const double *x, double *out);
+void or_proj_ball(double *px, double *py, double radius);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
