@@ -1,0 +1,182 @@
+/* sublabel.h -- C-ABI of the MI355X (gfx950) lifted primal-dual solver for the
+ * sublabel-accurate convex relaxation of
+ *
+ *     min_u  sum_x rho(x, u(x)) + lambda TV(u),   u : Omega -> Gamma = [gamma_1, gamma_L]
+ *
+ * (eq. 1 of Moellenhoff, Laude, Moeller, Lellmann, Cremers, "Sublabel-Accurate
+ * Relaxation of Nonconvex Energies", CVPR 2016).
+ *
+ * The range Gamma is sampled at labels gamma_1 < ... < gamma_L (Sec. 3); the lifted
+ * variable u(x) in R^k, k = L-1, is driven by the first-order primal-dual iteration on
+ * the saddle-point problem of Sec. 4 (dual (v, q) in the set C of per-interval
+ * epigraph constraints, rewritten with the auxiliary z and the multiplier s; dual p in
+ * the set K of Prop. 5), with diagonal preconditioning.
+ *
+ * Conventions common to every entry point
+ *  - Every function returns sl_status; nothing throws or aborts across the ABI. On an
+ *    error, sl_last_error() returns a thread-local message describing it.
+ *  - Argument checks run before any device work; a failed check returns
+ *    SL_ERR_INVALID_ARG and leaves every buffer untouched.
+ *  - Device buffers are plain device pointers (hipMalloc'd or a framework's tensor
+ *    storage) on the device that is current when sl_create is called. The library itself
+ *    never allocates device memory: all device storage it uses lives in the caller's
+ *    workspace.
+ *  - Work is enqueued on the hipStream_t given to sl_create (NULL = legacy stream);
+ *    calls are asynchronous unless stated otherwise.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *
+ * Storage layout of the lifted fields: planar, label-major, row-major: element (i, r, c)
+ * of a [k][H][W] field is at i*H*W + r*W + c in the packed layouts used by
+ * sl_read_u / sl_save_state (the workspace uses its own padded layout internally).
+ */
+#ifndef SUBLABEL_H
+#define SUBLABEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sl_problem_ *sl_problem; /* opaque, owned by the library */
+
+typedef enum {
+  SL_OK = 0,
+  SL_ERR_INVALID_ARG = 1, /* a documented precondition does not hold                  */
+  SL_ERR_UNSUPPORTED = 2, /* valid, but outside what this build implements            */
+  SL_ERR_DEVICE = 3,      /* a HIP runtime call failed (no device, launch failure ...) */
+  SL_ERR_WORKSPACE = 4,   /* workspace pointer NULL, misaligned or too small          */
+  SL_ERR_NUMERIC = 5      /* a NaN / Inf appeared in the energy monitor               */
+} sl_status;
+
+/* Data-term kinds (Sec. 4 supports quadratic and piecewise-linear convex pieces).
+ *  SL_RHO_QUAD       rho(x,t) = a/2 (t - f(x))^2                       (Sec. 5.1, ROF)
+ *  SL_RHO_TRUNC_QUAD rho(x,t) = min(a/2 (t - f(x))^2, nu)              (Sec. 5.2)
+ *                    intervals inside the band |t-f| <= sqrt(2 nu / a) are quadratic
+ *                    pieces, intervals outside it are constant (nu), intervals that
+ *                    straddle a band edge use the convex envelope of 16 equispaced
+ *                    samples of rho on the interval.
+ *  SL_RHO_SAMPLED    rho given at sample positions tau_m (M planes of costs); on every
+ *                    interval the convex envelope of its samples is used (Sec. 5.4). */
+typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2 } sl_rho_kind;
+
+/* TV kind: isotropic (Prop. 5: K is a product of l2 balls). */
+typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;
+
+/* Storage precision of the iteration state. FP32: everything in float. BF16_DUAL: the
+ * dual fields v, z and p are stored as bfloat16 (round to nearest even); arithmetic is
+ * float, energies and gaps are accumulated in double in both modes. */
+typedef enum { SL_STORE_FP32 = 0, SL_STORE_BF16_DUAL = 1 } sl_storage;
+
+typedef struct {
+  int32_t H, W, L;         /* H, W >= 1; 2 <= L <= SL_MAX_LABELS                         */
+  const double *gamma;     /* HOST [L], finite, strictly increasing; copied               */
+  sl_rho_kind rho;
+  const float *f;          /* DEVICE [H*W] data image (QUAD, TRUNC_QUAD); NULL for
+                              SAMPLED; read during sl_create only                          */
+  double a, nu;            /* a > 0 (QUAD, TRUNC_QUAD); nu > 0 (TRUNC_QUAD)                */
+  int32_t M;               /* number of sample positions (0 if samples == NULL)           */
+  const double *tau;       /* HOST [M] strictly increasing; every gamma_j must equal one
+                              tau_m; copied                                                */
+  const float *samples;    /* DEVICE [M][H*W]. SAMPLED: the costs rho(x, tau_m).
+                              QUAD / TRUNC_QUAD with M == L and tau == gamma: per-label
+                              additive values w_j(x), interpolated linearly between
+                              labels and added to rho. May be NULL. Read in sl_create. */
+  double lambda;           /* >= 0                                                        */
+  sl_tv_kind tv;           /* SL_TV_ISO only in this build (ANISO -> SL_ERR_UNSUPPORTED)  */
+  sl_storage storage;
+  int32_t check_every;     /* iterations between gap checks in sl_run_to_gap (>= 1)      */
+  int32_t normalize_labels;/* 1: iterate on the labels mapped affinely onto [0,1] (an
+                              exact reparametrisation; energies are unchanged)            */
+  int32_t adaptive_steps;  /* must be 0 in this build                                     */
+} sl_problem_desc;
+
+#define SL_MAX_LABELS 28      /* k = L-1 <= 27                                           */
+#define SL_MAX_SAMPLES 256    /* M for SAMPLED                                            */
+
+typedef struct {
+  double primal_ub;   /* certified upper bound of the relaxed optimum at the current iterate */
+  double dual_lb;     /* certified lower bound at the current iterate                        */
+  double gap;         /* primal_ub - dual_lb                                                  */
+  double best_gap;    /* min primal_ub so far - max dual_lb so far (monotone)                */
+  double rel_gap;     /* best_gap / max(|best primal|, |best dual|)                           */
+  double e_nonconvex; /* eq. 1 for the back-projected u with the original data term          */
+  int64_t iters;      /* iterations run since creation (or since the last sl_load_state)     */
+  double best_primal, best_dual;
+} sl_report;
+
+/* Bytes of device workspace sl_create needs for this problem (no device work). */
+sl_status sl_workspace_size(const sl_problem_desc *desc, size_t *bytes);
+
+/* Validate desc, carve the caller's workspace (>= sl_workspace_size bytes, 256-byte
+ * aligned, owned by the caller and kept alive until sl_destroy), normalise labels, build
+ * the per-interval convex envelopes of sampled costs (Sec. 5.4) and zero the iteration
+ * state (u = s = v = z = p = q = 0). Non-finite values in f or samples are argument
+ * errors (checked on the device before the state is touched). Synchronises the stream
+ * before returning, so f and samples may be freed afterwards. Cites: lifting Sec. 3,
+ * pieces Prop. 1 and Sec. 4. */
+sl_status sl_create(const sl_problem_desc *desc, void *dev_workspace, size_t bytes,
+                    void *hip_stream, sl_problem *out);
+
+/* Enqueue `iters` (>= 0) primal-dual iterations (Sec. 4): one fused kernel per iteration
+ * performs the dual ascent on (v, z, q, p) at the over-relaxed primal point, the
+ * projections onto the scaled epigraphs of rho_i^* and onto the l2 balls of K, and the
+ * primal descent on (u, s). Asynchronous. */
+sl_status sl_run(sl_problem p, int32_t iters);
+
+/* Run in chunks of check_every iterations until the certified relative gap is
+ * <= rel_gap or max_iters iterations were run; *done (may be NULL) receives the number
+ * of iterations run by this call. Synchronises the stream once per check. Returns
+ * SL_ERR_NUMERIC if a check sees a non-finite energy. */
+sl_status sl_run_to_gap(sl_problem p, double rel_gap, int32_t max_iters, int32_t *done);
+
+/* Write the lifted u ([k][H][W], float, may be NULL) and the back-projected
+ * u(x) = gamma_1 + sum_i clamp(u_i, 0, 1) (gamma_{i+1} - gamma_i)  (Sec. 3, layer-cake
+ * formula) ([H][W], float, may be NULL) to caller device buffers. Asynchronous. */
+sl_status sl_read_u(sl_problem p, float *u_lifted_dev, float *u_dev);
+
+/* Evaluate the certified bounds, the gap and the nonconvex energy at the current
+ * iterate (FP64 reductions, fixed order: bitwise reproducible) and update the best-so-far
+ * values. Synchronises the stream. */
+sl_status sl_energy(sl_problem p, sl_report *out);
+
+/* Bytes of the packed FP32 state: (8k + 1) * H * W * 4, order
+ * u, u_prev, s, s_prev, v, z, p_x, p_y ([k][H][W] each), q ([H][W]). */
+sl_status sl_state_size(sl_problem p, size_t *bytes);
+
+/* Copy the iteration state to / from a caller device buffer in the packed FP32 layout
+ * above (BF16 fields are widened on save and rounded to nearest even on load). Loading
+ * resets the best-so-far bounds and the iteration counter. Asynchronous. */
+sl_status sl_save_state(sl_problem p, void *dev_dst, size_t bytes);
+sl_status sl_load_state(sl_problem p, const void *dev_src, size_t bytes);
+
+/* Batched solve: n independent problems share one workspace and are advanced together
+ * by one persistent launch per iteration over a work list of (instance, tile).
+ * Returns SL_ERR_UNSUPPORTED in this build. */
+sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *dev_workspace,
+                          size_t bytes, void *hip_stream, sl_problem *out);
+
+/* Unrolled differentiation: K iterations with checkpoints every C iterations, then the
+ * adjoint pass. Return SL_ERR_UNSUPPORTED in this build. */
+sl_status sl_unrolled_forward(sl_problem p, int32_t K, int32_t C, void *ckpt_ws,
+                              size_t bytes);
+sl_status sl_unrolled_backward(sl_problem p, const float *grad_u_dev, float *grad_f_dev,
+                               double *grad_lambda, float *grad_w_dev);
+
+/* Tuning knob: rows of the tile each thread of the fused iteration owns (1 or 2; a
+ * tile is 64 columns x 4*rows_per_thread rows). Results do not depend on it. Returns
+ * SL_ERR_UNSUPPORTED if the tile would need more LDS than a workgroup may use. */
+sl_status sl_set_tile_rows(sl_problem p, int32_t rows_per_thread);
+
+/* Release the handle (NULL-safe). Does not free the caller's workspace; waits for the
+ * handle's stream first. */
+void sl_destroy(sl_problem p);
+
+const char *sl_status_string(sl_status s);
+const char *sl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

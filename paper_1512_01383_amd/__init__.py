@@ -1,0 +1,229 @@
+"""MI355X (gfx950) solver for the sublabel-accurate convex relaxation of
+min_u sum_x rho(x, u(x)) + lambda TV(u) (Moellenhoff et al., CVPR 2016).
+
+This module is a thin ctypes binding of ``libsublabel.so`` (C-ABI in
+``include/sublabel.h``): it marshals arguments, allocates the workspace and the
+input copies as torch device tensors, and passes torch's current HIP stream. Every step
+of the iteration, the monitor and the read-out runs in the library's HIP kernels; if the
+library is missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsublabel.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "sublabel.h")
+
+RHO_QUAD, RHO_TRUNC_QUAD, RHO_SAMPLED = 0, 1, 2
+TV_ISO, TV_ANISO = 0, 1
+STORE_FP32, STORE_BF16_DUAL = 0, 1
+
+STATUS = {0: "SL_OK", 1: "SL_ERR_INVALID_ARG", 2: "SL_ERR_UNSUPPORTED", 3: "SL_ERR_DEVICE",
+          4: "SL_ERR_WORKSPACE", 5: "SL_ERR_NUMERIC"}
+
+
+class SublabelError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("L", C.c_int32),
+                ("gamma", C.POINTER(C.c_double)), ("rho", C.c_int32),
+                ("f", C.c_void_p), ("a", C.c_double), ("nu", C.c_double),
+                ("M", C.c_int32), ("tau", C.POINTER(C.c_double)), ("samples", C.c_void_p),
+                ("lam", C.c_double), ("tv", C.c_int32), ("storage", C.c_int32),
+                ("check_every", C.c_int32), ("normalize_labels", C.c_int32),
+                ("adaptive_steps", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("primal_ub", C.c_double), ("dual_lb", C.c_double), ("gap", C.c_double),
+                ("best_gap", C.c_double), ("rel_gap", C.c_double), ("e_nonconvex", C.c_double),
+                ("iters", C.c_int64), ("best_primal", C.c_double), ("best_dual", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Names of the functions declared in include/sublabel.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sl_[a-z_]+)\s*\(", txt)))
+
+
+def lib():
+    """Load libsublabel.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1512_01383_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.sl_status_string.restype = C.c_char_p
+        L.sl_status_string.argtypes = [C.c_int]
+        L.sl_last_error.restype = C.c_char_p
+        L.sl_workspace_size.argtypes = [C.POINTER(Desc), C.POINTER(sz)]
+        L.sl_create.argtypes = [C.POINTER(Desc), vp, sz, vp, C.POINTER(vp)]
+        L.sl_run.argtypes = [vp, C.c_int32]
+        L.sl_run_to_gap.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(C.c_int32)]
+        L.sl_read_u.argtypes = [vp, vp, vp]
+        L.sl_energy.argtypes = [vp, C.POINTER(Report)]
+        L.sl_state_size.argtypes = [vp, C.POINTER(sz)]
+        L.sl_save_state.argtypes = [vp, vp, sz]
+        L.sl_load_state.argtypes = [vp, vp, sz]
+        L.sl_set_tile_rows.argtypes = [vp, C.c_int32]
+        L.sl_destroy.argtypes = [vp]
+        L.sl_destroy.restype = None
+        for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
+                     "sl_energy", "sl_state_size", "sl_save_state", "sl_load_state",
+                     "sl_set_tile_rows"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise SublabelError(status, lib().sl_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_f32(a, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
+
+
+class Problem:
+    """One lifted problem on one GPU. Inputs may be numpy arrays or torch tensors."""
+
+    def __init__(self, H: int, W: int, gamma, rho: int, lam: float, f=None, a: float = 1.0,
+                 nu: float = 0.0, tau=None, samples=None, storage: str = "fp32",
+                 normalize: bool = True, check_every: int = 50, device=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        L_ = lib()
+        self.H, self.W = int(H), int(W)
+        self.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+        self.k = len(self.gamma) - 1
+        self._keep = {}
+        d = Desc()
+        d.H, d.W, d.L = self.H, self.W, len(self.gamma)
+        d.gamma = self.gamma.ctypes.data_as(C.POINTER(C.c_double))
+        d.rho = int(rho)
+        if f is not None:
+            self._keep["f"] = _dev_f32(f, self.device).reshape(-1)
+            d.f = self._keep["f"].data_ptr()
+        d.a, d.nu = float(a), float(nu)
+        if tau is not None:
+            self.tau = np.ascontiguousarray(tau, dtype=np.float64)
+            self._keep["samples"] = _dev_f32(samples, self.device).reshape(-1)
+            d.M = len(self.tau)
+            d.tau = self.tau.ctypes.data_as(C.POINTER(C.c_double))
+            d.samples = self._keep["samples"].data_ptr()
+        d.lam = float(lam)
+        d.tv = TV_ISO
+        d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
+        d.check_every = int(check_every)
+        d.normalize_labels = 1 if normalize else 0
+        d.adaptive_steps = 0
+        self.desc = d
+        nbytes = C.c_size_t()
+        _check(L_.sl_workspace_size(C.byref(d), C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L_.sl_create(C.byref(d), C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self._keep = None    # sl_create synchronised after reading the inputs
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        return cls(wl.H, wl.W, wl.gamma, wl.rho, wl.lam, f=wl.f, a=wl.a, nu=wl.nu, tau=wl.tau,
+                   samples=wl.samples, **kw)
+
+    # ------------------------------------------------------------------ calls
+    def run(self, iters: int):
+        _check(lib().sl_run(self.h, int(iters)))
+
+    def run_to_gap(self, rel_gap: float, max_iters: int) -> int:
+        done = C.c_int32()
+        _check(lib().sl_run_to_gap(self.h, float(rel_gap), int(max_iters), C.byref(done)))
+        return done.value
+
+    def read_u(self):
+        torch = _torch()
+        ul = torch.empty((self.k, self.H, self.W), dtype=torch.float32, device=self.device)
+        u = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        _check(lib().sl_read_u(self.h, C.c_void_p(ul.data_ptr()), C.c_void_p(u.data_ptr())))
+        return ul, u
+
+    def energy(self) -> dict:
+        r = Report()
+        _check(lib().sl_energy(self.h, C.byref(r)))
+        return r.as_dict()
+
+    def state_size(self) -> int:
+        n = C.c_size_t()
+        _check(lib().sl_state_size(self.h, C.byref(n)))
+        return n.value
+
+    def save_state(self):
+        torch = _torch()
+        t = torch.empty(self.state_size() // 4, dtype=torch.float32, device=self.device)
+        _check(lib().sl_save_state(self.h, C.c_void_p(t.data_ptr()), t.numel() * 4))
+        return t
+
+    def load_state(self, t):
+        t = _dev_f32(t, self.device).reshape(-1)
+        _check(lib().sl_load_state(self.h, C.c_void_p(t.data_ptr()), t.numel() * 4))
+        self.stream.synchronize()
+
+    def set_tile_rows(self, rows_per_thread: int):
+        _check(lib().sl_set_tile_rows(self.h, int(rows_per_thread)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+STATE_ORDER = ("u", "u_prev", "s", "s_prev", "v", "z", "px", "py", "qd")
+
+
+def unpack_state(t, k: int, H: int, W: int) -> dict:
+    """Split a packed state vector into named [k][H][W] / [H][W] arrays (numpy)."""
+    a = t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+    kN = k * H * W
+    out = {n: a[b * kN:(b + 1) * kN].reshape(k, H, W) for b, n in enumerate(STATE_ORDER[:-1])}
+    out["qd"] = a[8 * kN:].reshape(H, W)
+    return out
+
+
+def pack_state(st: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(st[n], np.float32).reshape(-1) for n in STATE_ORDER])

@@ -1,0 +1,514 @@
+// aux.hip -- set-up, read-out, state packing and the certified energy monitor.
+//
+// Monitor (FP64): for the current iterate it evaluates
+//   * an upper bound of the relaxed optimum from two feasible primal points of the
+//     split problem (the primal objective is finite iff w = -h s lies on the probability
+//     simplex and u_i lies in [sum_{j>i} w_j, sum_{j>=i} w_j]; it then equals
+//     sum_i w_i rho_i^{**}(gamma_i + h_i alpha_i) + lambda sum_i h_i |grad u_i|):
+//       (a) w = simplex projection of -h s, u clamped into its ranges;
+//       (b) the graph lifting of the back-projected u (w = indicator of its interval);
+//   * a lower bound from the dual: with p projected onto K and v = div p, the best q is
+//     the pointwise max of the conjugates, D = -sum_x max_i [sum_{j<i} v_j - gamma_i v_i/h_i
+//     + rho_i^*(v_i/h_i)] (Prop. 1 with the conjugate in the form of its proof);
+//   * the nonconvex energy (eq. 1) of the back-projected u with the original data term.
+// Per-block partial sums are reduced in a fixed order: the result is bitwise reproducible.
+#include <math.h>
+
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace {
+
+constexpr int MB = 256;
+
+// ---------------------------------------------------------------- double-precision pieces
+
+struct PieceD {
+  int kind;  // 0 quad, 1 pl
+  double a, c, g0, g1, nu, hs;
+  int nv;      // PL vertex count
+  int ml, mr;  // straddle hull range
+  int mode;    // 0: explicit vertices from cost planes, 1: flat, 2: straddle samples
+  const float *cost, *tau;
+  long long ps, x;
+  int m0;
+  double bshift, cshift, wlo;  // additive term
+};
+
+__device__ double straddle_sample(const PieceD &P, int m) {
+  double t = P.g0 + P.hs * m;
+  double d = t - P.c;
+  double q = 0.5 * P.a * d * d;
+  return q < P.nu ? q : P.nu;
+}
+
+__device__ void vertex(const PieceD &P, int j, double &t, double &r) {
+  if (P.mode == 0) {
+    t = (double)P.tau[P.m0 + j];
+    r = (double)P.cost[(P.m0 + j) * P.ps + P.x];
+  } else if (P.mode == 1) {
+    t = j == 0 ? P.g0 : P.g1;
+    r = P.nu;
+  } else {
+    int m;
+    if (j == 0)
+      m = 0;
+    else if (j == P.nv - 1)
+      m = SLI_NSUB - 1;
+    else
+      m = P.ml + j - 1;
+    t = P.g0 + P.hs * m;
+    r = straddle_sample(P, m);
+  }
+}
+
+// rho_i^*(y) without the additive term
+__device__ double conj0(const PieceD &P, double y) {
+  if (P.kind == 0) {
+    double t = fmin(fmax(P.c + y / P.a, P.g0), P.g1);
+    return t * y - 0.5 * P.a * (t - P.c) * (t - P.c);
+  }
+  double g = -INFINITY;
+  for (int j = 0; j < P.nv; j++) {
+    double t, r;
+    vertex(P, j, t, r);
+    g = fmax(g, t * y - r);
+  }
+  return g;
+}
+
+// rho_i^{**}(t) on [g0, g1] without the additive term
+__device__ double val0(const PieceD &P, double t) {
+  if (P.kind == 0) return 0.5 * P.a * (t - P.c) * (t - P.c);
+  double tp, rp;
+  vertex(P, 0, tp, rp);
+  for (int j = 1; j < P.nv; j++) {
+    double tn, rn;
+    vertex(P, j, tn, rn);
+    if (t <= tn || j == P.nv - 1) {
+      double al = (t - tp) / (tn - tp);
+      return (1.0 - al) * rp + al * rn;
+    }
+    tp = tn;
+    rp = rn;
+  }
+  return rp;
+}
+
+__device__ double conj_full(const PieceD &P, double y) { return conj0(P, y - P.bshift) + P.cshift; }
+__device__ double val_full(const PieceD &P, double t) {
+  return val0(P, t) + P.wlo + P.bshift * (t - P.g0);
+}
+
+template <int PIECE, bool ADD>
+__device__ void make_piece(const IterArgs &A, const MonPtrs &M, long long x, int i, PieceD &P) {
+  P.g0 = A.gam[i];
+  P.g1 = A.gam[i + 1];
+  P.a = A.a;
+  P.nu = A.nu;
+  P.ps = A.ps;
+  P.x = x;
+  P.cost = M.cost;
+  P.tau = M.tau;
+  P.bshift = P.cshift = P.wlo = 0.0;
+  if (PIECE == SLI_SAMPLED) {
+    P.kind = 1;
+    P.mode = 0;
+    P.m0 = A.sidx[i];
+    P.nv = A.sidx[i + 1] - A.sidx[i] + 1;
+  } else {
+    const float fc = M.fn[x];
+    P.c = fc;
+    if (PIECE == SLI_QUAD) {
+      P.kind = 0;
+    } else {
+      // classification decided in float, as in the iteration
+      const float lo = fc - A.del, hb = fc + A.del;
+      const float g0 = A.gam[i], g1 = A.gam[i + 1];
+      if (lo <= g0 && g1 <= hb) {
+        P.kind = 0;
+      } else if (g1 <= lo || g0 >= hb) {
+        P.kind = 1;
+        P.mode = 1;
+        P.nv = 2;
+      } else {
+        P.kind = 1;
+        P.mode = 2;
+        P.hs = (P.g1 - P.g0) / (SLI_NSUB - 1);
+        // tangent points of the lower hull (see the FP32 version in device_math.hpp)
+        double r0 = straddle_sample(P, 0), rN = straddle_sample(P, SLI_NSUB - 1);
+        double best = INFINITY;
+        int ml = SLI_NSUB - 1;
+        for (int m = 1; m < SLI_NSUB; m++) {
+          double sl = (straddle_sample(P, m) - r0) / m;
+          if (sl <= best) {
+            best = sl;
+            ml = m;
+          }
+        }
+        best = -INFINITY;
+        int mr = 0;
+        for (int m = SLI_NSUB - 2; m >= 0; m--) {
+          double sl = (rN - straddle_sample(P, m)) / (SLI_NSUB - 1 - m);
+          if (sl >= best) {
+            best = sl;
+            mr = m;
+          }
+        }
+        P.ml = ml;
+        P.mr = mr;
+        P.nv = 2 + (ml <= mr ? mr - ml + 1 : 0);
+      }
+    }
+  }
+  if (ADD) {
+    double wl = M.wadd[i * A.ps + x], wh = M.wadd[(i + 1) * A.ps + x];
+    P.bshift = (wh - wl) / (P.g1 - P.g0);
+    P.cshift = -wl + P.bshift * P.g0;
+    P.wlo = wl;
+  }
+}
+
+template <typename DT>
+__device__ void proj_p(const IterArgs &A, const DT *p, int i, long long x, double rad, double &px,
+                       double &py) {
+  px = ldv(p, i * A.ps + x);
+  py = ldv(p, (A.k + i) * A.ps + x);
+  double n = sqrt(px * px + py * py);
+  if (n > rad) {
+    px *= rad / n;
+    py *= rad / n;
+  }
+}
+
+__device__ void block_sum(double *vals, int nv, double *out_row) {
+  __shared__ double red[SLI_NMON][MB];
+  for (int q = 0; q < nv; q++) red[q][threadIdx.x] = vals[q];
+  __syncthreads();
+  for (int s = MB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int q = 0; q < nv; q++) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < nv; q++) out_row[q] = red[q][0];
+}
+
+// per-pixel terms: data parts of both primal bounds, dual, nonconvex data term
+template <int PIECE, bool ADD, typename DT>
+__global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
+  const long long N = (long long)A.H * A.W;
+  const long long x = (long long)blockIdx.x * MB + threadIdx.x;
+  double vals[4] = {0, 0, 0, 0};
+  const DT *v_ = (const DT *)M.v;
+  (void)v_;
+  if (x < N) {
+    const int k = A.k;
+    const int r = (int)(x / A.W), cc = (int)(x % A.W);
+    PieceD P;
+    // (a) repair: simplex projection of -h s by Michelot's finite algorithm
+    double xs[SLI_MAXK], w[SLI_MAXK];
+    for (int i = 0; i < k; i++) xs[i] = -(double)A.h[i] * M.s[i * A.ps + x];
+    double theta = 0.0;
+    {
+      bool act[SLI_MAXK];
+      for (int i = 0; i < k; i++) act[i] = true;
+      for (int it = 0; it <= k; it++) {
+        double sum = 0.0;
+        int n = 0;
+        for (int i = 0; i < k; i++)
+          if (act[i]) {
+            sum += xs[i];
+            n++;
+          }
+        theta = (sum - 1.0) / n;
+        bool changed = false;
+        for (int i = 0; i < k; i++)
+          if (act[i] && xs[i] <= theta) {
+            act[i] = false;
+            changed = true;
+          }
+        if (!changed) break;
+      }
+    }
+    for (int i = 0; i < k; i++) w[i] = xs[i] > theta ? xs[i] - theta : 0.0;
+    double lo = 0.0, dat = 0.0;
+    for (int i = k - 1; i >= 0; i--) {
+      double al = 0.0;
+      if (w[i] > 0.0) al = fmin(fmax((M.u[i * A.ps + x] - lo) / w[i], 0.0), 1.0);
+      M.mon_u[i * A.ps + x] = (float)(lo + w[i] * al);
+      if (w[i] > 0.0) {
+        make_piece<PIECE, ADD>(A, M, x, i, P);
+        dat += w[i] * val_full(P, (double)A.gam[i] + (double)A.h[i] * al);
+      }
+      lo += w[i];
+    }
+    vals[0] = dat;
+    // (b) graph lifting of the back-projected u
+    double t = A.gam[0];
+    for (int i = 0; i < k; i++) t += (double)A.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
+    ((double *)M.mon_b)[x] = t;
+    int is = 0;
+    while (is < k - 1 && t > (double)A.gam[is + 1]) is++;
+    double al = fmin(fmax((t - A.gam[is]) / (double)A.h[is], 0.0), 1.0);
+    make_piece<PIECE, ADD>(A, M, x, is, P);
+    vals[1] = val_full(P, (double)A.gam[is] + (double)A.h[is] * al);
+    // dual bound
+    const DT *p = (const DT *)M.p;
+    double mx = -INFINITY, pre = 0.0;
+    for (int i = 0; i < k; i++) {
+      double rad = (double)A.lam * A.h[i];
+      double px, py, qx, qy;
+      proj_p(A, p, i, x, rad, px, py);
+      double vh = 0.0;
+      if (cc < A.W - 1) vh += px;
+      if (r < A.H - 1) vh += py;
+      if (cc > 0) {
+        proj_p(A, p, i, x - 1, rad, qx, qy);
+        vh -= qx;
+      }
+      if (r > 0) {
+        proj_p(A, p, i, x - A.W, rad, qx, qy);
+        vh -= qy;
+      }
+      make_piece<PIECE, ADD>(A, M, x, i, P);
+      double y = vh / A.h[i];
+      double val = pre - (double)A.gam[i] * y + conj_full(P, y);
+      mx = fmax(mx, val);
+      pre += vh;
+    }
+    vals[2] = -mx;
+    // nonconvex data term at the back-projected value
+    double e;
+    if (PIECE == SLI_SAMPLED) {
+      int m = 0;
+      while (m < A.M - 2 && t > (double)M.tau[m + 1]) m++;
+      double a2 = (t - M.tau[m]) / ((double)M.tau[m + 1] - M.tau[m]);
+      const float *raw = M.cost + (long long)A.M * A.ps;
+      e = (1.0 - a2) * raw[m * A.ps + x] + a2 * raw[(m + 1) * A.ps + x];
+    } else {
+      double d = t - (double)M.fn[x];
+      e = 0.5 * (double)A.a * d * d;
+      if (PIECE == SLI_TRUNC && e > A.nu) e = A.nu;
+    }
+    if (ADD) {
+      double a3 = (t - A.gam[is]) / (double)A.h[is];
+      e += (1.0 - a3) * M.wadd[is * A.ps + x] + a3 * M.wadd[(is + 1) * A.ps + x];
+    }
+    vals[3] = e;
+  }
+  block_sum(vals, 4, M.part1 + (long long)blockIdx.x * SLI_NMON);
+}
+
+// TV terms of both primal points and of the back-projected u
+__global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonPtrs M) {
+  const long long N = (long long)A.H * A.W;
+  const long long x = (long long)blockIdx.x * MB + threadIdx.x;
+  double vals[3] = {0, 0, 0};
+  if (x < N) {
+    const int r = (int)(x / A.W), cc = (int)(x % A.W);
+    const bool hx = cc < A.W - 1, hy = r < A.H - 1;
+    const double *b = (const double *)M.mon_b;
+    double tr = 0.0, tg = 0.0;
+    for (int i = 0; i < A.k; i++) {
+      double u0 = M.mon_u[i * A.ps + x];
+      double gx = hx ? M.mon_u[i * A.ps + x + 1] - u0 : 0.0;
+      double gy = hy ? M.mon_u[i * A.ps + x + A.W] - u0 : 0.0;
+      tr += (double)A.h[i] * sqrt(gx * gx + gy * gy);
+      double g0 = A.gam[i], ih = 1.0 / (double)A.h[i];
+      double l0 = fmin(fmax((b[x] - g0) * ih, 0.0), 1.0);
+      double lx = hx ? fmin(fmax((b[x + 1] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
+      double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
+      tg += (double)A.h[i] * sqrt(lx * lx + ly * ly);
+    }
+    double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
+    vals[0] = tr;
+    vals[1] = tg;
+    vals[2] = sqrt(bx * bx + by * by);
+  }
+  block_sum(vals, 3, M.part2 + (long long)blockIdx.x * SLI_NMON);
+}
+
+// fixed-order reduction of per-block partials: block q reduces column q
+__global__ __launch_bounds__(MB) void monitor_final(const double *part1, const double *part2,
+                                                   int nb, double *out) {
+  __shared__ double red[MB];
+  const int q = blockIdx.x;
+  const double *src = q < 4 ? part1 : part2;
+  const int col = q < 4 ? q : q - 4;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += MB) acc += src[(long long)b * SLI_NMON + col];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = MB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = red[0];
+}
+
+template <int PIECE, bool ADD>
+hipError_t launch_mon_t(const IterArgs &A, const MonPtrs &M, hipStream_t st, int nb) {
+  if (M.bf16)
+    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, uint16_t>), dim3(nb), dim3(MB), 0, st, A, M);
+  else
+    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, float>), dim3(nb), dim3(MB), 0, st, A, M);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- set-up / read-out
+
+__global__ void k_fill_zero(uint4 *dst, size_t n16) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_init_fn(const float *f, float *fn, long long N, float shift, float iscale) {
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < N) {
+    float t = __fsub_rn(f[x], shift);
+    fn[x] = __fmul_rn(t, iscale);
+  }
+}
+
+__global__ void k_copy_planes(const float *src, float *dst, int np, long long N, long long ps) {
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < N)
+    for (int i = 0; i < np; i++) dst[i * ps + x] = src[i * N + x];
+}
+
+// Convex envelope of the samples on every label interval: in one dimension the envelope
+// at a sample position is the least value of a chord between two samples that bracket it.
+__global__ void k_convexify(const float *samples, float *cost, const float *tau, IterArgs A) {
+  const long long N = (long long)A.H * A.W;
+  long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N * A.k) return;
+  const int i = (int)(g / N);
+  const long long x = g % N;
+  const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
+  const int mend = (i == A.k - 1) ? m1 : m1 - 1;
+  for (int m = m0; m <= mend; m++) {
+    const double tm = tau[m];
+    double env = samples[m * N + x];
+    for (int a = m0; a <= m; a++) {
+      const double ta = tau[a], ra = samples[a * N + x];
+      for (int b = (a == m ? m + 1 : m); b <= m1; b++) {
+        if (b == a) continue;
+        const double tb = tau[b], rb = samples[b * N + x];
+        const double lam = (tm - ta) / (tb - ta);
+        const double ch = (1.0 - lam) * ra + lam * rb;
+        if (ch < env) env = ch;
+      }
+    }
+    cost[m * A.ps + x] = (float)env;
+  }
+}
+
+__global__ void k_readout(const float *u, float *ulift, float *uout, IterArgs A, double shift,
+                          double scale) {
+  const long long N = (long long)A.H * A.W;
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  double t = A.gam[0];
+  for (int i = 0; i < A.k; i++) {
+    float ui = u[i * A.ps + x];
+    if (ulift) ulift[i * N + x] = ui;
+    t += (double)A.h[i] * fmin(fmax((double)ui, 0.0), 1.0);
+  }
+  if (uout) uout[x] = (float)(shift + scale * t);
+}
+
+struct PackArgs {
+  const void *planes[8 * SLI_MAXK + 1];
+  int bf16[8 * SLI_MAXK + 1];
+};
+
+__global__ void k_pack(PackArgs P, int np, long long N, long long ps, float *dst, int unpack) {
+  long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  for (int q = 0; q < np; q++) {
+    if (!unpack) {
+      dst[q * N + x] = P.bf16[q] ? ldv((const uint16_t *)P.planes[q], x)
+                                 : ((const float *)P.planes[q])[x];
+    } else {
+      float val = dst[q * N + x];
+      if (P.bf16[q])
+        stv((uint16_t *)P.planes[q], x, val);
+      else
+        ((float *)P.planes[q])[x] = val;
+    }
+  }
+}
+
+inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, MB); }
+
+hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonPtrs &M,
+                          hipStream_t st, int *nb_out) {
+  const int nb = monitor_blocks(A);
+  hipError_t e;
+  if (piece == SLI_QUAD)
+    e = add ? launch_mon_t<SLI_QUAD, true>(A, M, st, nb) : launch_mon_t<SLI_QUAD, false>(A, M, st, nb);
+  else if (piece == SLI_TRUNC)
+    e = add ? launch_mon_t<SLI_TRUNC, true>(A, M, st, nb) : launch_mon_t<SLI_TRUNC, false>(A, M, st, nb);
+  else
+    e = launch_mon_t<SLI_SAMPLED, false>(A, M, st, nb);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(monitor_tv, dim3(nb), dim3(MB), 0, st, A, M);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(monitor_final, dim3(7), dim3(MB), 0, st, M.part1, M.part2, nb, M.final_);
+  if (nb_out) *nb_out = nb;
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st) {
+  size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  unsigned nb = (unsigned)((n16 + 255) / 256);
+  if (nb > 65536u) nb = 65536u;
+  hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(256), 0, st, (uint4 *)dst, n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_fn(const float *f, float *fn, long long N, float shift, float iscale,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_init_fn, dim3(nblk(N, 256)), dim3(256), 0, st, f, fn, N, shift, iscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_planes(const float *src, float *dst, int np, long long N, long long ps,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_planes, dim3(nblk(N, 256)), dim3(256), 0, st, src, dst, np, N, ps);
+  return hipGetLastError();
+}
+
+hipError_t launch_convexify(const float *samples, float *cost, const float *tau,
+                            const IterArgs &A, hipStream_t st) {
+  long long n = (long long)A.H * A.W * A.k;
+  hipLaunchKernelGGL(k_convexify, dim3(nblk(n, 256)), dim3(256), 0, st, samples, cost, tau, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
+                          double shift, double scale, hipStream_t st) {
+  long long N = (long long)A.H * A.W;
+  hipLaunchKernelGGL(k_readout, dim3(nblk(N, 256)), dim3(256), 0, st, u, ulift, uout, A, shift,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(const void *const *planes, const int *bf16, int np, long long N,
+                             long long ps, float *dst, int unpack, hipStream_t st) {
+  (void)ps;
+  PackArgs P;
+  for (int q = 0; q < np; q++) {
+    P.planes[q] = planes[q];
+    P.bf16[q] = bf16[q];
+  }
+  hipLaunchKernelGGL(k_pack, dim3(nblk(N, 256)), dim3(256), 0, st, P, np, N, ps, dst, unpack);
+  return hipGetLastError();
+}

@@ -1,0 +1,573 @@
+// capi.hip -- host side of the C-ABI declared in include/sublabel.h: argument checks,
+// label normalisation and step sizes, workspace carving, buffer rotation, the monitor's
+// bookkeeping and the state save / load.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/sublabel.h"
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+sl_status fail(sl_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+sl_status fail(sl_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+sl_status hip_fail(hipError_t e, const char *what) {
+  return fail(SL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call, what)                   \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  long long N, ps;
+  size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_w, off_cost, off_tau;
+  size_t off_monu, off_monb, off_part1, off_part2, off_fin, off_flag, total;
+  size_t state_lo, state_hi;  // contiguous range holding u, s, v, z, p, qd
+};
+
+Layout make_layout(const sl_problem_desc *d, int nb_mon) {
+  Layout L{};
+  const int k = d->L - 1;
+  L.N = (long long)d->H * d->W;
+  L.ps = (L.N + 63) / 64 * 64;
+  const size_t pf = (size_t)L.ps * 4;
+  const size_t pd = (size_t)L.ps * (d->storage == SL_STORE_BF16_DUAL ? 2 : 4);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.state_lo = o;
+  L.off_u = take(3 * k * pf);
+  L.off_s = take(2 * k * pf);
+  L.off_v = take(k * pd);
+  L.off_z = take(k * pd);
+  L.off_p = take(2 * 2 * k * pd);
+  L.off_qd = take(pf);
+  L.state_hi = o;
+  const bool sampled = d->rho == SL_RHO_SAMPLED;
+  L.off_fn = take(sampled ? 0 : pf);
+  L.off_w = take((!sampled && d->samples) ? (size_t)d->L * pf : 0);
+  L.off_cost = take(sampled ? (size_t)2 * d->M * pf : 0);
+  L.off_tau = take(sampled ? (size_t)d->M * 4 : 0);
+  L.off_monu = take(k * pf);
+  L.off_monb = take((size_t)L.ps * 8);
+  L.off_part1 = take((size_t)nb_mon * SLI_NMON * 8);
+  L.off_part2 = take((size_t)nb_mon * SLI_NMON * 8);
+  L.off_fin = take(SLI_NMON * 8);
+  L.off_flag = take(16);
+  L.total = o;
+  return L;
+}
+
+sl_status validate(const sl_problem_desc *d) {
+  if (!d) return fail(SL_ERR_INVALID_ARG, "desc is NULL");
+  if (d->H < 1 || d->W < 1) return fail(SL_ERR_INVALID_ARG, "H and W must be >= 1");
+  if ((long long)d->H * d->W >= (1LL << 31)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^31");
+  if (d->L < 2) return fail(SL_ERR_INVALID_ARG, "L must be >= 2");
+  if (d->L > SL_MAX_LABELS) return fail(SL_ERR_UNSUPPORTED, "L must be <= %d", SL_MAX_LABELS);
+  if (!d->gamma) return fail(SL_ERR_INVALID_ARG, "gamma is NULL");
+  for (int j = 0; j < d->L; j++) {
+    if (!isfinite(d->gamma[j])) return fail(SL_ERR_INVALID_ARG, "gamma[%d] is not finite", j);
+    if (j > 0 && !(d->gamma[j] > d->gamma[j - 1]))
+      return fail(SL_ERR_INVALID_ARG, "gamma must be strictly increasing (index %d)", j);
+  }
+  if (!(d->lambda >= 0.0) || !isfinite(d->lambda))
+    return fail(SL_ERR_INVALID_ARG, "lambda must be finite and >= 0");
+  if (d->rho != SL_RHO_QUAD && d->rho != SL_RHO_TRUNC_QUAD && d->rho != SL_RHO_SAMPLED)
+    return fail(SL_ERR_INVALID_ARG, "unknown data-term kind %d", (int)d->rho);
+  if (d->tv == SL_TV_ANISO) return fail(SL_ERR_UNSUPPORTED, "anisotropic TV is not built");
+  if (d->tv != SL_TV_ISO) return fail(SL_ERR_INVALID_ARG, "unknown TV kind");
+  if (d->storage != SL_STORE_FP32 && d->storage != SL_STORE_BF16_DUAL)
+    return fail(SL_ERR_INVALID_ARG, "unknown storage kind");
+  if (d->check_every < 0) return fail(SL_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (d->normalize_labels != 0 && d->normalize_labels != 1)
+    return fail(SL_ERR_INVALID_ARG, "normalize_labels must be 0 or 1");
+  if (d->adaptive_steps != 0) return fail(SL_ERR_UNSUPPORTED, "adaptive steps are not built");
+  if (d->rho != SL_RHO_SAMPLED) {
+    if (!d->f) return fail(SL_ERR_INVALID_ARG, "f is NULL");
+    if (!(d->a > 0.0) || !isfinite(d->a)) return fail(SL_ERR_INVALID_ARG, "a must be > 0");
+    if (d->rho == SL_RHO_TRUNC_QUAD && (!(d->nu > 0.0) || !isfinite(d->nu)))
+      return fail(SL_ERR_INVALID_ARG, "nu must be > 0");
+    if (d->samples) {
+      if (d->M != d->L || !d->tau)
+        return fail(SL_ERR_INVALID_ARG, "additive values need M == L and tau == gamma");
+      for (int j = 0; j < d->L; j++)
+        if (d->tau[j] != d->gamma[j])
+          return fail(SL_ERR_INVALID_ARG, "additive values need tau == gamma");
+    }
+  } else {
+    if (!d->samples || !d->tau) return fail(SL_ERR_INVALID_ARG, "samples / tau are NULL");
+    if (d->M < 2) return fail(SL_ERR_INVALID_ARG, "M must be >= 2");
+    if (d->M > SL_MAX_SAMPLES) return fail(SL_ERR_UNSUPPORTED, "M must be <= %d", SL_MAX_SAMPLES);
+    for (int m = 0; m < d->M; m++) {
+      if (!isfinite(d->tau[m])) return fail(SL_ERR_INVALID_ARG, "tau[%d] is not finite", m);
+      if (m > 0 && !(d->tau[m] > d->tau[m - 1]))
+        return fail(SL_ERR_INVALID_ARG, "tau must be strictly increasing");
+    }
+    for (int j = 0; j < d->L; j++) {
+      bool found = false;
+      for (int m = 0; m < d->M; m++) found |= d->tau[m] == d->gamma[j];
+      if (!found) return fail(SL_ERR_INVALID_ARG, "label %d is not a sample position", j);
+    }
+  }
+  return SL_OK;
+}
+
+// count of non-finite values in a device array
+__global__ void k_nonfinite(const float *a, long long n, unsigned *flag) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned bad = 0;
+  for (; i < n; i += stride) bad |= !isfinite(a[i]);
+  if (bad) atomicOr(flag, 1u);
+}
+
+}  // namespace
+
+struct sl_problem_ {
+  sl_problem_desc d;
+  int piece = 0;
+  bool add = false, bf16 = false;
+  int rpt = 1;
+  IterArgs A{};
+  double shift = 0, scale = 1, lam = 0;
+  hipStream_t st = nullptr;
+  Layout lay{};
+  char *ws = nullptr;
+  int iu = 0, is = 0, ip = 0;
+  int64_t iters = 0;
+  double best_P = 0, best_D = 0;
+  bool have_best = false;
+  int check_every = 50;
+  int nb_mon = 0;
+  std::vector<float> tau_host;
+  double fin[SLI_NMON];
+
+  float *ubuf(int j) { return (float *)(ws + lay.off_u) + (size_t)j * A.k * lay.ps; }
+  float *sbuf(int j) { return (float *)(ws + lay.off_s) + (size_t)j * A.k * lay.ps; }
+  size_t esz() const { return bf16 ? 2 : 4; }
+  char *pbuf(int j) { return ws + lay.off_p + (size_t)j * 2 * A.k * lay.ps * esz(); }
+};
+
+namespace {
+
+void fill_args(sl_problem_ *P) {
+  const sl_problem_desc *d = &P->d;
+  IterArgs &A = P->A;
+  const int L = d->L, k = L - 1;
+  P->shift = d->normalize_labels ? d->gamma[0] : 0.0;
+  P->scale = d->normalize_labels ? d->gamma[L - 1] - d->gamma[0] : 1.0;
+  std::vector<double> g(L), h(k);
+  for (int j = 0; j < L; j++) g[j] = (d->gamma[j] - P->shift) / P->scale;
+  for (int i = 0; i < k; i++) h[i] = g[i + 1] - g[i];
+  A.H = d->H;
+  A.W = d->W;
+  A.k = k;
+  A.M = d->rho == SL_RHO_SAMPLED ? d->M : 0;
+  A.ps = P->lay.ps;
+  P->lam = d->lambda * P->scale;
+  A.lam = (float)P->lam;
+  // diagonal preconditioning: inverse absolute row / column sums of the operator
+  A.sig_p = 0.5f;
+  A.sig_q = (float)(1.0 / (g[k] - g[0]));
+  for (int j = 0; j < L; j++) A.gam[j] = (float)g[j];
+  for (int i = 0; i < k; i++) {
+    A.h[i] = (float)h[i];
+    A.ih[i] = (float)(1.0 / h[i]);
+    A.sig[i] = (float)(1.0 / (1.0 + fabs(g[i]) + (g[k] - g[i + 1])));
+    A.taus[i] = (float)(1.0 / (1.0 + fabs(g[i]) + (i + 1) * h[i]));
+    A.ig0[i] = (float)(1.0 / (1.0 + g[i] * g[i]));
+    A.ig1[i] = (float)(1.0 / (1.0 + g[i + 1] * g[i + 1]));
+  }
+  if (d->rho != SL_RHO_SAMPLED) {
+    const double an = d->a * P->scale * P->scale;
+    A.a = (float)an;
+    A.ia = (float)(1.0 / an);
+    A.nu = (float)d->nu;
+    A.del = d->rho == SL_RHO_TRUNC_QUAD ? (float)sqrt(2.0 * d->nu / an) : 0.f;
+  } else {
+    P->tau_host.resize(d->M);
+    for (int m = 0; m < d->M; m++) P->tau_host[m] = (float)((d->tau[m] - P->shift) / P->scale);
+    for (int j = 0; j < L; j++)
+      for (int m = 0; m < d->M; m++)
+        if (d->tau[m] == d->gamma[j]) A.sidx[j] = m;
+  }
+}
+
+IterPtrs<float> iter_ptrs_f(sl_problem_ *P) {
+  IterPtrs<float> Q;
+  Q.u = P->ubuf(P->iu);
+  Q.up = P->ubuf((P->iu + 2) % 3);
+  Q.un = P->ubuf((P->iu + 1) % 3);
+  Q.s = P->sbuf(P->is);
+  Q.sp = P->sbuf(1 - P->is);
+  Q.v = (float *)(P->ws + P->lay.off_v);
+  Q.z = (float *)(P->ws + P->lay.off_z);
+  Q.pin = (float *)P->pbuf(P->ip);
+  Q.pout = (float *)P->pbuf(1 - P->ip);
+  Q.qd = (float *)(P->ws + P->lay.off_qd);
+  Q.fn = (const float *)(P->ws + P->lay.off_fn);
+  Q.wadd = (const float *)(P->ws + P->lay.off_w);
+  Q.cost = (const float *)(P->ws + P->lay.off_cost);
+  Q.tau = (const float *)(P->ws + P->lay.off_tau);
+  return Q;
+}
+
+sl_status enqueue_iters(sl_problem_ *P, int iters) {
+  for (int n = 0; n < iters; n++) {
+    IterPtrs<float> Q = iter_ptrs_f(P);
+    hipError_t e;
+    if (P->bf16) {
+      IterPtrs<uint16_t> B;
+      B.u = Q.u;
+      B.up = Q.up;
+      B.un = Q.un;
+      B.s = Q.s;
+      B.sp = Q.sp;
+      B.v = (uint16_t *)Q.v;
+      B.z = (uint16_t *)Q.z;
+      B.pin = (const uint16_t *)Q.pin;
+      B.pout = (uint16_t *)Q.pout;
+      B.qd = Q.qd;
+      B.fn = Q.fn;
+      B.wadd = Q.wadd;
+      B.cost = Q.cost;
+      B.tau = Q.tau;
+      e = launch_pdhg_iter(P->piece, P->add, true, P->rpt, P->A, &B, P->st);
+    } else {
+      e = launch_pdhg_iter(P->piece, P->add, false, P->rpt, P->A, &Q, P->st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "iteration launch");
+    P->iu = (P->iu + 1) % 3;
+    P->is = 1 - P->is;
+    P->ip = 1 - P->ip;
+    P->iters++;
+  }
+  return SL_OK;
+}
+
+sl_status monitor(sl_problem_ *P, sl_report *out) {
+  MonPtrs M;
+  M.u = P->ubuf(P->iu);
+  M.s = P->sbuf(P->is);
+  M.v = P->ws + P->lay.off_v;
+  M.z = P->ws + P->lay.off_z;
+  M.p = P->pbuf(P->ip);
+  M.qd = (const float *)(P->ws + P->lay.off_qd);
+  M.fn = (const float *)(P->ws + P->lay.off_fn);
+  M.wadd = (const float *)(P->ws + P->lay.off_w);
+  M.cost = (const float *)(P->ws + P->lay.off_cost);
+  M.tau = (const float *)(P->ws + P->lay.off_tau);
+  M.f_orig = nullptr;
+  M.mon_u = (float *)(P->ws + P->lay.off_monu);
+  M.mon_b = (float *)(P->ws + P->lay.off_monb);
+  M.part1 = (double *)(P->ws + P->lay.off_part1);
+  M.part2 = (double *)(P->ws + P->lay.off_part2);
+  M.final_ = (double *)(P->ws + P->lay.off_fin);
+  M.bf16 = P->bf16;
+  HIPCHK(launch_monitor(P->piece, P->add, P->A, M, P->st, nullptr), "monitor launch");
+  HIPCHK(hipMemcpyAsync(P->fin, M.final_, 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
+         "monitor copy");
+  HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
+  const double lam = P->lam;
+  const double pr = P->fin[0] + lam * P->fin[4];
+  const double pg = P->fin[1] + lam * P->fin[5];
+  const double primal = std::min(pr, pg);
+  const double dual = P->fin[2];
+  const double enc = P->fin[3] + lam * P->fin[6];
+  if (!isfinite(primal) || !isfinite(dual) || !isfinite(enc))
+    return fail(SL_ERR_NUMERIC, "non-finite energy (primal %g, dual %g)", primal, dual);
+  if (!P->have_best || primal < P->best_P) P->best_P = primal;
+  if (!P->have_best || dual > P->best_D) P->best_D = dual;
+  P->have_best = true;
+  if (out) {
+    out->primal_ub = primal;
+    out->dual_lb = dual;
+    out->gap = primal - dual;
+    out->best_primal = P->best_P;
+    out->best_dual = P->best_D;
+    out->best_gap = P->best_P - P->best_D;
+    double den = std::max(std::max(fabs(P->best_P), fabs(P->best_D)), 1e-30);
+    out->rel_gap = out->best_gap / den;
+    out->e_nonconvex = enc;
+    out->iters = P->iters;
+  }
+  return SL_OK;
+}
+
+void state_planes(sl_problem_ *P, std::vector<const void *> &pl, std::vector<int> &bf) {
+  const int k = P->A.k;
+  const long long ps = P->lay.ps;
+  const size_t e = P->esz();
+  auto addf = [&](float *base) {
+    for (int i = 0; i < k; i++) {
+      pl.push_back(base + (size_t)i * ps);
+      bf.push_back(0);
+    }
+  };
+  auto addd = [&](char *base, int off) {
+    for (int i = 0; i < k; i++) {
+      pl.push_back(base + ((size_t)(off + i) * ps) * e);
+      bf.push_back(P->bf16 ? 1 : 0);
+    }
+  };
+  addf(P->ubuf(P->iu));
+  addf(P->ubuf((P->iu + 2) % 3));
+  addf(P->sbuf(P->is));
+  addf(P->sbuf(1 - P->is));
+  addd(P->ws + P->lay.off_v, 0);
+  addd(P->ws + P->lay.off_z, 0);
+  addd(P->pbuf(P->ip), 0);
+  addd(P->pbuf(P->ip), k);
+  pl.push_back(P->ws + P->lay.off_qd);
+  bf.push_back(0);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sl_status_string(sl_status s) {
+  switch (s) {
+    case SL_OK: return "ok";
+    case SL_ERR_INVALID_ARG: return "invalid argument";
+    case SL_ERR_UNSUPPORTED: return "unsupported";
+    case SL_ERR_DEVICE: return "device error";
+    case SL_ERR_WORKSPACE: return "workspace error";
+    case SL_ERR_NUMERIC: return "numeric error";
+  }
+  return "unknown status";
+}
+
+const char *sl_last_error(void) { return g_err.c_str(); }
+
+sl_status sl_workspace_size(const sl_problem_desc *desc, size_t *bytes) {
+  if (!bytes) return fail(SL_ERR_INVALID_ARG, "bytes is NULL");
+  sl_status s = validate(desc);
+  if (s != SL_OK) return s;
+  IterArgs A{};
+  A.H = desc->H;
+  A.W = desc->W;
+  *bytes = make_layout(desc, monitor_blocks(A)).total;
+  return SL_OK;
+}
+
+sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
+                    sl_problem *out) {
+  if (!out) return fail(SL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  sl_status s = validate(desc);
+  if (s != SL_OK) return s;
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  IterArgs A0{};
+  A0.H = desc->H;
+  A0.W = desc->W;
+  const int nb_mon = monitor_blocks(A0);
+  Layout lay = make_layout(desc, nb_mon);
+  if (bytes < lay.total)
+    return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, lay.total);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "no HIP device");
+  int maxlds = 0;
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
+
+  sl_problem_ *P = new sl_problem_();
+  P->d = *desc;
+  P->d.gamma = nullptr;
+  P->d.f = nullptr;
+  P->d.tau = nullptr;
+  P->d.samples = nullptr;
+  P->lay = lay;
+  P->ws = (char *)ws;
+  P->st = (hipStream_t)stream;
+  P->nb_mon = nb_mon;
+  P->bf16 = desc->storage == SL_STORE_BF16_DUAL;
+  P->piece = desc->rho == SL_RHO_QUAD ? SLI_QUAD : desc->rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : SLI_SAMPLED;
+  P->add = desc->rho != SL_RHO_SAMPLED && desc->samples != nullptr;
+  P->check_every = desc->check_every > 0 ? desc->check_every : 50;
+  {
+    // keep pointers for fill_args
+    sl_problem_desc dd = *desc;
+    sl_problem_desc keep = P->d;
+    P->d = dd;
+    fill_args(P);
+    P->d = keep;
+  }
+  const int k = P->A.k;
+  P->rpt = 1;
+  const size_t static_lds = 8 * 1024;
+  if (pdhg_iter_lds_bytes(k, P->rpt) + static_lds > (size_t)maxlds) {
+    delete P;
+    return fail(SL_ERR_UNSUPPORTED, "L = %d needs more LDS than a workgroup may use", desc->L);
+  }
+  const long long N = lay.N;
+  auto cleanup = [&](sl_status st) {
+    delete P;
+    return st;
+  };
+  // non-finite inputs are argument errors (checked before the state is touched)
+  unsigned *flag = (unsigned *)(P->ws + lay.off_flag);
+  unsigned hflag = 0;
+  if ((e = launch_fill_zero(P->ws + lay.off_flag, 16, P->st)) != hipSuccess) return cleanup(hip_fail(e, "fill"));
+  if (desc->f) hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, P->st, desc->f, N, flag);
+  if (desc->samples)
+    hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, P->st, desc->samples,
+                       (long long)desc->M * N, flag);
+  if ((e = hipGetLastError()) != hipSuccess) return cleanup(hip_fail(e, "input check"));
+  if ((e = hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, P->st)) != hipSuccess)
+    return cleanup(hip_fail(e, "input check copy"));
+  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return cleanup(hip_fail(e, "input check sync"));
+  if (hflag) return cleanup(fail(SL_ERR_INVALID_ARG, "f or samples contain NaN or Inf"));
+
+  // zero state, data planes
+  if ((e = launch_fill_zero(P->ws + lay.state_lo, lay.state_hi - lay.state_lo, P->st)) != hipSuccess)
+    return cleanup(hip_fail(e, "zero state"));
+  if (P->piece != SLI_SAMPLED) {
+    float fs = (float)P->shift, is = (float)(1.0 / P->scale);
+    if ((e = launch_init_fn(desc->f, (float *)(P->ws + lay.off_fn), N, fs, is, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "init f"));
+    if (P->add &&
+        (e = launch_copy_planes(desc->samples, (float *)(P->ws + lay.off_w), desc->L, N, lay.ps, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy w"));
+  } else {
+    float *tau_d = (float *)(P->ws + lay.off_tau);
+    if ((e = hipMemcpyAsync(tau_d, P->tau_host.data(), 4 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy tau"));
+    float *cost = (float *)(P->ws + lay.off_cost);
+    if ((e = launch_convexify(desc->samples, cost, tau_d, P->A, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "convexify"));
+    if ((e = launch_copy_planes(desc->samples, cost + (size_t)desc->M * lay.ps, desc->M, N, lay.ps, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy raw samples"));
+  }
+  // inputs are no longer read once this returns
+  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return cleanup(hip_fail(e, "setup sync"));
+  *out = P;
+  return SL_OK;
+}
+
+sl_status sl_run(sl_problem P, int32_t iters) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (iters < 0) return fail(SL_ERR_INVALID_ARG, "iters must be >= 0");
+  return enqueue_iters(P, iters);
+}
+
+sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t *done) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (max_iters < 0 || !(rel_gap >= 0.0)) return fail(SL_ERR_INVALID_ARG, "bad rel_gap / max_iters");
+  int32_t n = 0;
+  sl_report r;
+  while (n < max_iters) {
+    int chunk = std::min(P->check_every, max_iters - n);
+    sl_status s = enqueue_iters(P, chunk);
+    if (s != SL_OK) return s;
+    n += chunk;
+    if ((s = monitor(P, &r)) != SL_OK) {
+      if (done) *done = n;
+      return s;
+    }
+    if (r.rel_gap <= rel_gap) break;
+  }
+  if (done) *done = n;
+  return SL_OK;
+}
+
+sl_status sl_read_u(sl_problem P, float *ulift, float *u) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (!ulift && !u) return SL_OK;
+  HIPCHK(launch_readout(P->ubuf(P->iu), ulift, u, P->A, P->shift, P->scale, P->st), "readout");
+  return SL_OK;
+}
+
+sl_status sl_energy(sl_problem P, sl_report *out) {
+  if (!P || !out) return fail(SL_ERR_INVALID_ARG, "handle or out is NULL");
+  return monitor(P, out);
+}
+
+sl_status sl_state_size(sl_problem P, size_t *bytes) {
+  if (!P || !bytes) return fail(SL_ERR_INVALID_ARG, "handle or bytes is NULL");
+  *bytes = (size_t)(8 * P->A.k + 1) * P->lay.N * 4;
+  return SL_OK;
+}
+
+static sl_status pack(sl_problem P, void *buf, size_t bytes, int unpack) {
+  if (!P || !buf) return fail(SL_ERR_INVALID_ARG, "handle or buffer is NULL");
+  size_t need = (size_t)(8 * P->A.k + 1) * P->lay.N * 4;
+  if (bytes < need) return fail(SL_ERR_INVALID_ARG, "state buffer of %zu bytes < %zu", bytes, need);
+  std::vector<const void *> pl;
+  std::vector<int> bf;
+  state_planes(P, pl, bf);
+  HIPCHK(launch_pack_state(pl.data(), bf.data(), (int)pl.size(), P->lay.N, P->lay.ps, (float *)buf,
+                           unpack, P->st),
+         "state pack");
+  return SL_OK;
+}
+
+sl_status sl_save_state(sl_problem P, void *dst, size_t bytes) { return pack(P, dst, bytes, 0); }
+
+sl_status sl_load_state(sl_problem P, const void *src, size_t bytes) {
+  sl_status s = pack(P, const_cast<void *>(src), bytes, 1);
+  if (s == SL_OK) {
+    P->iters = 0;
+    P->have_best = false;
+  }
+  return s;
+}
+
+sl_status sl_batch_create(const sl_problem_desc *, int32_t, void *, size_t, void *, sl_problem *out) {
+  if (out) *out = nullptr;
+  return fail(SL_ERR_UNSUPPORTED, "batched solve is not built");
+}
+
+sl_status sl_unrolled_forward(sl_problem, int32_t, int32_t, void *, size_t) {
+  return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation is not built");
+}
+
+sl_status sl_unrolled_backward(sl_problem, const float *, float *, double *, float *) {
+  return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation is not built");
+}
+
+sl_status sl_set_tile_rows(sl_problem P, int32_t rows_per_thread) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (rows_per_thread != 1 && rows_per_thread != 2)
+    return fail(SL_ERR_INVALID_ARG, "rows_per_thread must be 1 or 2");
+  int dev = 0, maxlds = 0;
+  HIPCHK(hipGetDevice(&dev), "device");
+  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
+  if (pdhg_iter_lds_bytes(P->A.k, rows_per_thread) + 8 * 1024 > (size_t)maxlds)
+    return fail(SL_ERR_UNSUPPORTED, "tile needs more LDS than a workgroup may use");
+  P->rpt = rows_per_thread;
+  return SL_OK;
+}
+
+void sl_destroy(sl_problem P) {
+  if (!P) return;
+  (void)hipStreamSynchronize(P->st);
+  delete P;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// internal.hpp -- types shared by the host code and the HIP kernels of libsublabel.
+//
+// Workspace layout (all inside the caller's buffer, every array 256-byte aligned):
+//   planes of H*W elements padded to a multiple of 64 elements ("plane stride" ps)
+//   u[3][k]     rotating primal buffers: u_prev, u, u_next
+//   s[2][k]     multiplier of the z-equality: s, s_prev (s_new overwrites s_prev)
+//   v[k], z[k]  data-term duals (float or bf16), updated in place
+//   p[2][2k]    TV duals, double-buffered (halo reads of the old p): px_i at plane i,
+//               py_i at plane k+i (float or bf16)
+//   q[1]        scalar dual of the pointwise max of the conjugates
+//   fn[1]       data image mapped to normalised label coordinates (QUAD, TRUNC_QUAD)
+//   w[L]        per-label additive values (optional)
+//   cost[M]     per-interval convex envelopes of the sampled costs (SAMPLED)
+//   tau[M]      normalised sample positions (SAMPLED)
+//   mon_u[k], mon_b[1]  monitor scratch (repaired lifted u, back-projected u)
+//   partials    per-block FP64 partial sums of the monitor, final sums
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SLI_MAXK 32
+#define SLI_MAXM 256
+#define SLI_NSUB 16   // samples per straddling truncated-quadratic interval
+#define SLI_NMON 8    // monitor sums
+
+enum { SLI_QUAD = 0, SLI_TRUNC = 1, SLI_SAMPLED = 2 };
+
+// Scalars and per-label tables of one problem (passed by value as kernel argument).
+struct IterArgs {
+  int H, W, k, M;
+  long long ps;           // plane stride (elements)
+  float sig_p, sig_q;     // steps of p and q
+  float lam;              // lambda in normalised label units
+  float a, ia, nu, del;   // quadratic coefficient, its inverse, truncation, band half-width
+  float gam[SLI_MAXK + 1];
+  float h[SLI_MAXK], ih[SLI_MAXK];
+  float sig[SLI_MAXK];    // shared step of v_i and z_i
+  float taus[SLI_MAXK];   // step of s_i
+  float ig0[SLI_MAXK];    // 1 / (1 + gamma_i^2)
+  float ig1[SLI_MAXK];    // 1 / (1 + gamma_{i+1}^2)
+  int sidx[SLI_MAXK + 1]; // sample index of every label (SAMPLED)
+};
+
+template <typename DT>
+struct IterPtrs {
+  const float *u, *up;
+  float *un;
+  const float *s;
+  float *sp;   // s_prev on entry, s_new on exit
+  DT *v, *z;
+  const DT *pin;
+  DT *pout;
+  float *qd;
+  const float *fn, *wadd, *cost, *tau;
+};
+
+// Host-side launchers (pdhg_iter.hip, aux.hip).
+hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int rpt, const IterArgs &A,
+                            const void *ptrs, hipStream_t st);
+size_t pdhg_iter_lds_bytes(int k, int rpt);
+
+struct MonPtrs {
+  const float *u, *s;
+  const void *v, *z, *p;  // storage type per `bf16`
+  const float *qd, *fn, *wadd, *cost, *tau;
+  const float *f_orig;    // not used
+  float *mon_u, *mon_b;
+  double *part1, *part2, *final_;
+  int bf16;
+};
+
+hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonPtrs &P,
+                          hipStream_t st, int *nblocks_out);
+int monitor_blocks(const IterArgs &A);
+
+hipError_t launch_init_fn(const float *f, float *fn, long long N, float shift, float iscale,
+                          hipStream_t st);
+hipError_t launch_copy_planes(const float *src, float *dst, int nplanes, long long N,
+                              long long ps, hipStream_t st);
+hipError_t launch_convexify(const float *samples, float *cost, const float *tau,
+                            const IterArgs &A, hipStream_t st);
+hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
+                          double shift, double scale, hipStream_t st);
+hipError_t launch_pack_state(const void *const *planes, const int *bf16, int nplanes,
+                             long long N, long long ps, float *dst, int unpack,
+                             hipStream_t st);

@@ -1,0 +1,203 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle. GPU only.
+
+Tolerances (FP32 arithmetic against FP64):
+  * one iteration from a random state: |gpu - oracle| <= 2e-5 (1 + |oracle|) per entry
+  * ROF 64x64, L = 2, 2000 iterations: max |u_gpu - u_oracle| <= 1e-4 and relative
+    primal / dual bounds within 1e-5
+  * fixed iteration counts on truncated-quadratic and sampled problems: relative bounds
+    within 1e-5
+  * the monitor on an identical state: relative 1e-9 (both reduce in FP64)
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1512_01383_amd as S  # noqa: E402
+
+
+def _pair(wl, orc, storage="fp32", normalize=True):
+    g = S.Problem.from_workload(wl, storage=storage, normalize=normalize)
+    o = orc.Problem(wl, normalize=normalize)
+    return g, o
+
+
+def _load_same_state(g, o, st):
+    g.load_state(S.pack_state(st))
+    o.set_state({n: st[n].astype(np.float64) for n in st})
+
+
+def _gpu_state(g):
+    t = g.save_state()
+    torch.cuda.synchronize()
+    return S.unpack_state(t, g.k, g.H, g.W)
+
+
+def _rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-30)
+
+
+def _sampled_workload(H, Wd, seed, L=8, M=64, lam=0.5):
+    rng = np.random.default_rng(seed)
+    tau = np.arange(M, dtype=np.float64)
+    idx = np.round(np.linspace(0, M - 1, L)).astype(int)
+    gamma = tau[idx]
+    base = rng.uniform(0, 1, size=(M, H, Wd))
+    costs = np.abs(base - base[rng.integers(0, M)]).astype(np.float32)
+    return W.Workload("smp", H, Wd, gamma, W.SAMPLED, lam, tau=tau, samples=costs)
+
+
+def _cases():
+    rng = np.random.default_rng(100)
+    out = []
+    # (name, workload) spanning several 64x4 tiles with ragged tails
+    f = rng.uniform(-0.1, 1.1, size=(13, 150)).astype(np.float32)
+    out.append(("quad_L2", W.Workload("q2", 13, 150, W.equispaced(2), W.QUAD, 0.2, f=f, a=1.0)))
+    out.append(("quad_L6_offset", W.Workload("q6", 13, 150, np.array([-1.0, -0.4, 0.1, 0.9, 1.3, 2.0]),
+                                             W.QUAD, 0.3, f=2 * f, a=3.0)))
+    for L in (2, 5, 10, 20):
+        wl = W.truncated_quadratic(L=L, H=9, W=131, seed=7 + L)
+        out.append((f"tq_L{L}", wl))
+    wl = W.truncated_quadratic(L=8, H=11, W=70, seed=5)
+    wl.tau = wl.gamma.copy()
+    wl.samples = rng.normal(0, 0.05, size=(8, 11, 70)).astype(np.float32)
+    out.append(("tq_add_L8", wl))
+    wq = W.Workload("qa", 7, 66, W.equispaced(4), W.QUAD, 0.2, f=f[:7, :66].copy(), a=1.0,
+                    tau=W.equispaced(4), samples=rng.normal(0, 0.1, size=(4, 7, 66)).astype(np.float32))
+    out.append(("quad_add_L4", wq))
+    out.append(("sampled_L8", _sampled_workload(10, 97, 3)))
+    out.append(("sampled_L4_M13", _sampled_workload(6, 65, 4, L=4, M=13)))
+    out.append(("one_pixel", W.Workload("px", 1, 1, W.equispaced(4), W.TRUNC_QUAD, 0.2,
+                                        f=np.array([[0.3]], np.float32), a=2.0, nu=0.025)))
+    out.append(("one_row", W.truncated_quadratic(L=6, H=1, W=200, seed=3)))
+    out.append(("one_col", W.truncated_quadratic(L=6, H=77, W=1, seed=4)))
+    out.append(("k27", W.truncated_quadratic(L=28, H=5, W=70, seed=9)))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("storage", ["fp32"])
+@pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
+def test_single_iteration_from_random_state(orc, name, wl, storage):
+    """One fused iteration from the same random state: every field of the new state."""
+    g, o = _pair(wl, orc, storage)
+    st = W.random_state(11, wl.k, wl.H, wl.W)
+    _load_same_state(g, o, st)
+    g.run(1)
+    o.run(1)
+    got = _gpu_state(g)
+    ref = o.get_state()
+    for n in S.STATE_ORDER:
+        err = np.abs(got[n].astype(np.float64) - ref[n])
+        bound = 2e-5 * (1.0 + np.abs(ref[n]))
+        worst = np.unravel_index(np.argmax(err - bound), err.shape)
+        assert np.all(err <= bound), f"{name}/{n}: err {err[worst]:.3e} at {worst}, ref {ref[n][worst]}"
+
+
+@pytest.mark.parametrize("name,wl", CASES[:8], ids=[c[0] for c in CASES[:8]])
+def test_monitor_on_identical_state(orc, name, wl):
+    """The FP64 monitor of both sides on the same (FP32) state."""
+    g, o = _pair(wl, orc)
+    st = W.random_state(12, wl.k, wl.H, wl.W, scale=0.3)
+    _load_same_state(g, o, st)
+    eg = g.energy()
+    eo = o.monitor()
+    assert _rel(eg["primal_ub"], eo["primal"]) < 1e-9
+    assert _rel(eg["dual_lb"], eo["dual"]) < 1e-9
+    assert _rel(eg["e_nonconvex"], eo["e_nc"]) < 1e-9
+
+
+def test_rof_2000_iterations(orc):
+    """ROF 64x64, L = 2, lambda = 0.2, 2000 iterations: max |du| <= 1e-4, energies 1e-5."""
+    wl = W.rof()
+    g, o = _pair(wl, orc)
+    g.run(wl.iters)
+    o.run(wl.iters)
+    _, ug = g.read_u()
+    _, uo = o.read_u()
+    err = np.abs(ug.cpu().numpy().astype(np.float64) - uo).max()
+    assert err <= 1e-4, err
+    eg, eo = g.energy(), o.monitor()
+    assert _rel(eg["primal_ub"], eo["primal"]) <= 1e-5
+    assert _rel(eg["dual_lb"], eo["dual"]) <= 1e-5
+    assert eg["rel_gap"] < 1e-4
+
+
+@pytest.mark.parametrize("L,iters", [(5, 400), (10, 300), (20, 200)])
+def test_truncated_quadratic_fixed_iterations(orc, L, iters):
+    wl = W.truncated_quadratic(L=L, H=40, W=72, seed=20 + L)
+    g, o = _pair(wl, orc)
+    g.run(iters)
+    o.run(iters)
+    eg, eo = g.energy(), o.monitor()
+    assert _rel(eg["primal_ub"], eo["primal"]) <= 1e-5
+    assert _rel(eg["dual_lb"], eo["dual"]) <= 1e-5
+    assert _rel(eg["e_nonconvex"], eo["e_nc"]) <= 1e-5
+
+
+def test_sampled_fixed_iterations(orc):
+    wl = _sampled_workload(24, 90, 8)
+    g, o = _pair(wl, orc)
+    g.run(200)
+    o.run(200)
+    eg, eo = g.energy(), o.monitor()
+    assert _rel(eg["primal_ub"], eo["primal"]) <= 1e-5
+    assert _rel(eg["dual_lb"], eo["dual"]) <= 1e-5
+
+
+def test_save_load_roundtrip_and_determinism(orc):
+    wl = W.truncated_quadratic(L=6, H=30, W=100, seed=31)
+    g1 = S.Problem.from_workload(wl)
+    g1.run(37)
+    st = g1.save_state().clone()
+    g1.run(40)
+    a = g1.save_state().clone()
+    g2 = S.Problem.from_workload(wl)
+    g2.load_state(st)
+    g2.run(40)
+    b = g2.save_state().clone()
+    g3 = S.Problem.from_workload(wl)
+    g3.run(77)
+    c = g3.save_state().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a, c)
+    e1, e3 = g1.energy(), g3.energy()
+    assert e1["primal_ub"] == e3["primal_ub"] and e1["dual_lb"] == e3["dual_lb"]
+
+
+def test_tile_rows_do_not_change_results():
+    wl = W.truncated_quadratic(L=6, H=37, W=130, seed=32)
+    outs = []
+    for rpt in (1, 2):
+        g = S.Problem.from_workload(wl)
+        g.set_tile_rows(rpt)
+        g.run(25)
+        outs.append(g.save_state().clone())
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_invalid_arguments_gpu():
+    f = np.zeros((3, 3), np.float32)
+    with pytest.raises(S.SublabelError) as e:
+        S.Problem(3, 3, [0.0, 0.0, 1.0], S.RHO_QUAD, 0.1, f=f)
+    assert e.value.status == 1
+    with pytest.raises(S.SublabelError) as e:
+        S.Problem(3, 3, [0.0, 0.5, 1.0], S.RHO_QUAD, 0.1, f=np.full((3, 3), np.nan, np.float32))
+    assert e.value.status == 1
+    with pytest.raises(S.SublabelError) as e:
+        S.Problem(0, 3, [0.0, 1.0], S.RHO_QUAD, 0.1, f=f)
+    assert e.value.status == 1
+    with pytest.raises(S.SublabelError) as e:
+        S.Problem(3, 3, W.equispaced(40), S.RHO_QUAD, 0.1, f=f)
+    assert e.value.status == 2
