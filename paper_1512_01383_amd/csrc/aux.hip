@@ -29,7 +29,8 @@ struct PieceD {
   int nv;      // PL vertex count
   int ml, mr;  // straddle hull range
   int mode;    // 0: explicit vertices from cost planes, 1: flat, 2: straddle samples
-  const float *cost, *tau;
+  const float *cost;
+  const double *tau;
   long long ps, x;
   int m0;
   double bshift, cshift, wlo;  // additive term
@@ -101,15 +102,16 @@ __device__ double val_full(const PieceD &P, double t) {
 }
 
 template <int PIECE, bool ADD>
-__device__ void make_piece(const IterArgs &A, const MonPtrs &M, long long x, int i, PieceD &P) {
-  P.g0 = A.gam[i];
-  P.g1 = A.gam[i + 1];
-  P.a = A.a;
-  P.nu = A.nu;
+__device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long x,
+                           int i, PieceD &P) {
+  P.g0 = D.gam[i];
+  P.g1 = D.gam[i + 1];
+  P.a = D.a;
+  P.nu = D.nu;
   P.ps = A.ps;
   P.x = x;
   P.cost = M.cost;
-  P.tau = M.tau;
+  P.tau = M.taud;
   P.bshift = P.cshift = P.wlo = 0.0;
   if (PIECE == SLI_SAMPLED) {
     P.kind = 1;
@@ -118,7 +120,7 @@ __device__ void make_piece(const IterArgs &A, const MonPtrs &M, long long x, int
     P.nv = A.sidx[i + 1] - A.sidx[i] + 1;
   } else {
     const float fc = M.fn[x];
-    P.c = fc;
+    P.c = ((double)M.f_orig[x] - D.shift) / D.scale;
     if (PIECE == SLI_QUAD) {
       P.kind = 0;
     } else {
@@ -196,7 +198,7 @@ __device__ void block_sum(double *vals, int nv, double *out_row) {
 
 // per-pixel terms: data parts of both primal bounds, dual, nonconvex data term
 template <int PIECE, bool ADD, typename DT>
-__global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
+__global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPtrs M) {
   const long long N = (long long)A.H * A.W;
   const long long x = (long long)blockIdx.x * MB + threadIdx.x;
   double vals[4] = {0, 0, 0, 0};
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
     PieceD P;
     // (a) repair: simplex projection of -h s by Michelot's finite algorithm
     double xs[SLI_MAXK], w[SLI_MAXK];
-    for (int i = 0; i < k; i++) xs[i] = -(double)A.h[i] * M.s[i * A.ps + x];
+    for (int i = 0; i < k; i++) xs[i] = -D.h[i] * M.s[i * A.ps + x];
     double theta = 0.0;
     {
       bool act[SLI_MAXK];
@@ -236,28 +238,28 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
     for (int i = k - 1; i >= 0; i--) {
       double al = 0.0;
       if (w[i] > 0.0) al = fmin(fmax((M.u[i * A.ps + x] - lo) / w[i], 0.0), 1.0);
-      M.mon_u[i * A.ps + x] = (float)(lo + w[i] * al);
+      M.mon_u[i * A.ps + x] = lo + w[i] * al;
       if (w[i] > 0.0) {
-        make_piece<PIECE, ADD>(A, M, x, i, P);
-        dat += w[i] * val_full(P, (double)A.gam[i] + (double)A.h[i] * al);
+        make_piece<PIECE, ADD>(A, D, M, x, i, P);
+        dat += w[i] * val_full(P, D.gam[i] + D.h[i] * al);
       }
       lo += w[i];
     }
     vals[0] = dat;
     // (b) graph lifting of the back-projected u
-    double t = A.gam[0];
-    for (int i = 0; i < k; i++) t += (double)A.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
-    ((double *)M.mon_b)[x] = t;
+    double t = D.gam[0];
+    for (int i = 0; i < k; i++) t += D.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
+    M.mon_b[x] = t;
     int is = 0;
-    while (is < k - 1 && t > (double)A.gam[is + 1]) is++;
-    double al = fmin(fmax((t - A.gam[is]) / (double)A.h[is], 0.0), 1.0);
-    make_piece<PIECE, ADD>(A, M, x, is, P);
-    vals[1] = val_full(P, (double)A.gam[is] + (double)A.h[is] * al);
+    while (is < k - 1 && t > D.gam[is + 1]) is++;
+    double al = fmin(fmax((t - D.gam[is]) / D.h[is], 0.0), 1.0);
+    make_piece<PIECE, ADD>(A, D, M, x, is, P);
+    vals[1] = val_full(P, D.gam[is] + D.h[is] * al);
     // dual bound
     const DT *p = (const DT *)M.p;
     double mx = -INFINITY, pre = 0.0;
     for (int i = 0; i < k; i++) {
-      double rad = (double)A.lam * A.h[i];
+      double rad = D.lam * D.h[i];
       double px, py, qx, qy;
       proj_p(A, p, i, x, rad, px, py);
       double vh = 0.0;
@@ -271,9 +273,9 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
         proj_p(A, p, i, x - A.W, rad, qx, qy);
         vh -= qy;
       }
-      make_piece<PIECE, ADD>(A, M, x, i, P);
-      double y = vh / A.h[i];
-      double val = pre - (double)A.gam[i] * y + conj_full(P, y);
+      make_piece<PIECE, ADD>(A, D, M, x, i, P);
+      double y = vh / D.h[i];
+      double val = pre - D.gam[i] * y + conj_full(P, y);
       mx = fmax(mx, val);
       pre += vh;
     }
@@ -282,17 +284,17 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
     double e;
     if (PIECE == SLI_SAMPLED) {
       int m = 0;
-      while (m < A.M - 2 && t > (double)M.tau[m + 1]) m++;
-      double a2 = (t - M.tau[m]) / ((double)M.tau[m + 1] - M.tau[m]);
+      while (m < A.M - 2 && t > M.taud[m + 1]) m++;
+      double a2 = (t - M.taud[m]) / (M.taud[m + 1] - M.taud[m]);
       const float *raw = M.cost + (long long)A.M * A.ps;
       e = (1.0 - a2) * raw[m * A.ps + x] + a2 * raw[(m + 1) * A.ps + x];
     } else {
-      double d = t - (double)M.fn[x];
-      e = 0.5 * (double)A.a * d * d;
-      if (PIECE == SLI_TRUNC && e > A.nu) e = A.nu;
+      double d = t - ((double)M.f_orig[x] - D.shift) / D.scale;
+      e = 0.5 * D.a * d * d;
+      if (PIECE == SLI_TRUNC && e > D.nu) e = D.nu;
     }
     if (ADD) {
-      double a3 = (t - A.gam[is]) / (double)A.h[is];
+      double a3 = (t - D.gam[is]) / D.h[is];
       e += (1.0 - a3) * M.wadd[is * A.ps + x] + a3 * M.wadd[(is + 1) * A.ps + x];
     }
     vals[3] = e;
@@ -301,25 +303,26 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonPtrs M) {
 }
 
 // TV terms of both primal points and of the back-projected u
-__global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonPtrs M) {
+__global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs M) {
   const long long N = (long long)A.H * A.W;
   const long long x = (long long)blockIdx.x * MB + threadIdx.x;
   double vals[3] = {0, 0, 0};
   if (x < N) {
     const int r = (int)(x / A.W), cc = (int)(x % A.W);
     const bool hx = cc < A.W - 1, hy = r < A.H - 1;
-    const double *b = (const double *)M.mon_b;
+    const double *b = M.mon_b;
+    const double *mu = M.mon_u;
     double tr = 0.0, tg = 0.0;
     for (int i = 0; i < A.k; i++) {
-      double u0 = M.mon_u[i * A.ps + x];
-      double gx = hx ? M.mon_u[i * A.ps + x + 1] - u0 : 0.0;
-      double gy = hy ? M.mon_u[i * A.ps + x + A.W] - u0 : 0.0;
-      tr += (double)A.h[i] * sqrt(gx * gx + gy * gy);
-      double g0 = A.gam[i], ih = 1.0 / (double)A.h[i];
+      double u0 = mu[i * A.ps + x];
+      double gx = hx ? mu[i * A.ps + x + 1] - u0 : 0.0;
+      double gy = hy ? mu[i * A.ps + x + A.W] - u0 : 0.0;
+      tr += D.h[i] * sqrt(gx * gx + gy * gy);
+      double g0 = D.gam[i], ih = 1.0 / D.h[i];
       double l0 = fmin(fmax((b[x] - g0) * ih, 0.0), 1.0);
       double lx = hx ? fmin(fmax((b[x + 1] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
       double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
-      tg += (double)A.h[i] * sqrt(lx * lx + ly * ly);
+      tg += D.h[i] * sqrt(lx * lx + ly * ly);
     }
     double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
     vals[0] = tr;
@@ -348,11 +351,12 @@ __global__ __launch_bounds__(MB) void monitor_final(const double *part1, const d
 }
 
 template <int PIECE, bool ADD>
-hipError_t launch_mon_t(const IterArgs &A, const MonPtrs &M, hipStream_t st, int nb) {
+hipError_t launch_mon_t(const IterArgs &A, const MonArgs &D, const MonPtrs &M, hipStream_t st,
+                        int nb) {
   if (M.bf16)
-    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, uint16_t>), dim3(nb), dim3(MB), 0, st, A, M);
+    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, uint16_t>), dim3(nb), dim3(MB), 0, st, A, D, M);
   else
-    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, float>), dim3(nb), dim3(MB), 0, st, A, M);
+    hipLaunchKernelGGL((monitor_pixel<PIECE, ADD, float>), dim3(nb), dim3(MB), 0, st, A, D, M);
   return hipGetLastError();
 }
 
@@ -380,7 +384,7 @@ __global__ void k_copy_planes(const float *src, float *dst, int np, long long N,
 
 // Convex envelope of the samples on every label interval: in one dimension the envelope
 // at a sample position is the least value of a chord between two samples that bracket it.
-__global__ void k_convexify(const float *samples, float *cost, const float *tau, IterArgs A) {
+__global__ void k_convexify(const float *samples, float *cost, const double *tau, IterArgs A) {
   const long long N = (long long)A.H * A.W;
   long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N * A.k) return;
@@ -405,18 +409,17 @@ __global__ void k_convexify(const float *samples, float *cost, const float *tau,
   }
 }
 
-__global__ void k_readout(const float *u, float *ulift, float *uout, IterArgs A, double shift,
-                          double scale) {
+__global__ void k_readout(const float *u, float *ulift, float *uout, IterArgs A, MonArgs D) {
   const long long N = (long long)A.H * A.W;
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= N) return;
-  double t = A.gam[0];
+  double t = D.gam[0];
   for (int i = 0; i < A.k; i++) {
     float ui = u[i * A.ps + x];
     if (ulift) ulift[i * N + x] = ui;
-    t += (double)A.h[i] * fmin(fmax((double)ui, 0.0), 1.0);
+    t += D.h[i] * fmin(fmax((double)ui, 0.0), 1.0);
   }
-  if (uout) uout[x] = (float)(shift + scale * t);
+  if (uout) uout[x] = (float)(D.shift + D.scale * t);
 }
 
 struct PackArgs {
@@ -447,18 +450,18 @@ inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, MB); }
 
-hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonPtrs &M,
-                          hipStream_t st, int *nb_out) {
+hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonArgs &D,
+                          const MonPtrs &M, hipStream_t st, int *nb_out) {
   const int nb = monitor_blocks(A);
   hipError_t e;
   if (piece == SLI_QUAD)
-    e = add ? launch_mon_t<SLI_QUAD, true>(A, M, st, nb) : launch_mon_t<SLI_QUAD, false>(A, M, st, nb);
+    e = add ? launch_mon_t<SLI_QUAD, true>(A, D, M, st, nb) : launch_mon_t<SLI_QUAD, false>(A, D, M, st, nb);
   else if (piece == SLI_TRUNC)
-    e = add ? launch_mon_t<SLI_TRUNC, true>(A, M, st, nb) : launch_mon_t<SLI_TRUNC, false>(A, M, st, nb);
+    e = add ? launch_mon_t<SLI_TRUNC, true>(A, D, M, st, nb) : launch_mon_t<SLI_TRUNC, false>(A, D, M, st, nb);
   else
-    e = launch_mon_t<SLI_SAMPLED, false>(A, M, st, nb);
+    e = launch_mon_t<SLI_SAMPLED, false>(A, D, M, st, nb);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(monitor_tv, dim3(nb), dim3(MB), 0, st, A, M);
+  hipLaunchKernelGGL(monitor_tv, dim3(nb), dim3(MB), 0, st, A, D, M);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(monitor_final, dim3(7), dim3(MB), 0, st, M.part1, M.part2, nb, M.final_);
   if (nb_out) *nb_out = nb;
@@ -486,7 +489,7 @@ hipError_t launch_copy_planes(const float *src, float *dst, int np, long long N,
   return hipGetLastError();
 }
 
-hipError_t launch_convexify(const float *samples, float *cost, const float *tau,
+hipError_t launch_convexify(const float *samples, float *cost, const double *tau,
                             const IterArgs &A, hipStream_t st) {
   long long n = (long long)A.H * A.W * A.k;
   hipLaunchKernelGGL(k_convexify, dim3(nblk(n, 256)), dim3(256), 0, st, samples, cost, tau, A);
@@ -494,10 +497,9 @@ hipError_t launch_convexify(const float *samples, float *cost, const float *tau,
 }
 
 hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
-                          double shift, double scale, hipStream_t st) {
+                          const MonArgs &D, hipStream_t st) {
   long long N = (long long)A.H * A.W;
-  hipLaunchKernelGGL(k_readout, dim3(nblk(N, 256)), dim3(256), 0, st, u, ulift, uout, A, shift,
-                     scale);
+  hipLaunchKernelGGL(k_readout, dim3(nblk(N, 256)), dim3(256), 0, st, u, ulift, uout, A, D);
   return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   long long N, ps;
-  size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_w, off_cost, off_tau;
+  size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_forig, off_w, off_cost, off_tau,
+      off_taud;
   size_t off_monu, off_monb, off_part1, off_part2, off_fin, off_flag, total;
   size_t state_lo, state_hi;  // contiguous range holding u, s, v, z, p, qd
 };
@@ -70,10 +71,12 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   L.state_hi = o;
   const bool sampled = d->rho == SL_RHO_SAMPLED;
   L.off_fn = take(sampled ? 0 : pf);
+  L.off_forig = take(sampled ? 0 : pf);
   L.off_w = take((!sampled && d->samples) ? (size_t)d->L * pf : 0);
   L.off_cost = take(sampled ? (size_t)2 * d->M * pf : 0);
   L.off_tau = take(sampled ? (size_t)d->M * 4 : 0);
-  L.off_monu = take(k * pf);
+  L.off_taud = take(sampled ? (size_t)d->M * 8 : 0);
+  L.off_monu = take((size_t)k * L.ps * 8);
   L.off_monb = take((size_t)L.ps * 8);
   L.off_part1 = take((size_t)nb_mon * SLI_NMON * 8);
   L.off_part2 = take((size_t)nb_mon * SLI_NMON * 8);
@@ -154,6 +157,7 @@ struct sl_problem_ {
   bool add = false, bf16 = false;
   int rpt = 1;
   IterArgs A{};
+  MonArgs D{};
   double shift = 0, scale = 1, lam = 0;
   hipStream_t st = nullptr;
   Layout lay{};
@@ -165,6 +169,7 @@ struct sl_problem_ {
   int check_every = 50;
   int nb_mon = 0;
   std::vector<float> tau_host;
+  std::vector<double> taud_host;
   double fin[SLI_NMON];
 
   float *ubuf(int j) { return (float *)(ws + lay.off_u) + (size_t)j * A.k * lay.ps; }
@@ -190,6 +195,14 @@ void fill_args(sl_problem_ *P) {
   A.M = d->rho == SL_RHO_SAMPLED ? d->M : 0;
   A.ps = P->lay.ps;
   P->lam = d->lambda * P->scale;
+  MonArgs &D = P->D;
+  for (int j = 0; j < L; j++) D.gam[j] = g[j];
+  for (int i = 0; i < k; i++) D.h[i] = h[i];
+  D.shift = P->shift;
+  D.scale = P->scale;
+  D.lam = P->lam;
+  D.a = d->rho != SL_RHO_SAMPLED ? d->a * P->scale * P->scale : 0.0;
+  D.nu = d->nu;
   A.lam = (float)P->lam;
   // diagonal preconditioning: inverse absolute row / column sums of the operator
   A.sig_p = 0.5f;
@@ -211,7 +224,11 @@ void fill_args(sl_problem_ *P) {
     A.del = d->rho == SL_RHO_TRUNC_QUAD ? (float)sqrt(2.0 * d->nu / an) : 0.f;
   } else {
     P->tau_host.resize(d->M);
-    for (int m = 0; m < d->M; m++) P->tau_host[m] = (float)((d->tau[m] - P->shift) / P->scale);
+    P->taud_host.resize(d->M);
+    for (int m = 0; m < d->M; m++) {
+      P->taud_host[m] = (d->tau[m] - P->shift) / P->scale;
+      P->tau_host[m] = (float)P->taud_host[m];
+    }
     for (int j = 0; j < L; j++)
       for (int m = 0; m < d->M; m++)
         if (d->tau[m] == d->gamma[j]) A.sidx[j] = m;
@@ -281,15 +298,15 @@ sl_status monitor(sl_problem_ *P, sl_report *out) {
   M.fn = (const float *)(P->ws + P->lay.off_fn);
   M.wadd = (const float *)(P->ws + P->lay.off_w);
   M.cost = (const float *)(P->ws + P->lay.off_cost);
-  M.tau = (const float *)(P->ws + P->lay.off_tau);
-  M.f_orig = nullptr;
-  M.mon_u = (float *)(P->ws + P->lay.off_monu);
-  M.mon_b = (float *)(P->ws + P->lay.off_monb);
+  M.f_orig = (const float *)(P->ws + P->lay.off_forig);
+  M.taud = (const double *)(P->ws + P->lay.off_taud);
+  M.mon_u = (double *)(P->ws + P->lay.off_monu);
+  M.mon_b = (double *)(P->ws + P->lay.off_monb);
   M.part1 = (double *)(P->ws + P->lay.off_part1);
   M.part2 = (double *)(P->ws + P->lay.off_part2);
   M.final_ = (double *)(P->ws + P->lay.off_fin);
   M.bf16 = P->bf16;
-  HIPCHK(launch_monitor(P->piece, P->add, P->A, M, P->st, nullptr), "monitor launch");
+  HIPCHK(launch_monitor(P->piece, P->add, P->A, P->D, M, P->st, nullptr), "monitor launch");
   HIPCHK(hipMemcpyAsync(P->fin, M.final_, 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
          "monitor copy");
   HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
@@ -451,15 +468,20 @@ sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *s
     float fs = (float)P->shift, is = (float)(1.0 / P->scale);
     if ((e = launch_init_fn(desc->f, (float *)(P->ws + lay.off_fn), N, fs, is, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "init f"));
+    if ((e = launch_copy_planes(desc->f, (float *)(P->ws + lay.off_forig), 1, N, lay.ps, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy f"));
     if (P->add &&
         (e = launch_copy_planes(desc->samples, (float *)(P->ws + lay.off_w), desc->L, N, lay.ps, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy w"));
   } else {
     float *tau_d = (float *)(P->ws + lay.off_tau);
+    double *taud_d = (double *)(P->ws + lay.off_taud);
     if ((e = hipMemcpyAsync(tau_d, P->tau_host.data(), 4 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy tau"));
+    if ((e = hipMemcpyAsync(taud_d, P->taud_host.data(), 8 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "copy tau"));
     float *cost = (float *)(P->ws + lay.off_cost);
-    if ((e = launch_convexify(desc->samples, cost, tau_d, P->A, P->st)) != hipSuccess)
+    if ((e = launch_convexify(desc->samples, cost, taud_d, P->A, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "convexify"));
     if ((e = launch_copy_planes(desc->samples, cost + (size_t)desc->M * lay.ps, desc->M, N, lay.ps, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy raw samples"));
@@ -499,7 +521,7 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
 sl_status sl_read_u(sl_problem P, float *ulift, float *u) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (!ulift && !u) return SL_OK;
-  HIPCHK(launch_readout(P->ubuf(P->iu), ulift, u, P->A, P->shift, P->scale, P->st), "readout");
+  HIPCHK(launch_readout(P->ubuf(P->iu), ulift, u, P->A, P->D, P->st), "readout");
   return SL_OK;
 }
 

@@ -96,7 +96,13 @@ __device__ __forceinline__ void proj_quad(float a, float ia, float c, float g0, 
   const float ac = a * c;
   float Y = parabola_root(a, y + ac, w + 0.5f * ac * c);
   Y = fminf(fmaxf(Y, a * g0), a * g1);
-  y = Y - ac;
+  // one Newton step on the stationarity (yy - y) + (g(yy) - w) g'(yy) = 0 in the original
+  // coordinates removes the cancellation of the shift by a c
+  float yy = Y - ac;
+  const float gp = c + yy * ia, gv = yy * (c + 0.5f * yy * ia) - w;
+  const float den = 1.f + gp * gp + gv * ia;
+  if (den > 0.f) yy = fminf(fmaxf(yy - ((yy - y) + gv * gp) / den, a * d0), a * d1);
+  y = yy;
   w = y * (c + 0.5f * y * ia);
 }
 
@@ -104,25 +110,37 @@ __device__ __forceinline__ void proj_quad(float a, float ia, float c, float g0, 
 //
 // For a convex piecewise-linear rho_i with vertices (t_m, r_m) the conjugate is
 // max_m (t_m y - r_m): linear parts of slope t_m between kinks at the slopes of rho_i.
-// Vertices are pushed in increasing t; the nearest graph point is tracked on the fly.
+// Vertices are pushed in increasing t. The exterior of the epigraph is partitioned into
+// the strips above-normal to each linear part (the perpendicular foot lies on the part)
+// and the normal cones of the kinks (Fig. 2, right); the projection is decided by which
+// region holds the point. Deciding by comparing distances instead would be
+// ill-conditioned in FP32 for points far below the graph. Where rounding puts a point on
+// a region boundary, both neighbouring answers coincide up to rounding.
 
 struct PLProj {
-  float y0, w0, gmax, bd, by, bw, tp, cp, lo;
-  bool has;
+  float y0, w0, gmax, bd, by, bw, tp, cp, lo, ay, aw;
+  bool has, found;
   __device__ __forceinline__ void init(float y, float w) {
     y0 = y;
     w0 = w;
     gmax = -SL_INF;
     bd = SL_INF;
-    by = y;
-    bw = w;
+    by = ay = y;
+    bw = aw = w;
     lo = -SL_INF;
-    has = false;
+    has = found = false;
     tp = cp = 0.f;
   }
+  // linear part of slope t through (., -r) restricted to [l, hi]
   __device__ __forceinline__ void seg(float t, float r, float l, float hi) {
-    float mu = (t * y0 - r - w0) / (1.f + t * t);
-    float yf = fminf(fmaxf(y0 - mu * t, l), hi);
+    float mu = (t * y0 - r - w0) / (1.f + t * t);   // >= 0: point below the line
+    float yr = y0 - mu * t;                          // perpendicular foot
+    if (!found && mu >= 0.f && yr >= l && yr <= hi) {
+      found = true;
+      ay = yr;
+      aw = t * yr - r;
+    }
+    float yf = fminf(fmaxf(yr, l), hi);              // fallback: nearest point of the part
     float wf = t * yf - r;
     float d = (yf - y0) * (yf - y0) + (wf - w0) * (wf - w0);
     if (d < bd) {
@@ -131,12 +149,24 @@ struct PLProj {
       bw = wf;
     }
   }
+  // kink at y = b between parts of slopes t0 < t1: its normal cone is
+  // {(b, g(b)) + a (t0, -1) + c (t1, -1) : a, c >= 0}
+  __device__ __forceinline__ void kink(float b, float t0, float r0, float t1) {
+    float gb = t0 * b - r0;
+    float dw = gb - w0, dy = y0 - b;
+    if (!found && dw >= 0.f && t0 * dw <= dy && dy <= t1 * dw) {
+      found = true;
+      ay = b;
+      aw = gb;
+    }
+  }
   __device__ __forceinline__ void push(float t, float r) {
     gmax = fmaxf(gmax, t * y0 - r);
     if (has) {
-      float kink = (r - cp) / (t - tp);
-      seg(tp, cp, lo, kink);
-      lo = kink;
+      float b = (r - cp) / (t - tp);
+      seg(tp, cp, lo, b);
+      kink(b, tp, cp, t);
+      lo = b;
     }
     tp = t;
     cp = r;
@@ -145,8 +175,8 @@ struct PLProj {
   __device__ __forceinline__ void finish(float &y, float &w) {
     seg(tp, cp, lo, SL_INF);
     if (w0 < gmax) {
-      y = by;
-      w = bw;
+      y = found ? ay : by;
+      w = found ? aw : bw;
     }
   }
 };

@@ -60,29 +60,38 @@ hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int rpt, const IterA
                             const void *ptrs, hipStream_t st);
 size_t pdhg_iter_lds_bytes(int k, int rpt);
 
+// Double-precision problem parameters for the monitor (the certificate is evaluated for
+// the problem defined by the caller's double labels / coefficients and the FP32 data).
+struct MonArgs {
+  double gam[SLI_MAXK + 1];
+  double h[SLI_MAXK];
+  double a, nu, shift, scale, lam;
+};
+
 struct MonPtrs {
   const float *u, *s;
   const void *v, *z, *p;  // storage type per `bf16`
-  const float *qd, *fn, *wadd, *cost, *tau;
-  const float *f_orig;    // not used
-  float *mon_u, *mon_b;
+  const float *qd, *fn, *wadd, *cost;
+  const float *f_orig;    // caller's f (QUAD, TRUNC_QUAD)
+  const double *taud;     // normalised sample positions in double (SAMPLED)
+  double *mon_u, *mon_b;
   double *part1, *part2, *final_;
   int bf16;
 };
 
-hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonPtrs &P,
-                          hipStream_t st, int *nblocks_out);
+hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonArgs &D,
+                          const MonPtrs &P, hipStream_t st, int *nblocks_out);
 int monitor_blocks(const IterArgs &A);
 
 hipError_t launch_init_fn(const float *f, float *fn, long long N, float shift, float iscale,
                           hipStream_t st);
 hipError_t launch_copy_planes(const float *src, float *dst, int nplanes, long long N,
                               long long ps, hipStream_t st);
-hipError_t launch_convexify(const float *samples, float *cost, const float *tau,
+hipError_t launch_convexify(const float *samples, float *cost, const double *taud,
                             const IterArgs &A, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
-                          double shift, double scale, hipStream_t st);
+                          const MonArgs &D, hipStream_t st);
 hipError_t launch_pack_state(const void *const *planes, const int *bf16, int nplanes,
                              long long N, long long ps, float *dst, int unpack,
                              hipStream_t st);
