@@ -164,10 +164,14 @@ sl_status sl_unrolled_forward(sl_problem p, int32_t K, int32_t C, void *ckpt_ws,
 sl_status sl_unrolled_backward(sl_problem p, const float *grad_u_dev, float *grad_f_dev,
                                double *grad_lambda, float *grad_w_dev);
 
-/* Tuning knob: rows of the tile each thread of the fused iteration owns (1 or 2; a
- * tile is 64 columns x 4*rows_per_thread rows). Results do not depend on it. Returns
- * SL_ERR_UNSUPPORTED if the tile would need more LDS than a workgroup may use. */
-sl_status sl_set_tile_rows(sl_problem p, int32_t rows_per_thread);
+/* Tuning knobs of the fused iteration: a block works on a tile of 64 columns x
+ * tile_rows rows with label_groups groups of wavefronts, each walking a contiguous chunk
+ * of the labels. Supported (label_groups, tile_rows): (1,4), (1,8), (2,4), (2,8), (4,4);
+ * (0,0) restores the automatic choice made by sl_create. The iterates differ between
+ * tilings only by FP32 rounding of the label-chunk partial sums. Returns
+ * SL_ERR_UNSUPPORTED if the tiling needs more LDS than a workgroup may use. */
+sl_status sl_set_tiling(sl_problem p, int32_t label_groups, int32_t tile_rows);
+sl_status sl_get_tiling(sl_problem p, int32_t *label_groups, int32_t *tile_rows);
 
 /* Release the handle (NULL-safe). Does not free the caller's workspace; waits for the
  * handle's stream first. */

@@ -83,12 +83,13 @@ def lib():
         L.sl_state_size.argtypes = [vp, C.POINTER(sz)]
         L.sl_save_state.argtypes = [vp, vp, sz]
         L.sl_load_state.argtypes = [vp, vp, sz]
-        L.sl_set_tile_rows.argtypes = [vp, C.c_int32]
+        L.sl_set_tiling.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sl_get_tiling.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.sl_destroy.argtypes = [vp]
         L.sl_destroy.restype = None
         for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
                      "sl_energy", "sl_state_size", "sl_save_state", "sl_load_state",
-                     "sl_set_tile_rows"):
+                     "sl_set_tiling", "sl_get_tiling"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -198,8 +199,14 @@ class Problem:
         _check(lib().sl_load_state(self.h, C.c_void_p(t.data_ptr()), t.numel() * 4))
         self.stream.synchronize()
 
-    def set_tile_rows(self, rows_per_thread: int):
-        _check(lib().sl_set_tile_rows(self.h, int(rows_per_thread)))
+    def set_tiling(self, label_groups: int, tile_rows: int):
+        """(0, 0) restores the automatic choice."""
+        _check(lib().sl_set_tiling(self.h, int(label_groups), int(tile_rows)))
+
+    def get_tiling(self):
+        g, t = C.c_int32(), C.c_int32()
+        _check(lib().sl_get_tiling(self.h, C.byref(g), C.byref(t)))
+        return g.value, t.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -15,8 +15,9 @@ ARCH = os.environ.get("SUBLABEL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-    # no implicit FMA contraction: every variant of a kernel rounds the same way
-    "-ffp-contract=off",
+    # FMA contraction only within one source expression (never across statements), so
+    # every template variant of a kernel rounds the same way
+    "-ffp-contract=on",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",

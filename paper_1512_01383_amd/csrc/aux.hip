@@ -409,6 +409,28 @@ __global__ void k_convexify(const float *samples, float *cost, const double *tau
   }
 }
 
+// Classification of every interval against the band |t - f| <= sqrt(2 nu / a), with the same
+// float decisions as the iteration, and the hull tangent range of the straddling ones.
+__global__ void k_straddle_info(const float *fn, unsigned *sinfo, IterArgs A) {
+  const long long N = (long long)A.H * A.W;
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const float fc = fn[x];
+  const float lo = fc - A.del, hb = fc + A.del;
+  unsigned info = 31u | (31u << 13);
+  int slot = 0;
+  for (int i = 0; i < A.k && slot < 2; i++) {
+    const float g0 = A.gam[i], g1 = A.gam[i + 1];
+    if ((lo <= g0 && g1 <= hb) || (g1 <= lo || g0 >= hb)) continue;
+    int ml, mr;
+    tq_hull_range(A.a, fc, A.nu, g0, g1, ml, mr);
+    const unsigned f = (unsigned)i | ((unsigned)ml << 5) | ((unsigned)mr << 9);
+    info = (info & ~(0x1fffu << (13 * slot))) | (f << (13 * slot));
+    slot++;
+  }
+  sinfo[x] = info;
+}
+
 __global__ void k_readout(const float *u, float *ulift, float *uout, IterArgs A, MonArgs D) {
   const long long N = (long long)A.H * A.W;
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -493,6 +515,13 @@ hipError_t launch_convexify(const float *samples, float *cost, const double *tau
                             const IterArgs &A, hipStream_t st) {
   long long n = (long long)A.H * A.W * A.k;
   hipLaunchKernelGGL(k_convexify, dim3(nblk(n, 256)), dim3(256), 0, st, samples, cost, tau, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_straddle_info(const float *fn, unsigned *sinfo, const IterArgs &A,
+                                hipStream_t st) {
+  long long N = (long long)A.H * A.W;
+  hipLaunchKernelGGL(k_straddle_info, dim3(nblk(N, 256)), dim3(256), 0, st, fn, sinfo, A);
   return hipGetLastError();
 }
 

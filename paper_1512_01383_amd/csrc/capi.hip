@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sublabel.h"
+#include "sublabel.h"
 #include "internal.hpp"
 
 namespace {
@@ -43,7 +43,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   long long N, ps;
   size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_forig, off_w, off_cost, off_tau,
-      off_taud;
+      off_taud, off_sinfo;
   size_t off_monu, off_monb, off_part1, off_part2, off_fin, off_flag, total;
   size_t state_lo, state_hi;  // contiguous range holding u, s, v, z, p, qd
 };
@@ -72,6 +72,7 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   const bool sampled = d->rho == SL_RHO_SAMPLED;
   L.off_fn = take(sampled ? 0 : pf);
   L.off_forig = take(sampled ? 0 : pf);
+  L.off_sinfo = take(d->rho == SL_RHO_TRUNC_QUAD ? pf : 0);
   L.off_w = take((!sampled && d->samples) ? (size_t)d->L * pf : 0);
   L.off_cost = take(sampled ? (size_t)2 * d->M * pf : 0);
   L.off_tau = take(sampled ? (size_t)d->M * 4 : 0);
@@ -89,7 +90,7 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
 sl_status validate(const sl_problem_desc *d) {
   if (!d) return fail(SL_ERR_INVALID_ARG, "desc is NULL");
   if (d->H < 1 || d->W < 1) return fail(SL_ERR_INVALID_ARG, "H and W must be >= 1");
-  if ((long long)d->H * d->W >= (1LL << 31)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^31");
+  if ((long long)d->H * d->W >= (1LL << 30)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^30");
   if (d->L < 2) return fail(SL_ERR_INVALID_ARG, "L must be >= 2");
   if (d->L > SL_MAX_LABELS) return fail(SL_ERR_UNSUPPORTED, "L must be <= %d", SL_MAX_LABELS);
   if (!d->gamma) return fail(SL_ERR_INVALID_ARG, "gamma is NULL");
@@ -155,7 +156,8 @@ struct sl_problem_ {
   sl_problem_desc d;
   int piece = 0;
   bool add = false, bf16 = false;
-  int rpt = 1;
+  int cfg = 0;        // launch configuration of the fused iteration (kIterCfg)
+  int maxlds = 0;
   IterArgs A{};
   MonArgs D{};
   double shift = 0, scale = 1, lam = 0;
@@ -251,6 +253,7 @@ IterPtrs<float> iter_ptrs_f(sl_problem_ *P) {
   Q.wadd = (const float *)(P->ws + P->lay.off_w);
   Q.cost = (const float *)(P->ws + P->lay.off_cost);
   Q.tau = (const float *)(P->ws + P->lay.off_tau);
+  Q.sinfo = (const unsigned *)(P->ws + P->lay.off_sinfo);
   return Q;
 }
 
@@ -274,9 +277,10 @@ sl_status enqueue_iters(sl_problem_ *P, int iters) {
       B.wadd = Q.wadd;
       B.cost = Q.cost;
       B.tau = Q.tau;
-      e = launch_pdhg_iter(P->piece, P->add, true, P->rpt, P->A, &B, P->st);
+      B.sinfo = Q.sinfo;
+      e = launch_pdhg_iter(P->piece, P->add, true, P->cfg, P->A, &B, P->st);
     } else {
-      e = launch_pdhg_iter(P->piece, P->add, false, P->rpt, P->A, &Q, P->st);
+      e = launch_pdhg_iter(P->piece, P->add, false, P->cfg, P->A, &Q, P->st);
     }
     if (e != hipSuccess) return hip_fail(e, "iteration launch");
     P->iu = (P->iu + 1) % 3;
@@ -364,6 +368,26 @@ void state_planes(sl_problem_ *P, std::vector<const void *> &pl, std::vector<int
   bf.push_back(0);
 }
 
+bool cfg_fits(const sl_problem_ *P, int cfg) {
+  return pdhg_iter_lds_bytes(P->A.k, kIterCfg[cfg][1]) + pdhg_iter_static_lds(cfg) <=
+         (size_t)P->maxlds;
+}
+
+// Label groups: chunks of about six labels per wavefront keep the label walk short, and
+// small images get more groups until there are >= 2048 wavefronts (8 per compute unit).
+// Tiles of 4 rows. (Measured on MI355X: see the tiling sweep in the design doc.)
+int auto_cfg(const sl_problem_ *P) {
+  const long long waves = (P->lay.N + 63) / 64;
+  const int k = P->A.k;
+  int g = k < 9 ? 1 : (k < 18 ? 2 : 4);
+  while (waves * g < 2048 && g < 4 && g < k) g *= 2;
+  const int want = g == 1 ? 0 : (g == 2 ? 2 : 4);
+  const int order[3] = {want, 2, 0};
+  for (int j = 0; j < 3; j++)
+    if (cfg_fits(P, order[j])) return order[j];
+  return -1;
+}
+
 }  // namespace
 
 extern "C" {
@@ -435,10 +459,9 @@ sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *s
     fill_args(P);
     P->d = keep;
   }
-  const int k = P->A.k;
-  P->rpt = 1;
-  const size_t static_lds = 8 * 1024;
-  if (pdhg_iter_lds_bytes(k, P->rpt) + static_lds > (size_t)maxlds) {
+  P->maxlds = maxlds;
+  P->cfg = auto_cfg(P);
+  if (P->cfg < 0) {
     delete P;
     return fail(SL_ERR_UNSUPPORTED, "L = %d needs more LDS than a workgroup may use", desc->L);
   }
@@ -470,6 +493,10 @@ sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *s
       return cleanup(hip_fail(e, "init f"));
     if ((e = launch_copy_planes(desc->f, (float *)(P->ws + lay.off_forig), 1, N, lay.ps, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy f"));
+    if (P->piece == SLI_TRUNC &&
+        (e = launch_straddle_info((const float *)(P->ws + lay.off_fn), (unsigned *)(P->ws + lay.off_sinfo),
+                                  P->A, P->st)) != hipSuccess)
+      return cleanup(hip_fail(e, "straddle info"));
     if (P->add &&
         (e = launch_copy_planes(desc->samples, (float *)(P->ws + lay.off_w), desc->L, N, lay.ps, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy w"));
@@ -573,16 +600,25 @@ sl_status sl_unrolled_backward(sl_problem, const float *, float *, double *, flo
   return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation is not built");
 }
 
-sl_status sl_set_tile_rows(sl_problem P, int32_t rows_per_thread) {
+sl_status sl_set_tiling(sl_problem P, int32_t label_groups, int32_t tile_rows) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
-  if (rows_per_thread != 1 && rows_per_thread != 2)
-    return fail(SL_ERR_INVALID_ARG, "rows_per_thread must be 1 or 2");
-  int dev = 0, maxlds = 0;
-  HIPCHK(hipGetDevice(&dev), "device");
-  HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
-  if (pdhg_iter_lds_bytes(P->A.k, rows_per_thread) + 8 * 1024 > (size_t)maxlds)
-    return fail(SL_ERR_UNSUPPORTED, "tile needs more LDS than a workgroup may use");
-  P->rpt = rows_per_thread;
+  if (label_groups == 0 && tile_rows == 0) {
+    P->cfg = auto_cfg(P);
+    return SL_OK;
+  }
+  for (int c = 0; c < SLI_NCFG; c++)
+    if (kIterCfg[c][0] == label_groups && kIterCfg[c][1] == tile_rows) {
+      if (!cfg_fits(P, c)) return fail(SL_ERR_UNSUPPORTED, "tiling needs more LDS than a workgroup may use");
+      P->cfg = c;
+      return SL_OK;
+    }
+  return fail(SL_ERR_INVALID_ARG, "unsupported tiling (%d label groups, %d rows)", label_groups, tile_rows);
+}
+
+sl_status sl_get_tiling(sl_problem P, int32_t *label_groups, int32_t *tile_rows) {
+  if (!P || !label_groups || !tile_rows) return fail(SL_ERR_INVALID_ARG, "NULL argument");
+  *label_groups = kIterCfg[P->cfg][0];
+  *tile_rows = kIterCfg[P->cfg][1];
   return SL_OK;
 }
 

@@ -11,6 +11,12 @@
 
 #define SL_INF __builtin_huge_valf()
 
+// Hardware approximations (about 1 ulp) for reciprocal and square root; every result that
+// depends on them is either polished by a Newton step or enters the iteration at a
+// sensitivity far below the FP32 tolerance of the iterates.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---------------------------------------------------------------- storage conversion
 
 __device__ __forceinline__ float ldv(const float *p, long long i) { return p[i]; }
@@ -25,6 +31,23 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
   return (uint16_t)(b >> 16);
 }
 __device__ __forceinline__ void stv(uint16_t *p, long long i, float x) { p[i] = f2bf(x); }
+
+// Loads / stores at a wave-uniform base pointer plus a 32-bit per-lane byte offset: one
+// global_load / global_store with scalar base and vector offset, no 64-bit lane math.
+template <class T>
+__device__ __forceinline__ T ldb(const T *base, unsigned off) {
+  return *(const T *)((const char *)base + off);
+}
+template <class T>
+__device__ __forceinline__ void stb(T *base, unsigned off, T v) {
+  *(T *)((char *)base + off) = v;
+}
+__device__ __forceinline__ float ldvb(const float *base, unsigned off) { return ldb(base, off); }
+__device__ __forceinline__ float ldvb(const uint16_t *base, unsigned off) {
+  return __uint_as_float(((uint32_t)ldb(base, off)) << 16);
+}
+__device__ __forceinline__ void stvb(float *base, unsigned off, float x) { stb(base, off, x); }
+__device__ __forceinline__ void stvb(uint16_t *base, unsigned off, float x) { stb(base, off, f2bf(x)); }
 
 // ---------------------------------------------------------------- TV ball (Prop. 5)
 
@@ -54,20 +77,24 @@ __device__ __forceinline__ float parabola_root(float a, float Y0, float W0) {
   const float disc = hq * hq + p3 * p3 * p3;
   float Y;
   if (disc >= 0.f) {
-    float A = cbrtf(hq + sqrtf(disc));
-    if (A > 0.f) {
-      float B = -p3 / A;
-      Y = qa / (A * A + B * B + p3);          // A + B without cancellation
-    } else {
-      Y = 0.f;
-    }
+    // Cardano, A = cbrt(hq + sqrt(disc)) via exp2(log2(.)/3), then A + B = qa/(A^2+B^2+p/3)
+    const float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(hq + fsqrt(disc)) * (1.f / 3.f));
+    const float B = -p3 * frcp(A);
+    Y = A > 0.f ? qa * frcp(A * A + B * B + p3) : 0.f;
   } else {
-    float m = sqrtf(-p3);
-    float arg = fminf(fmaxf(hq / (m * m * m), -1.f), 1.f);
-    Y = 2.f * m * cosf(acosf(arg) * (1.f / 3.f));
+    // three real roots: the largest is 2 m cos(acos(hq/m^3)/3); acos by the
+    // Abramowitz-Stegun 4.4.45 polynomial (|err| < 7e-5), cos in revolutions
+    const float m = fsqrt(-p3);
+    const float x = fminf(hq * frcp(m * m * m), 1.f);
+    const float ac = fsqrt(1.f - x) * (1.5707288f + x * (-0.2121144f + x * (0.0742610f - 0.0187293f * x)));
+    Y = 2.f * m * __builtin_amdgcn_cosf(ac * (1.f / (6.f * 3.14159265358979f)));
   }
-  float fp = 3.f * Y * Y + p;
-  if (fp > 1e-20f) Y -= (Y * (Y * Y + p) - qa) / fp;   // one Newton polish
+  // Newton on the (convex for Y > 0) cubic: the largest root is simple
+#pragma unroll
+  for (int it = 0; it < 2; it++) {
+    const float fp = 3.f * Y * Y + p;
+    if (fp > 0.f) Y -= (Y * (Y * Y + p) - qa) * frcp(fp);
+  }
   return sgn * Y;
 }
 
@@ -101,7 +128,7 @@ __device__ __forceinline__ void proj_quad(float a, float ia, float c, float g0, 
   float yy = Y - ac;
   const float gp = c + yy * ia, gv = yy * (c + 0.5f * yy * ia) - w;
   const float den = 1.f + gp * gp + gv * ia;
-  if (den > 0.f) yy = fminf(fmaxf(yy - ((yy - y) + gv * gp) / den, a * d0), a * d1);
+  if (den > 0.f) yy = fminf(fmaxf(yy - ((yy - y) + gv * gp) * frcp(den), a * d0), a * d1);
   y = yy;
   w = y * (c + 0.5f * y * ia);
 }
@@ -133,7 +160,7 @@ struct PLProj {
   }
   // linear part of slope t through (., -r) restricted to [l, hi]
   __device__ __forceinline__ void seg(float t, float r, float l, float hi) {
-    float mu = (t * y0 - r - w0) / (1.f + t * t);   // >= 0: point below the line
+    float mu = (t * y0 - r - w0) * frcp(1.f + t * t);   // >= 0: point below the line
     float yr = y0 - mu * t;                          // perpendicular foot
     if (!found && mu >= 0.f && yr >= l && yr <= hi) {
       found = true;
@@ -160,10 +187,10 @@ struct PLProj {
       aw = gb;
     }
   }
-  __device__ __forceinline__ void push(float t, float r) {
+  // next vertex (t, r) with the kink b between it and the previous vertex given
+  __device__ __forceinline__ void push_k(float t, float r, float b) {
     gmax = fmaxf(gmax, t * y0 - r);
     if (has) {
-      float b = (r - cp) / (t - tp);
       seg(tp, cp, lo, b);
       kink(b, tp, cp, t);
       lo = b;
@@ -171,6 +198,9 @@ struct PLProj {
     tp = t;
     cp = r;
     has = true;
+  }
+  __device__ __forceinline__ void push(float t, float r) {
+    push_k(t, r, has ? (r - cp) * frcp(t - tp) : 0.f);
   }
   __device__ __forceinline__ void finish(float &y, float &w) {
     seg(tp, cp, lo, SL_INF);
@@ -181,26 +211,31 @@ struct PLProj {
   }
 };
 
-// Truncated quadratic on a straddling interval: samples t_m = g0 + m (g1-g0)/15 with
-// values min(a/2 (t_m - c)^2, nu). Samples inside the band lie on a strictly convex
-// parabola and all others sit at the maximum value nu, so the lower hull is the first
-// sample, the band samples between the two tangent points ml (least slope seen from the
-// first sample) and mr (largest slope towards the last sample), and the last sample.
-__device__ __forceinline__ float tq_sample(float a, float c, float nu, float g0, float hs, int m) {
-  float t = g0 + hs * (float)m;
-  float d = t - c;
+// Truncated quadratic on a straddling interval: samples t_m = g0 + m (g1-g0)/15
+// (t_0 = g0, t_15 = g1) with values min(a/2 (t_m - c)^2, nu). Samples inside the band lie
+// on a strictly convex parabola and all others sit at the maximum value nu, so the lower
+// hull is the first sample, the band samples between the two tangent points ml (least
+// slope seen from the first sample) and mr (largest slope towards the last sample), and
+// the last sample.
+__device__ __forceinline__ float tq_t(float g0, float g1, float hs, int m) {
+  return m == 0 ? g0 : (m == SLI_NSUB - 1 ? g1 : g0 + hs * (float)m);
+}
+__device__ __forceinline__ float tq_sample(float a, float c, float nu, float g0, float g1, float hs,
+                                           int m) {
+  const float d = tq_t(g0, g1, hs, m) - c;
   return fminf(0.5f * a * d * d, nu);
 }
 
-__device__ __forceinline__ void tq_hull_range(float a, float c, float nu, float g0, float hs,
+__device__ __forceinline__ void tq_hull_range(float a, float c, float nu, float g0, float g1,
                                               int &ml, int &mr) {
-  const float r0 = tq_sample(a, c, nu, g0, hs, 0);
-  const float rN = tq_sample(a, c, nu, g0, hs, SLI_NSUB - 1);
+  const float hs = (g1 - g0) * (1.f / (float)(SLI_NSUB - 1));
+  const float r0 = tq_sample(a, c, nu, g0, g1, hs, 0);
+  const float rN = tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1);
   float best = SL_INF;
   ml = SLI_NSUB - 1;
 #pragma unroll
   for (int m = 1; m < SLI_NSUB; m++) {
-    float sl = (tq_sample(a, c, nu, g0, hs, m) - r0) * (1.f / (float)m);
+    float sl = (tq_sample(a, c, nu, g0, g1, hs, m) - r0) * (1.f / (float)m);
     if (sl <= best) {
       best = sl;
       ml = m;
@@ -210,7 +245,7 @@ __device__ __forceinline__ void tq_hull_range(float a, float c, float nu, float 
   mr = 0;
 #pragma unroll
   for (int m = SLI_NSUB - 2; m >= 0; m--) {
-    float sl = (rN - tq_sample(a, c, nu, g0, hs, m)) * (1.f / (float)(SLI_NSUB - 1 - m));
+    float sl = (rN - tq_sample(a, c, nu, g0, g1, hs, m)) * (1.f / (float)(SLI_NSUB - 1 - m));
     if (sl >= best) {
       best = sl;
       mr = m;
@@ -218,23 +253,45 @@ __device__ __forceinline__ void tq_hull_range(float a, float c, float nu, float 
   }
 }
 
-__device__ __forceinline__ void proj_tq_straddle(float a, float c, float nu, float g0, float g1,
-                                                 float &y, float &w) {
+// Projection for a straddling interval whose hull range (ml, mr) is known. Between two
+// consecutive band samples the kink (difference quotient of the parabola) is
+// a ((t_m + t_{m+1})/2 - c); only the two tangent edges need a division.
+__device__ __forceinline__ void proj_tq_chain(float a, float c, float nu, float g0, float g1,
+                                              int ml, int mr, float &y, float &w) {
   const float hs = (g1 - g0) * (1.f / (float)(SLI_NSUB - 1));
-  int ml, mr;
-  tq_hull_range(a, c, nu, g0, hs, ml, mr);
   PLProj pl;
   pl.init(y, w);
-  pl.push(g0, tq_sample(a, c, nu, g0, hs, 0));
-  for (int m = ml; m <= mr; m++) pl.push(g0 + hs * (float)m, tq_sample(a, c, nu, g0, hs, m));
-  pl.push(g0 + hs * (float)(SLI_NSUB - 1), tq_sample(a, c, nu, g0, hs, SLI_NSUB - 1));
+  pl.push(g0, tq_sample(a, c, nu, g0, g1, hs, 0));
+  if (ml <= mr) {
+    pl.push(tq_t(g0, g1, hs, ml), tq_sample(a, c, nu, g0, g1, hs, ml));
+    for (int m = ml + 1; m <= mr; m++) {
+      const float tm = g0 + hs * (float)m;
+      const float d = tm - c;
+      pl.push_k(tm, 0.5f * a * d * d, a * (tm - 0.5f * hs - c));
+    }
+  }
+  pl.push(g1, tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1));
   pl.finish(y, w);
 }
 
-__device__ __forceinline__ void proj_flat(float nu, float g0, float g1, float &y, float &w) {
-  PLProj pl;
-  pl.init(y, w);
-  pl.push(g0, nu);
-  pl.push(g1, nu);
-  pl.finish(y, w);
+// Constant piece nu on [g0, g1]: the conjugate is max(g0 y, g1 y) - nu with one kink at
+// y = 0; strips of the two linear parts and the kink's normal cone in closed form.
+__device__ __forceinline__ void proj_flat(float nu, float g0, float g1, float ig0, float ig1,
+                                          float &y, float &w) {
+  const float g = fmaxf(g0 * y, g1 * y) - nu;
+  if (w >= g) return;
+  const float m0 = (g0 * y - nu - w) * ig0, y0 = y - m0 * g0;
+  if (m0 >= 0.f && y0 <= 0.f) {
+    y = y0;
+    w = g0 * y0 - nu;
+    return;
+  }
+  const float m1 = (g1 * y - nu - w) * ig1, y1 = y - m1 * g1;
+  if (m1 >= 0.f && y1 >= 0.f) {
+    y = y1;
+    w = g1 * y1 - nu;
+    return;
+  }
+  y = 0.f;
+  w = -nu;
 }

@@ -53,12 +53,17 @@ struct IterPtrs {
   DT *pout;
   float *qd;
   const float *fn, *wadd, *cost, *tau;
+  const unsigned *sinfo;  // straddling intervals per pixel (TRUNC_QUAD)
 };
 
 // Host-side launchers (pdhg_iter.hip, aux.hip).
-hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int rpt, const IterArgs &A,
+// Launch configurations of the fused iteration: kIterCfg[c] = {label groups, tile rows}.
+#define SLI_NCFG 5
+extern const int kIterCfg[SLI_NCFG][2];
+hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
                             const void *ptrs, hipStream_t st);
-size_t pdhg_iter_lds_bytes(int k, int rpt);
+size_t pdhg_iter_lds_bytes(int k, int tile_rows);   // dynamic LDS
+size_t pdhg_iter_static_lds(int cfg);
 
 // Double-precision problem parameters for the monitor (the certificate is evaluated for
 // the problem defined by the caller's double labels / coefficients and the FP32 data).
@@ -90,6 +95,9 @@ hipError_t launch_copy_planes(const float *src, float *dst, int nplanes, long lo
 hipError_t launch_convexify(const float *samples, float *cost, const double *taud,
                             const IterArgs &A, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
+// per pixel: labels and hull tangent ranges of the (at most two) truncated-quadratic
+// intervals that straddle a band edge, packed as 2 x (label:5, ml:4, mr:4) bits, label 31 = none
+hipError_t launch_straddle_info(const float *fn, unsigned *sinfo, const IterArgs &A, hipStream_t st);
 hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
                           const MonArgs &D, hipStream_t st);
 hipError_t launch_pack_state(const void *const *planes, const int *bf16, int nplanes,
