@@ -13,6 +13,7 @@ sample of the same workload (baseline, not the target).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 50
+KERNEL_SOURCES = ("paper_1512_01383_amd/csrc/pdhg_iter.hip", "paper_1512_01383_amd/csrc/device_math.hpp",
+                  "paper_1512_01383_amd/csrc/internal.hpp")
+
+
+def kernel_hash() -> str:
+    """Hash of the sources of the fused iteration kernel (ties counter data to a kernel)."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per launch from the committed counter profile of this workload, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"pdhg_iter_{workload_key}_traffic.json")
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+    except OSError:
+        return None
+    if prof.get("kernel_hash") != kernel_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
 
 
 def algorithmic_bytes_per_pixel(k: int, rho: int, M: int, bf16: bool, add: bool) -> int:
@@ -43,10 +69,12 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--kernel-iters", type=int, default=500)
-    ap.add_argument("--gap-max-iters", type=int, default=200000)
+    ap.add_argument("--gap-max-iters", type=int, default=60000)
     ap.add_argument("--no-gap", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,6 +122,14 @@ def main():
     bpp = algorithmic_bytes_per_pixel(k, wl.rho, wl.M, args.storage == "bf16", False)
     bytes_per_launch = bpp * N
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # time to a 1e-3 certified relative gap from a fresh start
     gap = None
@@ -146,9 +182,11 @@ def main():
                                f"iterations + FP64 gap monitor",
                    "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}"),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "kernel_hash": kernel_hash(), "tiling": list(g.get_tiling())},
         "cpu_baseline": cpu,
         "time_to_gap_1e-3": gap,
     }
