@@ -151,11 +151,38 @@ sl_status sl_state_size(sl_problem p, size_t *bytes);
 sl_status sl_save_state(sl_problem p, void *dev_dst, size_t bytes);
 sl_status sl_load_state(sl_problem p, const void *dev_src, size_t bytes);
 
-/* Batched solve: n independent problems share one workspace and are advanced together
- * by one persistent launch per iteration over a work list of (instance, tile).
- * Returns SL_ERR_UNSUPPORTED in this build. */
+/* Batched solve (many independent problems of uneven size and label count). All n
+ * problems share the data-term kind, the storage and whether additive values are given;
+ * each keeps its own labels, lambda, coefficients and image size. One persistent launch
+ * per iteration advances every active problem: its blocks pull (problem, tile) work items
+ * from a device counter, costliest problems first, and read each problem's parameters and
+ * buffers from device tables. Runs of 6 iterations (one period of the buffer rotation)
+ * are captured once in a hipGraph and replayed. sl_run and sl_run_to_gap accept the
+ * batch handle; sl_run_to_gap checks every problem each check interval (rounded up to a
+ * multiple of 6) and drops problems that reached the gap from the work list (their state
+ * is kept). The workspace holds every problem's workspace plus the work tables.
+ * sl_energy / sl_read_u / sl_save_state on a batch handle return SL_ERR_INVALID_ARG /
+ * SL_ERR_UNSUPPORTED: use the sl_batch_* calls. Each problem's iterates are bitwise those
+ * of the same problem solved alone with the same tiling. */
+sl_status sl_batch_workspace_size(const sl_problem_desc *descs, int32_t n, size_t *bytes);
 sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *dev_workspace,
                           size_t bytes, void *hip_stream, sl_problem *out);
+sl_status sl_batch_energy(sl_problem p, int32_t i, sl_report *out);  /* syncs; as sl_energy */
+sl_status sl_batch_read_u(sl_problem p, int32_t i, float *u_lifted_dev, float *u_dev);
+/* iterations run by problem i and whether it is still iterating (may be NULL) */
+sl_status sl_batch_info(sl_problem p, int32_t i, int64_t *iters, int32_t *active);
+
+/* Graph replay of batched iterations on (default) or off; results are identical. */
+sl_status sl_set_graphs(sl_problem p, int32_t enable);
+
+/* Tile-shape autotuner: times `iters` iterations with every tiling that fits, keeps the
+ * fastest, then resets the iteration state to its initial value (call it before
+ * iterating). With a cache file (may be NULL) a tiling measured before for the same
+ * device, kernel variant, label count and size bucket (power of two of the pixel count) is
+ * reused without timing, and new measurements are appended as lines "key|tiling". The
+ * chosen (label_groups, tile_rows) are returned (pointers may be NULL). Synchronises. */
+sl_status sl_autotune(sl_problem p, int32_t iters, const char *cache_path, int32_t *label_groups,
+                      int32_t *tile_rows);
 
 /* Unrolled differentiation: K iterations with checkpoints every C iterations, then the
  * adjoint pass. Return SL_ERR_UNSUPPORTED in this build. */

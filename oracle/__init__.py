@@ -209,9 +209,12 @@ class Problem:
         self.N = wl.H * wl.W
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().or_destroy(self.h)
+                self.h = None
+        except Exception:   # interpreter shutdown: module globals already cleared
+            pass
 
     def run(self, iters: int):
         lib().or_run(self.h, int(iters))

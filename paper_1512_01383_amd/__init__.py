@@ -85,11 +85,20 @@ def lib():
         L.sl_load_state.argtypes = [vp, vp, sz]
         L.sl_set_tiling.argtypes = [vp, C.c_int32, C.c_int32]
         L.sl_get_tiling.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sl_batch_workspace_size.argtypes = [C.POINTER(Desc), C.c_int32, C.POINTER(sz)]
+        L.sl_batch_create.argtypes = [C.POINTER(Desc), C.c_int32, vp, sz, vp, C.POINTER(vp)]
+        L.sl_batch_energy.argtypes = [vp, C.c_int32, C.POINTER(Report)]
+        L.sl_batch_read_u.argtypes = [vp, C.c_int32, vp, vp]
+        L.sl_batch_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.sl_set_graphs.argtypes = [vp, C.c_int32]
+        L.sl_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.sl_destroy.argtypes = [vp]
         L.sl_destroy.restype = None
         for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
                      "sl_energy", "sl_state_size", "sl_save_state", "sl_load_state",
-                     "sl_set_tiling", "sl_get_tiling"):
+                     "sl_set_tiling", "sl_get_tiling", "sl_batch_workspace_size", "sl_batch_create",
+                     "sl_batch_energy", "sl_batch_read_u", "sl_batch_info", "sl_set_graphs",
+                     "sl_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -112,6 +121,40 @@ def _dev_f32(a, device):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
 
 
+def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
+               check_every, device):
+    """Fill a Desc; device copies of the inputs are kept on ``obj._keep``."""
+    obj.H, obj.W = int(H), int(W)
+    obj.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    obj.k = len(obj.gamma) - 1
+    d = Desc()
+    d.H, d.W, d.L = obj.H, obj.W, len(obj.gamma)
+    d.gamma = obj.gamma.ctypes.data_as(C.POINTER(C.c_double))
+    d.rho = int(rho)
+    if f is not None:
+        obj._keep["f"] = _dev_f32(f, device).reshape(-1)
+        d.f = obj._keep["f"].data_ptr()
+    d.a, d.nu = float(a), float(nu)
+    if tau is not None:
+        obj.tau = np.ascontiguousarray(tau, dtype=np.float64)
+        obj._keep["samples"] = _dev_f32(samples, device).reshape(-1)
+        d.M = len(obj.tau)
+        d.tau = obj.tau.ctypes.data_as(C.POINTER(C.c_double))
+        d.samples = obj._keep["samples"].data_ptr()
+    d.lam = float(lam)
+    d.tv = TV_ISO
+    d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
+    d.check_every = int(check_every)
+    d.normalize_labels = 1 if normalize else 0
+    d.adaptive_steps = 0
+    return d
+
+
+class _Inst:
+    def __init__(self):
+        self._keep = {}
+
+
 class Problem:
     """One lifted problem on one GPU. Inputs may be numpy arrays or torch tensors."""
 
@@ -121,30 +164,9 @@ class Problem:
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()
-        self.H, self.W = int(H), int(W)
-        self.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
-        self.k = len(self.gamma) - 1
         self._keep = {}
-        d = Desc()
-        d.H, d.W, d.L = self.H, self.W, len(self.gamma)
-        d.gamma = self.gamma.ctypes.data_as(C.POINTER(C.c_double))
-        d.rho = int(rho)
-        if f is not None:
-            self._keep["f"] = _dev_f32(f, self.device).reshape(-1)
-            d.f = self._keep["f"].data_ptr()
-        d.a, d.nu = float(a), float(nu)
-        if tau is not None:
-            self.tau = np.ascontiguousarray(tau, dtype=np.float64)
-            self._keep["samples"] = _dev_f32(samples, self.device).reshape(-1)
-            d.M = len(self.tau)
-            d.tau = self.tau.ctypes.data_as(C.POINTER(C.c_double))
-            d.samples = self._keep["samples"].data_ptr()
-        d.lam = float(lam)
-        d.tv = TV_ISO
-        d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
-        d.check_every = int(check_every)
-        d.normalize_labels = 1 if normalize else 0
-        d.adaptive_steps = 0
+        d = _make_desc(self, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
+                       check_every, self.device)
         self.desc = d
         nbytes = C.c_size_t()
         _check(L_.sl_workspace_size(C.byref(d), C.byref(nbytes)))
@@ -199,6 +221,13 @@ class Problem:
         _check(lib().sl_load_state(self.h, C.c_void_p(t.data_ptr()), t.numel() * 4))
         self.stream.synchronize()
 
+    def autotune(self, iters: int = 20, cache: Optional[str] = None):
+        """Pick the fastest tiling (resets the iteration state); returns (groups, rows)."""
+        g, t = C.c_int32(), C.c_int32()
+        _check(lib().sl_autotune(self.h, int(iters), cache.encode() if cache else None,
+                                 C.byref(g), C.byref(t)))
+        return g.value, t.value
+
     def set_tiling(self, label_groups: int, tile_rows: int):
         """(0, 0) restores the automatic choice."""
         _check(lib().sl_set_tiling(self.h, int(label_groups), int(tile_rows)))
@@ -218,6 +247,59 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class BatchProblem(Problem):
+    """Many independent problems advanced together by one persistent launch per
+    iteration (sl_batch_create). ``instances`` are ``workloads.Workload``-like objects."""
+
+    def __init__(self, instances, storage: str = "fp32", normalize: bool = True,
+                 check_every: int = 48, device=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda:0")
+        L_ = lib()
+        self._insts = []
+        descs = (Desc * len(instances))()
+        for j, wl in enumerate(instances):
+            it = _Inst()
+            descs[j] = _make_desc(it, wl.H, wl.W, wl.gamma, wl.rho, wl.lam, wl.f, wl.a, wl.nu,
+                                  wl.tau, wl.samples, storage, normalize, check_every,
+                                  self.device)
+            self._insts.append(it)
+        self.n = len(instances)
+        nbytes = C.c_size_t()
+        _check(L_.sl_batch_workspace_size(descs, self.n, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        _check(L_.sl_batch_create(descs, self.n, C.c_void_p(self.workspace.data_ptr()),
+                                  nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        for it in self._insts:
+            it._keep = None
+
+    def energy_of(self, i: int) -> dict:
+        r = Report()
+        _check(lib().sl_batch_energy(self.h, int(i), C.byref(r)))
+        return r.as_dict()
+
+    def read_u_of(self, i: int):
+        torch = _torch()
+        it = self._insts[i]
+        ul = torch.empty((it.k, it.H, it.W), dtype=torch.float32, device=self.device)
+        u = torch.empty((it.H, it.W), dtype=torch.float32, device=self.device)
+        _check(lib().sl_batch_read_u(self.h, int(i), C.c_void_p(ul.data_ptr()),
+                                     C.c_void_p(u.data_ptr())))
+        return ul, u
+
+    def info_of(self, i: int):
+        n, a = C.c_int64(), C.c_int32()
+        _check(lib().sl_batch_info(self.h, int(i), C.byref(n), C.byref(a)))
+        return n.value, bool(a.value)
+
+    def set_graphs(self, enable: bool):
+        _check(lib().sl_set_graphs(self.h, 1 if enable else 0))
 
 
 STATE_ORDER = ("u", "u_prev", "s", "s_prev", "v", "z", "px", "py", "qd")

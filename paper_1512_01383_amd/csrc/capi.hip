@@ -174,6 +174,33 @@ struct sl_problem_ {
   std::vector<double> taud_host;
   double fin[SLI_NMON];
 
+  // batch handles: sub-problems advance together in one persistent launch per iteration
+  bool is_batch = false;
+  std::vector<sl_problem_ *> sub;
+  std::vector<char> active;
+  std::vector<BatchItem> items_host;
+  std::vector<int> kcount_host;
+  BatchItem *items_dev = nullptr;
+  int *count_dev = nullptr, *counter_dev = nullptr;
+  void *ptrs_dev = nullptr;
+  IterArgs *args_dev = nullptr;
+  std::vector<char> ptrs_host;
+  std::vector<IterArgs> args_host;
+  int kmax = 0;
+  int64_t biters = 0;       // batch iterations since creation (rotation phase = biters % 6)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_cfg = -1;
+  bool use_graph = true;
+
+  ~sl_problem_() {
+    for (sl_problem_ *q : sub) delete q;
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+
   float *ubuf(int j) { return (float *)(ws + lay.off_u) + (size_t)j * A.k * lay.ps; }
   float *sbuf(int j) { return (float *)(ws + lay.off_s) + (size_t)j * A.k * lay.ps; }
   size_t esz() const { return bf16 ? 2 : 4; }
@@ -368,17 +395,176 @@ void state_planes(sl_problem_ *P, std::vector<const void *> &pl, std::vector<int
   bf.push_back(0);
 }
 
+
+// ------------------------------------------------------------------------ batches and tuning
+
+void set_rotation(sl_problem_ *P, int64_t n) {
+  P->iu = (int)(n % 3);
+  P->is = (int)(n % 2);
+  P->ip = (int)(n % 2);
+}
+
+sl_status reset_state(sl_problem_ *P) {
+  if (P->is_batch) {
+    for (sl_problem_ *q : P->sub) {
+      sl_status s = reset_state(q);
+      if (s != SL_OK) return s;
+    }
+    P->biters = 0;
+    std::fill(P->active.begin(), P->active.end(), 1);
+    return SL_OK;
+  }
+  HIPCHK(launch_fill_zero(P->ws + P->lay.state_lo, P->lay.state_hi - P->lay.state_lo, P->st), "reset");
+  P->iters = 0;
+  P->have_best = false;
+  set_rotation(P, 0);
+  return SL_OK;
+}
+
+int batch_tiles(const sl_problem_ *q, int th) {
+  return ((q->A.H + th - 1) / th) * ((q->A.W + 63) / 64);
+}
+
+size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
+  size_t items = 0;
+  for (int t : maxtiles) items += (size_t)t;
+  return align256(items * sizeof(BatchItem)) + 256 + align256((size_t)n * 6 * sizeof(IterPtrs<float>)) +
+         align256((size_t)n * sizeof(IterArgs));
+}
+
+// work list of the active instances, costliest (k x tiles) first, tiles in row-major order
+sl_status batch_rebuild_items(sl_problem_ *P) {
+  const int th = kIterCfg[P->cfg][1];
+  std::vector<int> order;
+  for (int i = 0; i < (int)P->sub.size(); i++)
+    if (P->active[i]) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long long)P->sub[a]->A.k * batch_tiles(P->sub[a], th) >
+           (long long)P->sub[b]->A.k * batch_tiles(P->sub[b], th);
+  });
+  P->items_host.clear();
+  for (int i : order)
+    for (int t = 0; t < batch_tiles(P->sub[i], th); t++) P->items_host.push_back({i, t});
+  P->kcount_host.assign(1, (int)P->items_host.size());
+  if (!P->items_host.empty())
+    HIPCHK(hipMemcpyAsync(P->items_dev, P->items_host.data(), P->items_host.size() * sizeof(BatchItem),
+                          hipMemcpyHostToDevice, P->st), "work list");
+  HIPCHK(hipMemcpyAsync(P->count_dev, P->kcount_host.data(), sizeof(int), hipMemcpyHostToDevice, P->st),
+         "work count");
+  HIPCHK(hipStreamSynchronize(P->st), "work list sync");
+  return SL_OK;
+}
+
+BatchLaunch batch_launch(sl_problem_ *P, int phase) {
+  BatchLaunch L;
+  L.items = P->items_dev;
+  L.count = P->count_dev;
+  L.counter = P->counter_dev;
+  L.ptrs = P->ptrs_dev;
+  L.args = P->args_dev;
+  L.phase = phase;
+  L.kmax = P->kmax;
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, P->bf16, P->cfg, P->kmax));
+  long long total = 0;
+  for (size_t i = 0; i < P->sub.size(); i++) total += batch_tiles(P->sub[i], kIterCfg[P->cfg][1]);
+  L.grid = (int)std::max(1LL, std::min((long long)occ * ncu, total));
+  return L;
+}
+
+sl_status batch_capture(sl_problem_ *P) {
+  if (P->gexec && P->graph_cfg == P->cfg) return SL_OK;
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+  if (!P->cap) HIPCHK(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "capture stream");
+  HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+  hipError_t e = hipSuccess;
+  for (int ph = 0; ph < 6 && e == hipSuccess; ph++)
+    e = launch_pdhg_batch(P->piece, P->add, P->bf16, P->cfg, batch_launch(P, ph), P->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(P->cap, &g);
+  if (e != hipSuccess) return hip_fail(e, "captured launch");
+  if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+  P->graph = g;
+  HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0), "graph instantiate");
+  P->graph_cfg = P->cfg;
+  return SL_OK;
+}
+
+sl_status batch_enqueue(sl_problem_ *P, int iters) {
+  while (iters > 0) {
+    const int ph = (int)(P->biters % 6);
+    if (P->use_graph && ph == 0 && iters >= 6) {
+      sl_status s = batch_capture(P);
+      if (s != SL_OK) return s;
+      HIPCHK(hipGraphLaunch(P->gexec, P->st), "graph launch");
+      P->biters += 6;
+      iters -= 6;
+    } else {
+      HIPCHK(launch_pdhg_batch(P->piece, P->add, P->bf16, P->cfg, batch_launch(P, ph), P->st),
+             "batch launch");
+      P->biters += 1;
+      iters -= 1;
+    }
+  }
+  for (size_t i = 0; i < P->sub.size(); i++)
+    if (P->active[i]) {
+      set_rotation(P->sub[i], P->biters);
+      P->sub[i]->iters = P->biters;
+    }
+  return SL_OK;
+}
+
+sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
+  const int chunk = std::max(6, (P->check_every + 5) / 6 * 6);
+  int32_t n = 0;
+  while (n < max_iters) {
+    bool any = false;
+    for (char a : P->active) any |= a != 0;
+    if (!any) break;
+    const int c = std::min(chunk, max_iters - n);
+    sl_status s = batch_enqueue(P, c);
+    if (s != SL_OK) return s;
+    n += c;
+    bool changed = false;
+    for (size_t i = 0; i < P->sub.size(); i++) {
+      if (!P->active[i]) continue;
+      sl_report r;
+      if ((s = monitor(P->sub[i], &r)) != SL_OK) {
+        if (done) *done = n;
+        return s;
+      }
+      if (r.rel_gap <= tol) {
+        P->active[i] = 0;
+        changed = true;
+      }
+    }
+    if (changed && (s = batch_rebuild_items(P)) != SL_OK) return s;
+  }
+  if (done) *done = n;
+  return SL_OK;
+}
+
 bool cfg_fits(const sl_problem_ *P, int cfg) {
-  return pdhg_iter_lds_bytes(P->A.k, kIterCfg[cfg][1]) + pdhg_iter_static_lds(cfg) <=
-         (size_t)P->maxlds;
+  const int k = P->is_batch ? P->kmax : P->A.k;
+  return pdhg_iter_lds_bytes(k, kIterCfg[cfg][1]) + pdhg_iter_static_lds(cfg) <= (size_t)P->maxlds;
 }
 
 // Label groups: chunks of about six labels per wavefront keep the label walk short, and
 // small images get more groups until there are >= 2048 wavefronts (8 per compute unit).
 // Tiles of 4 rows. (Measured on MI355X: see the tiling sweep in the design doc.)
 int auto_cfg(const sl_problem_ *P) {
-  const long long waves = (P->lay.N + 63) / 64;
-  const int k = P->A.k;
+  long long waves = (P->lay.N + 63) / 64;
+  int k = P->A.k;
+  if (P->is_batch) {
+    waves = 0;
+    for (const sl_problem_ *q : P->sub) waves += (q->lay.N + 63) / 64;
+    k = P->kmax;
+  }
   int g = k < 9 ? 1 : (k < 18 ? 2 : 4);
   while (waves * g < 2048 && g < 4 && g < k) g *= 2;
   const int want = g == 1 ? 0 : (g == 2 ? 2 : 4);
@@ -417,9 +603,8 @@ sl_status sl_workspace_size(const sl_problem_desc *desc, size_t *bytes) {
   return SL_OK;
 }
 
-sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
-                    sl_problem *out) {
-  if (!out) return fail(SL_ERR_INVALID_ARG, "out is NULL");
+static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
+                             sl_problem *out) {
   *out = nullptr;
   sl_status s = validate(desc);
   if (s != SL_OK) return s;
@@ -519,15 +704,23 @@ sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *s
   return SL_OK;
 }
 
+sl_status sl_create(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
+                    sl_problem *out) {
+  if (!out) return fail(SL_ERR_INVALID_ARG, "out is NULL");
+  return create_impl(desc, ws, bytes, stream, out);
+}
+
 sl_status sl_run(sl_problem P, int32_t iters) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (iters < 0) return fail(SL_ERR_INVALID_ARG, "iters must be >= 0");
+  if (P->is_batch) return batch_enqueue(P, iters);
   return enqueue_iters(P, iters);
 }
 
 sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t *done) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (max_iters < 0 || !(rel_gap >= 0.0)) return fail(SL_ERR_INVALID_ARG, "bad rel_gap / max_iters");
+  if (P->is_batch) return batch_run_to_gap(P, rel_gap, max_iters, done);
   int32_t n = 0;
   sl_report r;
   while (n < max_iters) {
@@ -547,6 +740,7 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
 
 sl_status sl_read_u(sl_problem P, float *ulift, float *u) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (P->is_batch) return fail(SL_ERR_INVALID_ARG, "batch handle: use sl_batch_read_u");
   if (!ulift && !u) return SL_OK;
   HIPCHK(launch_readout(P->ubuf(P->iu), ulift, u, P->A, P->D, P->st), "readout");
   return SL_OK;
@@ -554,17 +748,20 @@ sl_status sl_read_u(sl_problem P, float *ulift, float *u) {
 
 sl_status sl_energy(sl_problem P, sl_report *out) {
   if (!P || !out) return fail(SL_ERR_INVALID_ARG, "handle or out is NULL");
+  if (P->is_batch) return fail(SL_ERR_INVALID_ARG, "batch handle: use sl_batch_energy");
   return monitor(P, out);
 }
 
 sl_status sl_state_size(sl_problem P, size_t *bytes) {
   if (!P || !bytes) return fail(SL_ERR_INVALID_ARG, "handle or bytes is NULL");
+  if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "state save / load of a batch is not built");
   *bytes = (size_t)(8 * P->A.k + 1) * P->lay.N * 4;
   return SL_OK;
 }
 
 static sl_status pack(sl_problem P, void *buf, size_t bytes, int unpack) {
   if (!P || !buf) return fail(SL_ERR_INVALID_ARG, "handle or buffer is NULL");
+  if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "state save / load of a batch is not built");
   size_t need = (size_t)(8 * P->A.k + 1) * P->lay.N * 4;
   if (bytes < need) return fail(SL_ERR_INVALID_ARG, "state buffer of %zu bytes < %zu", bytes, need);
   std::vector<const void *> pl;
@@ -587,9 +784,215 @@ sl_status sl_load_state(sl_problem P, const void *src, size_t bytes) {
   return s;
 }
 
-sl_status sl_batch_create(const sl_problem_desc *, int32_t, void *, size_t, void *, sl_problem *out) {
-  if (out) *out = nullptr;
-  return fail(SL_ERR_UNSUPPORTED, "batched solve is not built");
+sl_status sl_batch_workspace_size(const sl_problem_desc *descs, int32_t n, size_t *bytes) {
+  if (!descs || n < 1 || !bytes) return fail(SL_ERR_INVALID_ARG, "need descs, n >= 1 and bytes");
+  size_t total = 0;
+  std::vector<int> maxtiles;
+  for (int i = 0; i < n; i++) {
+    sl_status s = validate(&descs[i]);
+    if (s != SL_OK) return fail(s, "instance %d: %s", i, g_err.c_str());
+    IterArgs A{};
+    A.H = descs[i].H;
+    A.W = descs[i].W;
+    total += align256(make_layout(&descs[i], monitor_blocks(A)).total);
+    maxtiles.push_back(((descs[i].H + 3) / 4) * ((descs[i].W + 63) / 64));
+  }
+  *bytes = total + batch_table_bytes(maxtiles, n);
+  return SL_OK;
+}
+
+sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, size_t bytes,
+                          void *stream, sl_problem *out) {
+  if (!out) return fail(SL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  sl_status s = sl_batch_workspace_size(descs, n, &need);
+  if (s != SL_OK) return s;
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (bytes < need) return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, need);
+  for (int i = 1; i < n; i++)
+    if (descs[i].rho != descs[0].rho || descs[i].storage != descs[0].storage ||
+        (descs[i].samples != nullptr) != (descs[0].samples != nullptr))
+      return fail(SL_ERR_INVALID_ARG, "instance %d: a batch shares one data-term kind, storage and "
+                  "additive-term setting", i);
+  sl_problem_ *B = new sl_problem_();
+  B->is_batch = true;
+  B->d = descs[0];
+  B->st = (hipStream_t)stream;
+  B->bf16 = descs[0].storage == SL_STORE_BF16_DUAL;
+  B->piece = descs[0].rho == SL_RHO_QUAD ? SLI_QUAD : descs[0].rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : SLI_SAMPLED;
+  B->add = descs[0].rho != SL_RHO_SAMPLED && descs[0].samples != nullptr;
+  B->check_every = descs[0].check_every > 0 ? descs[0].check_every : 48;
+  char *base = (char *)ws;
+  size_t off = 0;
+  std::vector<int> maxtiles;
+  for (int i = 0; i < n; i++) {
+    IterArgs A{};
+    A.H = descs[i].H;
+    A.W = descs[i].W;
+    const size_t sz = align256(make_layout(&descs[i], monitor_blocks(A)).total);
+    sl_problem q = nullptr;
+    s = create_impl(&descs[i], base + off, sz, stream, &q);
+    if (s != SL_OK) {
+      delete B;
+      return fail(s, "instance %d: %s", i, g_err.c_str());
+    }
+    B->sub.push_back(q);
+    B->kmax = std::max(B->kmax, q->A.k);
+    maxtiles.push_back(((descs[i].H + 3) / 4) * ((descs[i].W + 63) / 64));
+    off += sz;
+  }
+  B->maxlds = B->sub[0]->maxlds;
+  B->active.assign(n, 1);
+  // device tables
+  size_t items_bytes = 0;
+  for (int t : maxtiles) items_bytes += (size_t)t * sizeof(BatchItem);
+  B->ws = base + off;
+  B->items_dev = (BatchItem *)(base + off);
+  off += align256(items_bytes);
+  B->count_dev = (int *)(base + off);
+  B->counter_dev = (int *)(base + off + 128);
+  off += 256;
+  B->ptrs_dev = base + off;
+  off += align256((size_t)n * 6 * sizeof(IterPtrs<float>));
+  B->args_dev = (IterArgs *)(base + off);
+  B->ptrs_host.resize((size_t)n * 6 * sizeof(IterPtrs<float>));
+  B->args_host.resize(n);
+  for (int i = 0; i < n; i++) {
+    sl_problem_ *q = B->sub[i];
+    for (int ph = 0; ph < 6; ph++) {
+      set_rotation(q, ph);
+      IterPtrs<float> Q = iter_ptrs_f(q);   // same layout as the bf16 variant (pointers only)
+      memcpy(&B->ptrs_host[((size_t)i * 6 + ph) * sizeof(IterPtrs<float>)], &Q, sizeof(Q));
+    }
+    set_rotation(q, 0);
+    B->args_host[i] = q->A;
+  }
+  static_assert(sizeof(IterPtrs<float>) == sizeof(IterPtrs<uint16_t>), "pointer sets");
+  hipError_t e;
+  if ((e = hipMemcpyAsync(B->ptrs_dev, B->ptrs_host.data(), B->ptrs_host.size(), hipMemcpyHostToDevice, B->st)) != hipSuccess ||
+      (e = hipMemcpyAsync(B->args_dev, B->args_host.data(), n * sizeof(IterArgs), hipMemcpyHostToDevice, B->st)) != hipSuccess) {
+    delete B;
+    return hip_fail(e, "batch tables");
+  }
+  B->cfg = auto_cfg(B);
+  if (B->cfg < 0) {
+    delete B;
+    return fail(SL_ERR_UNSUPPORTED, "labels need more LDS than a workgroup may use");
+  }
+  if ((s = batch_rebuild_items(B)) != SL_OK) {
+    delete B;
+    return s;
+  }
+  *out = B;
+  return SL_OK;
+}
+
+sl_status sl_batch_energy(sl_problem P, int32_t i, sl_report *out) {
+  if (!P || !P->is_batch || !out || i < 0 || i >= (int)P->sub.size())
+    return fail(SL_ERR_INVALID_ARG, "need a batch handle, 0 <= i < n and out");
+  return monitor(P->sub[i], out);
+}
+
+sl_status sl_batch_read_u(sl_problem P, int32_t i, float *ulift, float *u) {
+  if (!P || !P->is_batch || i < 0 || i >= (int)P->sub.size())
+    return fail(SL_ERR_INVALID_ARG, "need a batch handle and 0 <= i < n");
+  return sl_read_u(P->sub[i], ulift, u);
+}
+
+sl_status sl_batch_info(sl_problem P, int32_t i, int64_t *iters, int32_t *active) {
+  if (!P || !P->is_batch || i < 0 || i >= (int)P->sub.size())
+    return fail(SL_ERR_INVALID_ARG, "need a batch handle and 0 <= i < n");
+  if (iters) *iters = P->sub[i]->iters;
+  if (active) *active = P->active[i];
+  return SL_OK;
+}
+
+sl_status sl_set_graphs(sl_problem P, int32_t enable) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  P->use_graph = enable != 0;
+  return SL_OK;
+}
+
+// Time `iters` iterations with every tiling that fits, keep the fastest, and reset the
+// iteration state to its initial value. With a cache file, a tiling measured before for
+// the same device, kernel variant, label count and size bucket is reused.
+sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32_t *label_groups,
+                      int32_t *tile_rows) {
+  if (!P || iters < 1) return fail(SL_ERR_INVALID_ARG, "need a handle and iters >= 1");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev), "device");
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev), "device properties");
+  long long N = 0;
+  if (P->is_batch)
+    for (const sl_problem_ *q : P->sub) N += q->lay.N;
+  else
+    N = P->lay.N;
+  int nb = 0;
+  while ((1LL << nb) < N) nb++;
+  char key[256];
+  snprintf(key, sizeof key, "%s piece=%d add=%d bf16=%d batch=%d k=%d n2=%d", prop.gcnArchName, P->piece,
+           (int)P->add, (int)P->bf16, (int)P->is_batch, P->is_batch ? P->kmax : P->A.k, nb);
+  int best = -1;
+  if (cache_path) {
+    FILE *fp = fopen(cache_path, "r");
+    if (fp) {
+      char line[512];
+      while (fgets(line, sizeof line, fp)) {
+        char *bar = strrchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (strcmp(line, key) == 0) {
+          int c = atoi(bar + 1);
+          if (c >= 0 && c < SLI_NCFG && cfg_fits(P, c)) best = c;
+        }
+      }
+      fclose(fp);
+    }
+  }
+  if (best < 0) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "event");
+    HIPCHK(hipEventCreate(&e1), "event");
+    float best_ms = 1e30f;
+    for (int c = 0; c < SLI_NCFG; c++) {
+      if (!cfg_fits(P, c)) continue;
+      P->cfg = c;
+      if (P->is_batch && batch_rebuild_items(P) != SL_OK) continue;
+      sl_status s = P->is_batch ? batch_enqueue(P, 6) : enqueue_iters(P, 2);
+      if (s != SL_OK) return s;
+      HIPCHK(hipEventRecord(e0, P->st), "event record");
+      s = P->is_batch ? batch_enqueue(P, iters) : enqueue_iters(P, iters);
+      if (s != SL_OK) return s;
+      HIPCHK(hipEventRecord(e1, P->st), "event record");
+      HIPCHK(hipEventSynchronize(e1), "event sync");
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best < 0) return fail(SL_ERR_UNSUPPORTED, "no tiling fits");
+    if (cache_path) {
+      FILE *fp = fopen(cache_path, "a");
+      if (fp) {
+        fprintf(fp, "%s|%d\n", key, best);
+        fclose(fp);
+      }
+    }
+  }
+  P->cfg = best;
+  sl_status s = reset_state(P);
+  if (s != SL_OK) return s;
+  if (P->is_batch && (s = batch_rebuild_items(P)) != SL_OK) return s;
+  HIPCHK(hipStreamSynchronize(P->st), "autotune sync");
+  if (label_groups) *label_groups = kIterCfg[best][0];
+  if (tile_rows) *tile_rows = kIterCfg[best][1];
+  return SL_OK;
 }
 
 sl_status sl_unrolled_forward(sl_problem, int32_t, int32_t, void *, size_t) {
@@ -604,12 +1007,14 @@ sl_status sl_set_tiling(sl_problem P, int32_t label_groups, int32_t tile_rows) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (label_groups == 0 && tile_rows == 0) {
     P->cfg = auto_cfg(P);
+    if (P->is_batch) return batch_rebuild_items(P);
     return SL_OK;
   }
   for (int c = 0; c < SLI_NCFG; c++)
     if (kIterCfg[c][0] == label_groups && kIterCfg[c][1] == tile_rows) {
       if (!cfg_fits(P, c)) return fail(SL_ERR_UNSUPPORTED, "tiling needs more LDS than a workgroup may use");
       P->cfg = c;
+      if (P->is_batch) return batch_rebuild_items(P);
       return SL_OK;
     }
   return fail(SL_ERR_INVALID_ARG, "unsupported tiling (%d label groups, %d rows)", label_groups, tile_rows);

@@ -62,6 +62,23 @@ struct IterPtrs {
 extern const int kIterCfg[SLI_NCFG][2];
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
                             const void *ptrs, hipStream_t st);
+
+// Batched launch: work items (instance, tile), per-instance pointer sets (6 rotation
+// phases per instance, IterPtrs<float> or IterPtrs<uint16_t>) and parameters in device memory.
+struct BatchItem {
+  int inst, tile;
+};
+struct BatchLaunch {
+  const BatchItem *items;
+  const int *count;
+  int *counter;
+  const void *ptrs;
+  const IterArgs *args;
+  int phase, grid, kmax;
+};
+hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
+                             hipStream_t st);
+int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax);  // blocks per CU
 size_t pdhg_iter_lds_bytes(int k, int tile_rows);   // dynamic LDS
 size_t pdhg_iter_static_lds(int cfg);
 

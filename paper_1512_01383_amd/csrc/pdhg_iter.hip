@@ -34,14 +34,15 @@ namespace {
 
 constexpr int TW = 64;
 
+// One iteration on one tile of one problem (all labels of its pixels).
 template <int PIECE, bool ADD, typename DT, int G, int TH>
-__global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, IterArgs A) {
+__device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs &A, int tile,
+                                          float *dyn) {
   constexpr int NP = TW * TH;   // pixels of a tile = threads of a label group
   __shared__ float ubs[G][TH + 2][TW + 2];
   __shared__ float pxs[G][TH + 1][TW + 1];
   __shared__ float pys[G][TH + 1][TW + 1];
   __shared__ float ex[G][NP];      // per-chunk partial sums (reused: sbar sums, then v sums)
-  extern __shared__ float dyn[];
   float *lsb = dyn;               // [k][NP] sbar
   float *lsa = dyn + A.k * NP;    // [k][NP] s, then the partial s update
 
@@ -52,12 +53,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
   const int lt = tid - grp * NP;
   const int tx = lt & 63, ty = lt >> 6;
 
-  // XCD-aware tile order: blocks b, b+8, b+16, ... run on one XCD; give it a contiguous run
   const int ntc = (W + TW - 1) / TW;
-  const int nb = (int)gridDim.x;
-  const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
-  const int per = nb >> 3, rem = nb & 7;
-  const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
   const int r0 = (tile / ntc) * TH;
   const int c0 = (tile % ntc) * TW;
   const int r = r0 + ty, c = c0 + tx;
@@ -322,6 +318,40 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
 }
 
 template <int PIECE, bool ADD, typename DT, int G, int TH>
+__global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, IterArgs A) {
+  extern __shared__ float dyn[];
+  // XCD-aware tile order: blocks b, b+8, b+16, ... run on one XCD; give it a contiguous run
+  const int nb = (int)gridDim.x;
+  const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
+  const int per = nb >> 3, rem = nb & 7;
+  const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  iter_tile<PIECE, ADD, DT, G, TH>(P, A, tile, dyn);
+}
+
+// Batched iteration: persistent blocks pull (instance, tile) work items from a counter.
+// Per-instance pointers (one set per rotation phase) and parameters come from device tables.
+template <int PIECE, bool ADD, typename DT, int G, int TH>
+__global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
+    const BatchItem *__restrict__ items, const int *__restrict__ count, int *counter,
+    const IterPtrs<DT> *__restrict__ ptrs, const IterArgs *__restrict__ args, int phase) {
+  extern __shared__ float dyn[];
+  __shared__ int s_item;
+  const int n = *count;
+  for (;;) {
+    __syncthreads();   // the previous item's LDS is no longer read
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= n) return;
+    const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
+    const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
+    iter_tile<PIECE, ADD, DT, G, TH>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
+  }
+}
+
+__global__ void k_reset_counter(int *counter) { *counter = 0; }
+
+template <int PIECE, bool ADD, typename DT, int G, int TH>
 hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
   const int ntc = (A.W + TW - 1) / TW, ntr = (A.H + TH - 1) / TH;
   const size_t lds = pdhg_iter_lds_bytes(A.k, TH);
@@ -330,6 +360,38 @@ hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
                      lds, st, P, A);
   return hipGetLastError();
 }
+
+template <int PIECE, bool ADD, typename DT, int G, int TH>
+hipError_t launch_bt(const BatchLaunch &L, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, L.counter);
+  hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH>), dim3(L.grid), dim3(64 * TH * G),
+                     pdhg_iter_lds_bytes(L.kmax, TH), st, L.items, L.count, L.counter,
+                     (const IterPtrs<DT> *)L.ptrs, L.args, L.phase);
+  return hipGetLastError();
+}
+
+template <int PIECE, bool ADD, typename DT, int G, int TH>
+int occ_t(int kmax) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pdhg_batch_kernel<PIECE, ADD, DT, G, TH>,
+                                                   64 * TH * G, pdhg_iter_lds_bytes(kmax, TH)) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+#define SLI_DISPATCH_CFG(FN, ...)                                   \
+  switch (cfg) {                                                     \
+    case 0: return FN<PIECE, ADD, DT, 1, 4>(__VA_ARGS__);            \
+    case 1: return FN<PIECE, ADD, DT, 1, 8>(__VA_ARGS__);            \
+    case 2: return FN<PIECE, ADD, DT, 2, 4>(__VA_ARGS__);            \
+    case 3: return FN<PIECE, ADD, DT, 2, 8>(__VA_ARGS__);            \
+    default: return FN<PIECE, ADD, DT, 4, 4>(__VA_ARGS__);           \
+  }
+
+template <int PIECE, bool ADD, typename DT>
+hipError_t launch_bg(int cfg, const BatchLaunch &L, hipStream_t st) { SLI_DISPATCH_CFG(launch_bt, L, st) }
+template <int PIECE, bool ADD, typename DT>
+int occ_g(int cfg, int kmax) { SLI_DISPATCH_CFG(occ_t, kmax) }
 
 template <int PIECE, bool ADD, typename DT>
 hipError_t launch_g(int cfg, const IterArgs &A, const void *ptrs, hipStream_t st) {
@@ -372,4 +434,29 @@ hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterA
     default:
       return launch_d<SLI_SAMPLED, false>(bf16, cfg, A, ptrs, st);
   }
+}
+
+hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
+                             hipStream_t st) {
+  if (piece == SLI_QUAD) {
+    if (add) return bf16 ? launch_bg<SLI_QUAD, true, uint16_t>(cfg, L, st) : launch_bg<SLI_QUAD, true, float>(cfg, L, st);
+    return bf16 ? launch_bg<SLI_QUAD, false, uint16_t>(cfg, L, st) : launch_bg<SLI_QUAD, false, float>(cfg, L, st);
+  }
+  if (piece == SLI_TRUNC) {
+    if (add) return bf16 ? launch_bg<SLI_TRUNC, true, uint16_t>(cfg, L, st) : launch_bg<SLI_TRUNC, true, float>(cfg, L, st);
+    return bf16 ? launch_bg<SLI_TRUNC, false, uint16_t>(cfg, L, st) : launch_bg<SLI_TRUNC, false, float>(cfg, L, st);
+  }
+  return bf16 ? launch_bg<SLI_SAMPLED, false, uint16_t>(cfg, L, st) : launch_bg<SLI_SAMPLED, false, float>(cfg, L, st);
+}
+
+int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax) {
+  if (piece == SLI_QUAD) {
+    if (add) return bf16 ? occ_g<SLI_QUAD, true, uint16_t>(cfg, kmax) : occ_g<SLI_QUAD, true, float>(cfg, kmax);
+    return bf16 ? occ_g<SLI_QUAD, false, uint16_t>(cfg, kmax) : occ_g<SLI_QUAD, false, float>(cfg, kmax);
+  }
+  if (piece == SLI_TRUNC) {
+    if (add) return bf16 ? occ_g<SLI_TRUNC, true, uint16_t>(cfg, kmax) : occ_g<SLI_TRUNC, true, float>(cfg, kmax);
+    return bf16 ? occ_g<SLI_TRUNC, false, uint16_t>(cfg, kmax) : occ_g<SLI_TRUNC, false, float>(cfg, kmax);
+  }
+  return bf16 ? occ_g<SLI_SAMPLED, false, uint16_t>(cfg, kmax) : occ_g<SLI_SAMPLED, false, float>(cfg, kmax);
 }

@@ -1,0 +1,191 @@
+"""Batched solves (many independent problems per persistent launch, hipGraph replay of the
+iteration period, autotuned tiling) through the C-ABI. GPU only.
+
+The batch kernel runs the same per-tile code as the single-instance kernel, so a batch
+member must match a single-instance solve of the same problem with the same tiling bit for
+bit, whatever mix of sizes and label counts shares the launch and whether the period is
+replayed from a graph or launched eagerly.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1512_01383_amd as S  # noqa: E402
+
+TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)]
+
+
+def _mixed_tq():
+    # sizes that leave ragged 64 x 4 and 64 x 8 tiles, label counts 2 .. 20
+    shapes = [(9, 131, 5), (40, 90, 10), (1, 70, 2), (33, 64, 20), (17, 200, 8), (1, 1, 4)]
+    return [W.truncated_quadratic(L=L, H=H, W=Wd, seed=40 + j) for j, (H, Wd, L) in enumerate(shapes)]
+
+
+def _mixed_sampled():
+    out = []
+    for j, (H, Wd, L, M) in enumerate([(10, 97, 8, 64), (6, 65, 4, 13), (21, 30, 6, 40)]):
+        rng = np.random.default_rng(70 + j)
+        tau = np.arange(M, dtype=np.float64)
+        idx = np.round(np.linspace(0, M - 1, L)).astype(int)
+        base = rng.uniform(0, 1, size=(M, H, Wd))
+        costs = np.abs(base - base[rng.integers(0, M)]).astype(np.float32)
+        out.append(W.Workload(f"smp{j}", H, Wd, tau[idx], W.SAMPLED, 0.5, tau=tau, samples=costs))
+    return out
+
+
+def _single(wl, tiling, iters):
+    g = S.Problem.from_workload(wl)
+    g.set_tiling(*tiling)
+    g.run(iters)
+    ul, u = g.read_u()
+    rep = g.energy()
+    torch.cuda.synchronize()
+    g.close()
+    return ul.cpu().numpy(), u.cpu().numpy(), rep
+
+
+def _assert_member_equals(b, i, ref):
+    ul, u = b.read_u_of(i)
+    rep = b.energy_of(i)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ul.cpu().numpy(), ref[0])
+    np.testing.assert_array_equal(u.cpu().numpy(), ref[1])
+    for key in ("primal_ub", "dual_lb", "e_nonconvex"):
+        assert rep[key] == ref[2][key], (i, key, rep[key], ref[2][key])
+
+
+@pytest.mark.parametrize("tiling", TILINGS, ids=[f"g{a}t{b}" for a, b in TILINGS])
+def test_batch_member_equals_single_solve(tiling):
+    wls = _mixed_tq()
+    iters = 13                     # two graph periods and a tail of eager launches
+    b = S.BatchProblem(wls)
+    b.set_tiling(*tiling)
+    b.run(iters)
+    torch.cuda.synchronize()
+    for i, wl in enumerate(wls):
+        print(f"batch member {i} {wl.H}x{wl.W} L={wl.L} tiling={tiling}", flush=True)
+        _assert_member_equals(b, i, _single(wl, tiling, iters))
+        assert b.info_of(i) == (iters, True)
+    b.close()
+
+
+def test_batch_sampled_member_equals_single_solve():
+    wls = _mixed_sampled()
+    b = S.BatchProblem(wls)
+    tiling = b.get_tiling()
+    b.run(20)
+    for i, wl in enumerate(wls):
+        _assert_member_equals(b, i, _single(wl, tiling, 20))
+    b.close()
+
+
+def test_batch_bf16_member_equals_single_solve():
+    wls = _mixed_tq()[:4]
+    b = S.BatchProblem(wls, storage="bf16")
+    tiling = b.get_tiling()
+    b.run(9)
+    for i, wl in enumerate(wls):
+        g = S.Problem.from_workload(wl, storage="bf16")
+        g.set_tiling(*tiling)
+        g.run(9)
+        ul, u = g.read_u()
+        rep = g.energy()
+        torch.cuda.synchronize()
+        _assert_member_equals(b, i, (ul.cpu().numpy(), u.cpu().numpy(), rep))
+        g.close()
+    b.close()
+
+
+def test_graph_replay_equals_eager_launches():
+    """Graph replays interleaved with the program's own eager work and synchronisations
+    give the same iterates as eager launches after every replay."""
+    wls = _mixed_tq()
+    bg = S.BatchProblem(wls)
+    be = S.BatchProblem(wls)
+    be.set_graphs(False)
+    x = torch.randn(1 << 20, device="cuda:0")
+    for chunk in (6, 12, 5, 7, 18):
+        bg.run(chunk)
+        be.run(chunk)
+        y = (x * 1.5).sum()          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        for i in range(len(wls)):
+            ug, _ = bg.read_u_of(i)
+            ue, _ = be.read_u_of(i)
+            torch.cuda.synchronize()
+            assert torch.equal(ug, ue), (chunk, i)
+    for i in range(len(wls)):
+        assert bg.energy_of(i) == be.energy_of(i)
+    bg.close()
+    be.close()
+
+
+def test_batch_member_matches_oracle(orc):
+    wls = _mixed_tq()
+    b = S.BatchProblem(wls)
+    b.run(60)
+    for i in (1, 3, 4):
+        o = orc.Problem(wls[i])
+        o.run(60)
+        rg, ro = b.energy_of(i), o.monitor()
+        for kg, ko in (("primal_ub", "primal"), ("dual_lb", "dual"), ("e_nonconvex", "e_nc")):
+            assert abs(rg[kg] - ro[ko]) <= 1e-5 * abs(ro[ko]), (i, kg, rg[kg], ro[ko])
+    b.close()
+
+
+def test_batch_run_to_gap_retires_members():
+    wls = [W.truncated_quadratic(L=2, H=32, W=32, seed=1)]
+    wls += [W.truncated_quadratic(L=L, H=24, W=70, seed=90 + L) for L in (4, 6)]
+    b = S.BatchProblem(wls, check_every=48)
+    tol = 2e-2                     # the oracle reaches it after 576, 2304 and 5568 iterations
+    done = b.run_to_gap(tol, 20000)
+    assert done <= 20000
+    for i in range(len(wls)):
+        n, active = b.info_of(i)
+        rep = b.energy_of(i)
+        assert not active and rep["rel_gap"] <= tol, (i, n, rep)
+        assert n % 48 == 0
+    # retired members are frozen
+    before = [b.read_u_of(i)[0].clone() for i in range(len(wls))]
+    b.run(12)
+    for i in range(len(wls)):
+        assert torch.equal(b.read_u_of(i)[0], before[i])
+    b.close()
+
+
+def test_autotune_resets_state_and_uses_cache(tmp_path):
+    wl = W.truncated_quadratic(L=10, H=64, W=128, seed=11)
+    g = S.Problem.from_workload(wl)
+    fresh = g.energy()
+    g.run(30)
+    cache = str(tmp_path / "tiling.cache")
+    t1 = g.autotune(iters=10, cache=cache)
+    assert t1 in TILINGS and g.get_tiling() == t1
+    assert g.energy() == fresh                    # iteration state back at its start
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(f"|{TILINGS.index(t1)}")
+    t2 = g.autotune(iters=10, cache=cache)        # served from the cache
+    assert t2 == t1 and len(open(cache).read().splitlines()) == 1
+    g.close()
+
+    b = S.BatchProblem(_mixed_tq())
+    tb = b.autotune(iters=6)
+    assert tb in TILINGS
+    for i in range(6):
+        assert b.info_of(i) == (0, True)
+    b.close()
+
+
+def test_batch_rejects_mixed_kinds():
+    wls = [_mixed_tq()[0], _mixed_sampled()[0]]
+    with pytest.raises(S.SublabelError):
+        S.BatchProblem(wls)
