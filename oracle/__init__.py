@@ -91,6 +91,12 @@ def lib():
         L.or_lower_hull.restype = C.c_int
         L.or_proj_simplex.argtypes = [C.c_int, _dp, _dp]
         L.or_proj_ball.argtypes = [_dp, _dp, C.c_double]
+        L.or_unrolled_forward.argtypes = [C.c_void_p, C.c_int]
+        L.or_unrolled_backward.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.or_step_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.or_proj_ball_vjp.argtypes = [C.c_double] * 5 + [_dp] * 3
+        L.or_proj_epi_quad_vjp.argtypes = [C.c_double] * 9 + [_dp] * 4
+        L.or_proj_epi_pl_vjp.argtypes = [C.c_int, _dp, _dp] + [C.c_double] * 4 + [_dp] * 3
         _lib = L
     return _lib
 
@@ -165,6 +171,29 @@ def proj_ball(px, py, radius):
     a, b = C.c_double(px), C.c_double(py)
     lib().or_proj_ball(C.byref(a), C.byref(b), radius)
     return a.value, b.value
+
+
+def proj_ball_vjp(ax, ay, radius, pxb, pyb):
+    """Adjoint of the ball projection: returns (axb, ayb, radius_b)."""
+    a, b, r = C.c_double(), C.c_double(), C.c_double(0.0)
+    lib().or_proj_ball_vjp(ax, ay, radius, pxb, pyb, C.byref(a), C.byref(b), C.byref(r))
+    return a.value, b.value, r.value
+
+
+def proj_epi_quad_vjp(a, c, d, g0, g1, y0, w0, yb, wb):
+    """Adjoint of proj_epi_quad at (y0, w0): returns (y0b, w0b, cb, db)."""
+    o = [C.c_double(0.0) for _ in range(4)]
+    lib().or_proj_epi_quad_vjp(a, c, d, g0, g1, y0, w0, yb, wb, *[C.byref(x) for x in o])
+    return tuple(x.value for x in o)
+
+
+def proj_epi_pl_vjp(t, r, y0, w0, yb, wb):
+    """Adjoint of proj_epi_pl at (y0, w0): returns (y0b, w0b, rb[n])."""
+    t, r = _f64(t), _f64(r)
+    rb = np.zeros(len(t))
+    y0b, w0b = C.c_double(), C.c_double()
+    lib().or_proj_epi_pl_vjp(len(t), _p(t), _p(r), y0, w0, yb, wb, C.byref(y0b), C.byref(w0b), _p(rb))
+    return y0b.value, w0b.value, rb
 
 
 # ----------------------------------------------------------------------------- problem
@@ -275,6 +304,45 @@ class Problem:
         svz, ts, tu = np.empty(k), np.empty(k), np.empty(N)
         lib().or_steps(self.h, C.byref(sp), _p(svz), C.byref(sq), _p(tu), _p(ts))
         return sp.value, svz, sq.value, tu, ts
+
+    # ---- reverse pass
+    def unrolled_forward(self, K: int):
+        """Run K iterations from the current state, keeping every state for the reverse pass."""
+        if lib().or_unrolled_forward(self.h, int(K)) != 0:
+            raise ValueError(lib().or_last_error().decode())
+
+    def unrolled_backward(self, gu):
+        """Gradients (f [H,W], lambda, w [L,H,W] or None) of a function of the read-out u
+        after the unrolled pass, given its adjoint gu [H,W] in original label units."""
+        gu = _f64(gu).reshape(-1)
+        gf = np.empty(self.N)
+        gl = C.c_double()
+        has_w = self.wl.tau is not None
+        gw = np.empty((self.k + 1) * self.N) if has_w else None
+        rc = lib().or_unrolled_backward(self.h, _p(gu), _p(gf), C.byref(gl),
+                                        _p(gw) if has_w else None)
+        if rc != 0:
+            raise ValueError(lib().or_last_error().decode())
+        return (gf.reshape(self.H, self.W), gl.value,
+                gw.reshape(self.k + 1, self.H, self.W) if has_w else None)
+
+    def step_vjp(self, state: dict, adj: dict):
+        """Adjoint of one iteration at ``state`` (STATE_ORDER dict): the adjoint of the
+        state before it, and the accumulated adjoints of the normalised data centre [H,W],
+        the normalised lambda and the additive values [L,H,W] (or None)."""
+        st = np.ascontiguousarray(np.concatenate([_f64(state[n]).reshape(-1) for n in STATE_ORDER]))
+        ab = np.ascontiguousarray(np.concatenate([_f64(adj[n]).reshape(-1) for n in STATE_ORDER]))
+        gc = np.zeros(self.N)
+        gl = C.c_double(0.0)
+        has_w = self.wl.tau is not None
+        gw = np.zeros((self.k + 1) * self.N) if has_w else None
+        if lib().or_step_vjp(self.h, _p(st), _p(ab), _p(gc), C.byref(gl), _p(gw) if has_w else None) != 0:
+            raise ValueError(lib().or_last_error().decode())
+        k, H, W = self.k, self.H, self.W
+        kN = k * H * W
+        out = {n: ab[b * kN:(b + 1) * kN].reshape(k, H, W).copy() for b, n in enumerate(STATE_ORDER[:-1])}
+        out["qd"] = ab[8 * kN:].reshape(H, W).copy()
+        return out, gc.reshape(H, W), gl.value, (gw.reshape(k + 1, H, W) if has_w else None)
 
     def piece(self, x: int, i: int):
         kind = C.c_int()

@@ -79,6 +79,9 @@ struct or_problem {
   double best_P, best_D;
   int have_best;
   int64_t iters;
+  double *tape;        /* states x_0 .. x_{K-1} of an unrolled forward pass          */
+  int tape_len;
+  int64_t tape_end;    /* iteration count when the unrolled forward pass ended       */
 };
 
 /* ------------------------------------------------------------------------------- */
@@ -159,16 +162,33 @@ static int cubic_roots(double p, double q, double *R) {
   return n;
 }
 
+/* which part of the graph of the conjugate a projection landed on (used by the reverse
+ * pass to pick the Jacobian of that part) */
+enum {
+  PK_INSIDE = 0,  /* point already in the epigraph                                  */
+  PK_RAY0,        /* quadratic piece: interior of the ray of slope g0                */
+  PK_RAY1,        /* quadratic piece: interior of the ray of slope g1                */
+  PK_ARC,         /* quadratic piece: interior of the parabola arc                   */
+  PK_JUNC0,       /* quadratic piece: junction of ray g0 and arc, y = a (g0 - c)     */
+  PK_JUNC1,       /* quadratic piece: junction of arc and ray g1, y = a (g1 - c)     */
+  PK_SEG,         /* PL piece: interior of the linear part of slope t_m              */
+  PK_KINK_LO,     /* PL piece: kink between the parts of slopes t_{m-1} and t_m      */
+  PK_KINK_HI      /* PL piece: kink between the parts of slopes t_m and t_{m+1}      */
+};
+
 typedef struct {
   double y0, w0, by, bw, bd;
+  int bk, bm;     /* part and vertex index of the nearest candidate so far */
 } nearest;
 
-static void cand(nearest *nr, double y, double w) {
+static void cand(nearest *nr, double y, double w, int kind, int m) {
   double d = (y - nr->y0) * (y - nr->y0) + (w - nr->w0) * (w - nr->w0);
   if (d < nr->bd) {
     nr->bd = d;
     nr->by = y;
     nr->bw = w;
+    nr->bk = kind;
+    nr->bm = m;
   }
 }
 
@@ -178,51 +198,77 @@ static void cand(nearest *nr, double y, double w) {
  * (y >= a(g1-c)) (Fig. 2, left). The nearest point on each part is computed and the
  * closest one wins: on a ray by the perpendicular foot clamped to the ray, on the arc
  * from every real stationary point of the squared distance (a cubic) clamped to the arc. */
-void or_proj_epi_quad(double a, double c, double d, double g0, double g1, double *y,
-                      double *w) {
+static int proj_quad_part(double a, double c, double d, double g0, double g1, double *y,
+                          double *w) {
   double y0 = *y, w0 = *w;
-  if (w0 >= or_conj_quad(a, c, d, g0, g1, y0)) return;
-  nearest nr = {y0, w0, y0, w0, INFINITY};
+  if (w0 >= or_conj_quad(a, c, d, g0, g1, y0)) return PK_INSIDE;
+  nearest nr = {y0, w0, y0, w0, INFINITY, PK_INSIDE, 0};
   double rho0 = 0.5 * a * (g0 - c) * (g0 - c) + d;
   double rho1 = 0.5 * a * (g1 - c) * (g1 - c) + d;
   double y1 = a * (g0 - c), y2 = a * (g1 - c);
   double yf = (y0 + g0 * (w0 + rho0)) / (1.0 + g0 * g0);
-  if (yf > y1) yf = y1;
-  cand(&nr, yf, g0 * yf - rho0);
+  int kind = PK_RAY0;
+  if (yf > y1) {
+    yf = y1;
+    kind = PK_JUNC0;
+  }
+  cand(&nr, yf, g0 * yf - rho0, kind, 0);
   yf = (y0 + g1 * (w0 + rho1)) / (1.0 + g1 * g1);
-  if (yf < y2) yf = y2;
-  cand(&nr, yf, g1 * yf - rho1);
+  kind = PK_RAY1;
+  if (yf < y2) {
+    yf = y2;
+    kind = PK_JUNC1;
+  }
+  cand(&nr, yf, g1 * yf - rho1, kind, 0);
   /* arc: with Y = y + a c and W = w + a c^2/2 + d the arc is W = Y^2/(2a); stationary
    * points of (Y-Y0)^2 + (Y^2/(2a)-W0)^2 solve Y^3 + 2a(a-W0) Y - 2a^2 Y0 = 0 */
   double Y0 = y0 + a * c, W0 = w0 + 0.5 * a * c * c + d;
   double R[3];
   int nr_ = cubic_roots(2.0 * a * (a - W0), -2.0 * a * a * Y0, R);
   for (int j = 0; j < nr_; j++) {
-    double Y = clampd(R[j], y1 + a * c, y2 + a * c);
+    double lo = y1 + a * c, hi = y2 + a * c;
+    double Y = clampd(R[j], lo, hi);
+    kind = R[j] < lo ? PK_JUNC0 : (R[j] > hi ? PK_JUNC1 : PK_ARC);
     double yy = Y - a * c;
-    cand(&nr, yy, Y * Y / (2.0 * a) - 0.5 * a * c * c - d);
+    cand(&nr, yy, Y * Y / (2.0 * a) - 0.5 * a * c * c - d, kind, 0);
   }
   *y = nr.by;
   *w = nr.bw;
+  return nr.bk;
+}
+
+void or_proj_epi_quad(double a, double c, double d, double g0, double g1, double *y,
+                      double *w) {
+  (void)proj_quad_part(a, c, d, g0, g1, y, w);
 }
 
 /* Euclidean projection onto epi rho_i^* for a convex piecewise-linear piece with
  * vertices (t_m, r_m): the conjugate is piecewise linear with slopes t_m and kinks at
  * the slopes of rho_i between consecutive vertices (Fig. 2, right). Nearest point on
  * every linear part of the graph, closest wins. */
-void or_proj_epi_pl(int n, const double *t, const double *r, double *y, double *w) {
+static int proj_pl_part(int n, const double *t, const double *r, double *y, double *w,
+                        int *mm) {
   double y0 = *y, w0 = *w;
-  if (w0 >= or_conj_pl(n, t, r, y0)) return;
-  nearest nr = {y0, w0, y0, w0, INFINITY};
+  *mm = 0;
+  if (w0 >= or_conj_pl(n, t, r, y0)) return PK_INSIDE;
+  nearest nr = {y0, w0, y0, w0, INFINITY, PK_INSIDE, 0};
   for (int m = 0; m < n; m++) {
     double lo = (m > 0) ? (r[m] - r[m - 1]) / (t[m] - t[m - 1]) : -INFINITY;
     double hi = (m < n - 1) ? (r[m + 1] - r[m]) / (t[m + 1] - t[m]) : INFINITY;
     double yf = (y0 + t[m] * (w0 + r[m])) / (1.0 + t[m] * t[m]);
+    int kind = yf < lo ? PK_KINK_LO : (yf > hi ? PK_KINK_HI : PK_SEG);
     yf = clampd(yf, lo, hi);
-    cand(&nr, yf, t[m] * yf - r[m]);
+    cand(&nr, yf, t[m] * yf - r[m], kind, m);
   }
   *y = nr.by;
   *w = nr.bw;
+  *mm = nr.bm;
+  return nr.bk;
+}
+
+void or_proj_epi_pl(int n, const double *t, const double *r, double *y, double *w) {
+  int m;
+  (void)proj_pl_part(n, t, r, y, w, &m);
 }
 
 /* lower convex hull of points sorted by t (Andrew's monotone chain); returns the
@@ -604,7 +650,8 @@ void or_destroy(or_problem *P) {
   void *ptrs[] = {P->gam,  P->h,   P->c,   P->cf,  P->taun, P->sidx,   P->cost, P->hn,
                   P->ht,   P->hr,  P->wadd, P->u,  P->up,   P->s,      P->sp,   P->v,
                   P->z,    P->px,  P->py,  P->q,   P->sig_vz, P->tau_u, P->tau_s, P->ub,
-                  P->sb,   P->Kv,  P->Kq,  P->Kpx, P->Kpy,  P->Kz,     P->Ku,   P->Ks};
+                  P->sb,   P->Kv,  P->Kq,  P->Kpx, P->Kpy,  P->Kz,     P->Ku,   P->Ks,
+                  P->tape};
   for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; i++) free(ptrs[i]);
   free(P);
 }
@@ -831,4 +878,323 @@ void or_normalized(const or_problem *P, double *gam, double *lam, double *shift,
   if (lam) *lam = P->lam;
   if (shift) *shift = P->shift;
   if (scale) *scale = P->scale;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* reverse pass: gradients of a function of the iterate reached after K unrolled      */
+/* iterations with respect to the data image f, lambda and the per-label additive      */
+/* values w. Every map of the iteration is differentiated where it is smooth; on the   */
+/* boundary between two parts of a projection the part the forward pass chose decides */
+/* (the graph of a conjugate is C^1 at ray/arc junctions, so only kinks of PL pieces  */
+/* and the ball boundary are genuine nonsmooth points).                               */
+
+/* adjoint of the projection onto the l2 ball: p = a if |a| <= r, else r a / |a| */
+void or_proj_ball_vjp(double ax, double ay, double radius, double pxb, double pyb,
+                      double *axb, double *ayb, double *rb) {
+  double nrm = sqrt(ax * ax + ay * ay);
+  if (nrm > radius) {
+    double ex = ax / nrm, ey = ay / nrm, f = radius / nrm;
+    double dot = ex * pxb + ey * pyb;
+    *axb = f * (pxb - ex * dot);
+    *ayb = f * (pyb - ey * dot);
+    *rb += dot;
+  } else {
+    *axb = pxb;
+    *ayb = pyb;
+  }
+}
+
+/* adjoint of the projection onto epi rho_i^* of a quadratic piece a/2 (t-c)^2 + d on
+ * [g0,g1], evaluated at the input point (y0, w0); (yb, wb) is the adjoint of the output.
+ * Writes the input adjoint, accumulates the adjoints of c and d. */
+void or_proj_epi_quad_vjp(double a, double c, double d, double g0, double g1, double y0,
+                          double w0, double yb, double wb, double *y0b, double *w0b,
+                          double *cb, double *db) {
+  double y = y0, w = w0;
+  int part = proj_quad_part(a, c, d, g0, g1, &y, &w);
+  *y0b = 0.0;
+  *w0b = 0.0;
+  if (part == PK_INSIDE) {
+    *y0b = yb;
+    *w0b = wb;
+  } else if (part == PK_RAY0 || part == PK_RAY1) {
+    /* foot on the line w = g y - rho(g): orthogonal projector onto direction (1, g) plus
+     * the offset rho(g) = a/2 (g-c)^2 + d */
+    double g = part == PK_RAY0 ? g0 : g1;
+    double e = (yb + g * wb) / (1.0 + g * g);
+    *y0b = e;
+    *w0b = g * e;
+    double rhob = g * e - wb;
+    *cb += rhob * (-a * (g - c));
+    *db += rhob;
+  } else if (part == PK_JUNC0 || part == PK_JUNC1) {
+    /* the junction point (a (g-c), g a (g-c) - rho(g)) does not move with (y0, w0) */
+    double g = part == PK_JUNC0 ? g0 : g1;
+    double ybt = yb + g * wb;
+    double rhob = -wb;
+    *cb += -a * ybt + rhob * (-a * (g - c));
+    *db += rhob;
+  } else {
+    /* arc w = g(y) = c y + y^2/(2a) - d; the foot solves the stationarity
+     * G = (y - y0) + (g(y) - w0) g'(y) = 0; implicit differentiation */
+    double gp = c + y / a, gv = c * y + y * y / (2.0 * a) - d;
+    double Gy = 1.0 + gp * gp + (gv - w0) / a;
+    double ybt = yb + wb * gp;   /* w = g(y): dw = g' dy + y dc - dd */
+    *cb += wb * y;
+    *db += -wb;
+    if (Gy > 0.0) {
+      double e = ybt / Gy;
+      *y0b = e;
+      *w0b = e * gp;
+      *cb += -e * (y * gp + gv - w0);
+      *db += e * gp;
+    }
+  }
+}
+
+/* adjoint of the projection onto epi rho_i^* of a convex PL piece with vertices (t, r);
+ * accumulates the adjoints of the vertex values r[n] */
+void or_proj_epi_pl_vjp(int n, const double *t, const double *r, double y0, double w0,
+                        double yb, double wb, double *y0b, double *w0b, double *rb) {
+  double y = y0, w = w0;
+  int m;
+  int part = proj_pl_part(n, t, r, &y, &w, &m);
+  *y0b = 0.0;
+  *w0b = 0.0;
+  if (part == PK_INSIDE) {
+    *y0b = yb;
+    *w0b = wb;
+  } else if (part == PK_SEG) {
+    double e = (yb + t[m] * wb) / (1.0 + t[m] * t[m]);
+    *y0b = e;
+    *w0b = t[m] * e;
+    rb[m] += t[m] * e - wb;
+  } else {
+    /* kink point (b, t_m b - r_m), b the slope of rho between the two vertices */
+    int j0 = part == PK_KINK_LO ? m - 1 : m, j1 = j0 + 1;
+    double bb = yb + t[m] * wb;
+    double dt = t[j1] - t[j0];
+    rb[m] += -wb;
+    rb[j1] += bb / dt;
+    rb[j0] -= bb / dt;
+  }
+}
+
+/* adjoints of the final piece parameters (quadratic: c', d'; PL: vertex values r) mapped
+ * back to the normalised data centre c(x) and the additive values w_i, w_{i+1} */
+static void piece_params_vjp(const or_problem *P, int64_t x, int i, const piece *pc,
+                             double cpb, double dpb, const double *rb, double *gc, double *gw) {
+  const double g0 = P->gam[i], g1 = P->gam[i + 1], hi = g1 - g0;
+  const double c = P->c ? P->c[x] : 0.0;
+  if (pc->kind == OR_PIECE_QUAD) {
+    if (P->wadd) {
+      /* c' = c - beta/a, d' = w_i - beta g0 + a/2 (c^2 - c'^2) */
+      double beta = (P->wadd[(int64_t)(i + 1) * P->N + x] - P->wadd[(int64_t)i * P->N + x]) / hi;
+      double c2 = c - beta / P->a;
+      gc[x] += cpb + dpb * P->a * (c - c2);
+      double betab = -cpb / P->a + dpb * (c2 - g0);
+      gw[(int64_t)i * P->N + x] += dpb - betab / hi;
+      gw[(int64_t)(i + 1) * P->N + x] += betab / hi;
+    } else {
+      gc[x] += cpb;
+    }
+    return;
+  }
+  /* PL piece from a truncated quadratic: vertex values min(a/2 (t-c)^2, nu) (+ additive) */
+  if (P->rho == OR_TRUNC_QUAD) {
+    float del = (float)sqrt(2.0 * P->nu / P->a);
+    float lo = P->cf[x] - del, hf = P->cf[x] + del;
+    int flat = ((float)g1 <= lo || (float)g0 >= hf);
+    for (int m = 0; m < pc->n; m++) {
+      double qv = 0.5 * P->a * (pc->t[m] - c) * (pc->t[m] - c);
+      if (!flat && qv < P->nu) gc[x] += rb[m] * (-P->a * (pc->t[m] - c));
+    }
+  }
+  if (P->wadd)
+    for (int m = 0; m < pc->n; m++) {
+      double al = (pc->t[m] - g0) / hi;
+      gw[(int64_t)i * P->N + x] += rb[m] * (1.0 - al);
+      gw[(int64_t)(i + 1) * P->N + x] += rb[m] * al;
+    }
+}
+
+/* Adjoint of one iteration. `st` is the state before it (or_get_state layout); `adj` holds
+ * on entry the adjoint of the state after it (same layout) and on exit the adjoint of the
+ * state before it. Accumulates into gc [N] (normalised data centre), *glam (normalised
+ * lambda) and gw [L][N] (additive values; may be NULL without them). Reverse order of the
+ * forward steps: primal descent, q, p, (v, z), over-relaxation. */
+int or_step_vjp(or_problem *P, const double *st, double *adj, double *gc, double *glam,
+                double *gw) {
+  const int k = P->k;
+  const int64_t N = P->N, kN = (int64_t)k * N;
+  const double *u = st, *up = st + kN, *s = st + 2 * kN, *sp = st + 3 * kN;
+  const double *v = st + 4 * kN, *z = st + 5 * kN, *px = st + 6 * kN, *py = st + 7 * kN;
+  const double *q = st + 8 * kN;
+  double *ub_ = adj, *upb = adj + kN, *sb_ = adj + 2 * kN, *spb = adj + 3 * kN;
+  double *vb = adj + 4 * kN, *zb = adj + 5 * kN, *pxb = adj + 6 * kN, *pyb = adj + 7 * kN;
+  double *qb = adj + 8 * kN;
+  (void)q;
+  double *buf = (double *)calloc((size_t)(16 * kN + 3 * N), sizeof(double));
+  if (!buf) {
+    set_err("out of memory");
+    return -1;
+  }
+  double *ubr = buf, *sbr = buf + kN;                       /* over-relaxed x          */
+  double *Kv = buf + 2 * kN, *Kpx = buf + 3 * kN, *Kpy = buf + 4 * kN, *Kz = buf + 5 * kN;
+  double *Bu = buf + 6 * kN, *Bs = buf + 7 * kN;             /* adjoint of K^T y        */
+  double *Av = buf + 8 * kN, *Apx = buf + 9 * kN, *Apy = buf + 10 * kN, *Az = buf + 11 * kN;
+  double *Cv = buf + 12 * kN, *Cpx = buf + 13 * kN, *Cpy = buf + 14 * kN, *Cz = buf + 15 * kN;
+  double *Kq = buf + 16 * kN, *Aq = Kq + N, *Cq = Aq + N;
+  double *Cu = Bu, *Cs = Bs;   /* reused after Bu, Bs are consumed */
+
+  /* forward quantities: xbar and K xbar (the points the projections were applied to) */
+  for (int64_t e = 0; e < kN; e++) {
+    ubr[e] = 2.0 * u[e] - up[e];
+    sbr[e] = 2.0 * s[e] - sp[e];
+  }
+  or_apply_K(P, ubr, sbr, Kv, Kq, Kpx, Kpy, Kz);
+
+  /* primal descent u' = u - T_u K_u^T y', s' = s - T_s K_s^T y' (up' = u, sp' = s):
+   * the adjoint of the linear map y' -> K^T y' is K */
+  for (int i = 0; i < k; i++)
+    for (int64_t x = 0; x < N; x++) {
+      int64_t e = i * N + x;
+      Bu[e] = -P->tau_u[x] * ub_[e];
+      Bs[e] = -P->tau_s[i] * sb_[e];
+    }
+  or_apply_K(P, Bu, Bs, Av, Aq, Apx, Apy, Az);
+  for (int64_t e = 0; e < kN; e++) {
+    Av[e] += vb[e];
+    Az[e] += zb[e];
+    Apx[e] += pxb[e];
+    Apy[e] += pyb[e];
+  }
+  for (int64_t x = 0; x < N; x++) Aq[x] += qb[x];
+
+  /* q' = q + sigma_q (K_q xbar - 1); p' = Proj_ball(p + sigma_p grad ubar);
+   * (v', z') = h Proj_epi((v + sigma K_v xbar, z + sigma K_z xbar) / h) */
+  double lam_acc = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : lam_acc)
+  for (int64_t x = 0; x < N; x++) {
+    piece pc;
+    double rb[OR_MAXV];
+    qb[x] = Aq[x];
+    Cq[x] = P->sig_q * Aq[x];
+    for (int i = 0; i < k; i++) {
+      int64_t e = i * N + x;
+      double ax = px[e] + P->sig_p * Kpx[e], ay = py[e] + P->sig_p * Kpy[e];
+      double axb, ayb, radb = 0.0;
+      or_proj_ball_vjp(ax, ay, P->lam * P->h[i], Apx[e], Apy[e], &axb, &ayb, &radb);
+      lam_acc += radb * P->h[i];
+      pxb[e] = axb;
+      pyb[e] = ayb;
+      Cpx[e] = P->sig_p * axb;
+      Cpy[e] = P->sig_p * ayb;
+
+      double y0 = (v[e] + P->sig_vz[i] * Kv[e]) / P->h[i];
+      double w0 = (z[e] + P->sig_vz[i] * Kz[e]) / P->h[i];
+      double yb = P->h[i] * Av[e], wb = P->h[i] * Az[e];
+      double y0b, w0b, cpb = 0.0, dpb = 0.0;
+      get_piece(P, x, i, &pc);
+      if (pc.kind == OR_PIECE_QUAD) {
+        or_proj_epi_quad_vjp(pc.a, pc.c, pc.d, pc.g0, pc.g1, y0, w0, yb, wb, &y0b, &w0b, &cpb, &dpb);
+      } else {
+        for (int m = 0; m < pc.n; m++) rb[m] = 0.0;
+        or_proj_epi_pl_vjp(pc.n, pc.t, pc.r, y0, w0, yb, wb, &y0b, &w0b, rb);
+      }
+      if (P->rho != OR_SAMPLED) piece_params_vjp(P, x, i, &pc, cpb, dpb, rb, gc, gw);
+      vb[e] = y0b / P->h[i];
+      zb[e] = w0b / P->h[i];
+      Cv[e] = P->sig_vz[i] * vb[e];
+      Cz[e] = P->sig_vz[i] * zb[e];
+    }
+  }
+  *glam += lam_acc;
+
+  /* xbar = 2 x - x_prev: the adjoint of xbar is K^T of the dual-step adjoints */
+  or_apply_KT(P, Cv, Cq, Cpx, Cpy, Cz, Cu, Cs);
+  for (int64_t e = 0; e < kN; e++) {
+    double ut = ub_[e] + upb[e], stt = sb_[e] + spb[e];
+    ub_[e] = ut + 2.0 * Cu[e];
+    upb[e] = -Cu[e];
+    sb_[e] = stt + 2.0 * Cs[e];
+    spb[e] = -Cs[e];
+  }
+  free(buf);
+  return 0;
+}
+
+int or_unrolled_forward(or_problem *P, int K) {
+  if (K < 1) {
+    set_err("K must be >= 1");
+    return -1;
+  }
+  const int64_t S = or_state_size(P);
+  free(P->tape);
+  P->tape = (double *)malloc(sizeof(double) * (size_t)S * (size_t)K);
+  if (!P->tape) {
+    set_err("out of memory for the tape");
+    P->tape_len = 0;
+    return -1;
+  }
+  for (int n = 0; n < K; n++) {
+    or_get_state(P, P->tape + (int64_t)n * S);
+    pdhg_iteration(P);
+  }
+  P->tape_len = K;
+  P->tape_end = P->iters;
+  return 0;
+}
+
+/* gu [N]: adjoint of the back-projected u (original label units) after the unrolled
+ * pass. Outputs in the caller's units: gf [N] (may be NULL), *glam, gw [L][N] (may be
+ * NULL; needs the additive values). */
+int or_unrolled_backward(or_problem *P, const double *gu, double *gf, double *glam,
+                         double *gw) {
+  if (!P->tape || P->tape_end != P->iters) {
+    set_err("needs an unrolled forward pass immediately before");
+    return -1;
+  }
+  if (P->rho == OR_SAMPLED) {
+    set_err("gradients are defined for quadratic and truncated-quadratic data terms");
+    return -1;
+  }
+  const int k = P->k;
+  const int64_t N = P->N, S = or_state_size(P);
+  double *adj = (double *)calloc((size_t)S, sizeof(double));
+  double *gc = (double *)calloc((size_t)N, sizeof(double));
+  double *gwn = P->wadd ? (double *)calloc((size_t)P->L * N, sizeof(double)) : NULL;
+  if (!adj || !gc || (P->wadd && !gwn)) {
+    free(adj);
+    free(gc);
+    free(gwn);
+    set_err("out of memory");
+    return -1;
+  }
+  /* read-out u = shift + scale (gamma_1 + sum_i h_i clamp(u_i, 0, 1)) */
+  for (int i = 0; i < k; i++)
+    for (int64_t x = 0; x < N; x++) {
+      double ui = P->u[i * N + x];
+      adj[i * N + x] = (ui > 0.0 && ui < 1.0) ? P->scale * P->h[i] * gu[x] : 0.0;
+    }
+  double gl = 0.0;
+  int rc = 0;
+  for (int n = P->tape_len - 1; n >= 0 && rc == 0; n--)
+    rc = or_step_vjp(P, P->tape + (int64_t)n * S, adj, gc, &gl, gwn);
+  if (rc == 0) {
+    /* c = (f - shift) / scale, lambda_normalised = lambda * scale */
+    if (gf)
+      for (int64_t x = 0; x < N; x++) gf[x] = gc[x] / P->scale;
+    if (glam) *glam = gl * P->scale;
+    if (gw) {
+      if (gwn)
+        memcpy(gw, gwn, sizeof(double) * P->L * N);
+      else
+        memset(gw, 0, sizeof(double) * P->L * N);
+    }
+  }
+  free(adj);
+  free(gc);
+  free(gwn);
+  return rc;
 }

@@ -72,6 +72,24 @@ void or_steps(const or_problem *P, double *sigma_p, double *sigma_vz, double *si
 void or_piece(const or_problem *P, int64_t x, int i, int *kind, double *acd, int *n,
               double *t, double *r);
 
+/* reverse pass (differentiation of K unrolled iterations). or_unrolled_forward runs K
+ * iterations from the current state and keeps every state; or_unrolled_backward then
+ * returns the gradients of a function of the back-projected u with respect to f, lambda
+ * and the additive values w, given its adjoint gu [H*W]. Quadratic and truncated-
+ * quadratic data terms only. or_step_vjp is the adjoint of one iteration (see oracle.c).
+ * Return 0, or -1 with or_last_error() set. */
+int or_unrolled_forward(or_problem *P, int K);
+int or_unrolled_backward(or_problem *P, const double *gu, double *gf, double *glam, double *gw);
+int or_step_vjp(or_problem *P, const double *state, double *adj, double *gc, double *glam,
+                double *gw);
+void or_proj_ball_vjp(double ax, double ay, double radius, double pxb, double pyb,
+                      double *axb, double *ayb, double *rb);
+void or_proj_epi_quad_vjp(double a, double c, double d, double g0, double g1, double y0,
+                          double w0, double yb, double wb, double *y0b, double *w0b,
+                          double *cb, double *db);
+void or_proj_epi_pl_vjp(int n, const double *t, const double *r, double y0, double w0,
+                        double yb, double wb, double *y0b, double *w0b, double *rb);
+
 /* primitives */
 void or_grad(int H, int W, const double *u, double *gx, double *gy);
 void or_div(int H, int W, const double *px, const double *py, double *d);
