@@ -184,10 +184,35 @@ sl_status sl_set_graphs(sl_problem p, int32_t enable);
 sl_status sl_autotune(sl_problem p, int32_t iters, const char *cache_path, int32_t *label_groups,
                       int32_t *tile_rows);
 
-/* Unrolled differentiation: K iterations with checkpoints every C iterations, then the
- * adjoint pass. Return SL_ERR_UNSUPPORTED in this build. */
-sl_status sl_unrolled_forward(sl_problem p, int32_t K, int32_t C, void *ckpt_ws,
-                              size_t bytes);
+/* Unrolled differentiation (gradients of a function of the read-out u after K iterations
+ * with respect to f, lambda and the additive values w, for learning data terms).
+ *
+ * The forward pass is the iteration of Sec. 4 run K times from the handle's current state;
+ * the reverse pass applies the adjoint of each iteration backwards: the transposed
+ * operators K and K^T, the Jacobian transposes of the ball projection (Prop. 5) and of the
+ * epigraph projections (Sec. 4, Fig. 2; the parabola by implicit differentiation of the
+ * foot, piecewise-linear parts by their segment or kink), and the data-term parameters
+ * (quadratic centre f, the hull vertices of straddling truncated-quadratic intervals, the
+ * linear term through w). Where a projection sits on the boundary between two parts, the
+ * part the forward pass chose is differentiated.
+ *
+ * sl_unrolled_workspace_size: bytes of device workspace for K iterations with a checkpoint
+ *   every C iterations: ceil(K/C) full states, one segment of C replayed states, the
+ *   adjoint state and accumulators (at most (ceil(K/C) (8k+1) + C (6k+1) + 11k + 5) planes of
+ *   4 H*W bytes, k = L-1).
+ * sl_unrolled_forward: runs K iterations (1 <= C <= K) and stores the checkpoints in the
+ *   caller's workspace `ckpt_ws` (device, 256-byte aligned, owned by the caller, must stay
+ *   valid until sl_unrolled_backward returns).
+ * sl_unrolled_backward: grad_u [H*W] (device) is the adjoint of the read-out u in the
+ *   caller's label units. Writes grad_f [H*W] (device, may be NULL), *grad_lambda (host,
+ *   may be NULL; reduced in FP64 in a fixed order) and grad_w [L][H*W] (device, may be NULL;
+ *   only for problems with additive values). The segments are replayed from their
+ *   checkpoints with the launch configuration of the forward pass, so the replay reproduces
+ *   the forward states bit for bit. Synchronises the handle's stream.
+ * Errors: SL_ERR_UNSUPPORTED for batches, BF16 storage and sampled data terms;
+ *   SL_ERR_INVALID_ARG if iterations ran between the forward and the backward pass. */
+sl_status sl_unrolled_workspace_size(sl_problem p, int32_t K, int32_t C, size_t *bytes);
+sl_status sl_unrolled_forward(sl_problem p, int32_t K, int32_t C, void *ckpt_ws, size_t bytes);
 sl_status sl_unrolled_backward(sl_problem p, const float *grad_u_dev, float *grad_f_dev,
                                double *grad_lambda, float *grad_w_dev);
 

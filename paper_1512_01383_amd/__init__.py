@@ -10,6 +10,7 @@ library is missing, every entry point raises.
 from __future__ import annotations
 
 import ctypes as C
+import ctypes as C_  # the same module; methods with a parameter named C use this name
 import os
 import re
 from typing import Optional
@@ -92,13 +93,17 @@ def lib():
         L.sl_batch_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.sl_set_graphs.argtypes = [vp, C.c_int32]
         L.sl_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sl_unrolled_workspace_size.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(sz)]
+        L.sl_unrolled_forward.argtypes = [vp, C.c_int32, C.c_int32, vp, sz]
+        L.sl_unrolled_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
         L.sl_destroy.argtypes = [vp]
         L.sl_destroy.restype = None
         for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
                      "sl_energy", "sl_state_size", "sl_save_state", "sl_load_state",
                      "sl_set_tiling", "sl_get_tiling", "sl_batch_workspace_size", "sl_batch_create",
                      "sl_batch_energy", "sl_batch_read_u", "sl_batch_info", "sl_set_graphs",
-                     "sl_autotune"):
+                     "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
+                     "sl_unrolled_backward"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -141,6 +146,7 @@ def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, norm
         d.M = len(obj.tau)
         d.tau = obj.tau.ctypes.data_as(C.POINTER(C.c_double))
         d.samples = obj._keep["samples"].data_ptr()
+    obj.has_w = tau is not None and int(rho) != RHO_SAMPLED
     d.lam = float(lam)
     d.tv = TV_ISO
     d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
@@ -220,6 +226,31 @@ class Problem:
         t = _dev_f32(t, self.device).reshape(-1)
         _check(lib().sl_load_state(self.h, C.c_void_p(t.data_ptr()), t.numel() * 4))
         self.stream.synchronize()
+
+    # ---- unrolled differentiation
+    def unrolled_forward(self, K: int, C: int):
+        """Run K iterations with a checkpoint every C (workspace allocated here and kept
+        until the next unrolled_forward or close)."""
+        torch = _torch()
+        n = C_.c_size_t()
+        _check(lib().sl_unrolled_workspace_size(self.h, int(K), int(C), C_.byref(n)))
+        self._uws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(lib().sl_unrolled_forward(self.h, int(K), int(C), C_.c_void_p(self._uws.data_ptr()), n.value))
+
+    def unrolled_backward(self, grad_u, want_f: bool = True, want_w: bool = True):
+        """Gradients of a function of the read-out u after unrolled_forward, given its
+        adjoint grad_u [H, W]: (grad_f [H, W] or None, grad_lambda, grad_w [L, H, W] or None)."""
+        torch = _torch()
+        gu = _dev_f32(grad_u, self.device).reshape(-1)
+        gf = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device) if want_f else None
+        gw = (torch.empty((self.k + 1, self.H, self.W), dtype=torch.float32, device=self.device)
+              if (want_w and self.has_w) else None)
+        gl = C_.c_double()
+        _check(lib().sl_unrolled_backward(self.h, C_.c_void_p(gu.data_ptr()),
+                                          C_.c_void_p(gf.data_ptr() if gf is not None else 0),
+                                          C_.byref(gl),
+                                          C_.c_void_p(gw.data_ptr() if gw is not None else 0)))
+        return gf, gl.value, gw
 
     def autotune(self, iters: int = 20, cache: Optional[str] = None):
         """Pick the fastest tiling (resets the iteration state); returns (groups, rows)."""

@@ -194,6 +194,11 @@ struct sl_problem_ {
   int graph_cfg = -1;
   bool use_graph = true;
 
+  // unrolled differentiation: caller's workspace of checkpoints, replay states and adjoints
+  char *uws = nullptr;
+  int uK = 0, uC = 0, ucfg = 0;
+  int64_t u_end = -1;
+
   ~sl_problem_() {
     for (sl_problem_ *q : sub) delete q;
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -546,6 +551,47 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
     if (changed && (s = batch_rebuild_items(P)) != SL_OK) return s;
   }
   if (done) *done = n;
+  return SL_OK;
+}
+
+struct ULayout {
+  int ncp;
+  size_t ckpt, useq, sseq, yseq, adj, cbar, wbar, lbar, lsum, total;
+};
+
+// Workspace of the unrolled pass: ceil(K/C) checkpoints of the full state, the replay of one
+// segment (u and s of states -1 .. C-1, (v, z, q, p) of states 0 .. C-1), the adjoint state
+// and the parameter-adjoint accumulators.
+ULayout unrolled_layout(const sl_problem_ *P, int K, int C) {
+  const size_t pl = (size_t)P->lay.ps * 4;
+  const int k = P->A.k;
+  ULayout U{};
+  U.ncp = (K + C - 1) / C;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  U.ckpt = take((size_t)U.ncp * (8 * k + 1) * pl);
+  U.useq = take((size_t)(C + 1) * k * pl);
+  U.sseq = take((size_t)(C + 1) * k * pl);
+  U.yseq = take((size_t)C * (4 * k + 1) * pl);
+  U.adj = take((size_t)(8 * k + 1) * pl);
+  U.cbar = take(pl);
+  U.wbar = take(P->add ? (size_t)(k + 1) * pl : 0);
+  U.lbar = take((size_t)P->lay.ps * 8);
+  U.lsum = take(8);
+  U.total = o;
+  return U;
+}
+
+sl_status unrolled_check(const sl_problem_ *P, int K, int C) {
+  if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation of a batch is not built");
+  if (P->bf16) return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation needs FP32 storage");
+  if (P->piece == SLI_SAMPLED)
+    return fail(SL_ERR_UNSUPPORTED, "gradients are defined for quadratic and truncated-quadratic data terms");
+  if (K < 1 || C < 1 || C > K) return fail(SL_ERR_INVALID_ARG, "need K >= 1 and 1 <= C <= K");
   return SL_OK;
 }
 
@@ -995,12 +1041,136 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
   return SL_OK;
 }
 
-sl_status sl_unrolled_forward(sl_problem, int32_t, int32_t, void *, size_t) {
-  return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation is not built");
+sl_status sl_unrolled_workspace_size(sl_problem P, int32_t K, int32_t C, size_t *bytes) {
+  if (!P || !bytes) return fail(SL_ERR_INVALID_ARG, "need a handle and bytes");
+  sl_status s = unrolled_check(P, K, C);
+  if (s != SL_OK) return s;
+  *bytes = unrolled_layout(P, K, C).total;
+  return SL_OK;
 }
 
-sl_status sl_unrolled_backward(sl_problem, const float *, float *, double *, float *) {
-  return fail(SL_ERR_UNSUPPORTED, "unrolled differentiation is not built");
+sl_status sl_unrolled_forward(sl_problem P, int32_t K, int32_t C, void *ws, size_t bytes) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  sl_status s = unrolled_check(P, K, C);
+  if (s != SL_OK) return s;
+  const ULayout U = unrolled_layout(P, K, C);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (bytes < U.total)
+    return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, U.total);
+  P->uws = nullptr;
+  char *w = (char *)ws;
+  const int k = P->A.k;
+  const size_t pl = (size_t)P->lay.ps * 4;
+  for (int c = 0; c < U.ncp; c++) {
+    // checkpoint c: [up][u][sp][s][v][z][q][px][py] of the state before iteration c*C
+    char *ck = w + U.ckpt + (size_t)c * (8 * k + 1) * pl;
+    const void *src[7] = {P->ubuf((P->iu + 2) % 3), P->ubuf(P->iu), P->sbuf(1 - P->is), P->sbuf(P->is),
+                          P->ws + P->lay.off_v, P->ws + P->lay.off_z, P->ws + P->lay.off_qd};
+    const int np[7] = {k, k, k, k, k, k, 1};
+    for (int g = 0; g < 7; g++) {
+      HIPCHK(hipMemcpyAsync(ck, src[g], np[g] * pl, hipMemcpyDeviceToDevice, P->st), "checkpoint");
+      ck += np[g] * pl;
+    }
+    HIPCHK(hipMemcpyAsync(ck, P->pbuf(P->ip), 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "checkpoint");
+    s = enqueue_iters(P, std::min(C, K - c * C));
+    if (s != SL_OK) return s;
+  }
+  P->uws = w;
+  P->uK = K;
+  P->uC = C;
+  P->ucfg = P->cfg;
+  P->u_end = P->iters;
+  return SL_OK;
+}
+
+sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f, double *grad_lambda,
+                               float *grad_w) {
+  if (!P || !grad_u) return fail(SL_ERR_INVALID_ARG, "need a handle and grad_u");
+  if (!P->uws || P->iters != P->u_end)
+    return fail(SL_ERR_INVALID_ARG, "needs sl_unrolled_forward immediately before (no iterations since)");
+  if (grad_w && !P->add) return fail(SL_ERR_INVALID_ARG, "grad_w needs a problem with additive values");
+  const int K = P->uK, C = P->uC, k = P->A.k;
+  const ULayout U = unrolled_layout(P, K, C);
+  char *w = P->uws;
+  const long long ps = P->lay.ps, N = P->lay.N;
+  const size_t pl = (size_t)ps * 4;
+  float *adj = (float *)(w + U.adj);
+  AdjBuf B;
+  B.u = adj;
+  B.up = adj + (size_t)k * ps;
+  B.s = adj + (size_t)2 * k * ps;
+  B.sp = adj + (size_t)3 * k * ps;
+  B.v = adj + (size_t)4 * k * ps;
+  B.z = adj + (size_t)5 * k * ps;
+  B.px = adj + (size_t)6 * k * ps;
+  B.py = adj + (size_t)7 * k * ps;
+  B.q = adj + (size_t)8 * k * ps;
+  AdjAcc Q;
+  Q.fn = (const float *)(P->ws + P->lay.off_fn);
+  Q.wadd = (const float *)(P->ws + P->lay.off_w);
+  Q.sinfo = (const unsigned *)(P->ws + P->lay.off_sinfo);
+  Q.cbar = (float *)(w + U.cbar);
+  Q.wbar = (float *)(w + U.wbar);
+  Q.lbar = (double *)(w + U.lbar);
+  HIPCHK(launch_fill_zero(w + U.adj, U.lsum - U.adj, P->st), "zero adjoints");
+  HIPCHK(launch_adj_readout(grad_u, P->ubuf(P->iu), B.u, P->A, (float)P->scale, P->st), "read-out adjoint");
+
+  float *useq = (float *)(w + U.useq), *sseq = (float *)(w + U.sseq);
+  char *yseq = w + U.yseq;
+  const size_t yslot = (size_t)(4 * k + 1) * pl;
+  auto uslot = [&](int j) { return useq + (size_t)j * k * ps; };   // u_{j-1}
+  auto sslot = [&](int j) { return sseq + (size_t)j * k * ps; };
+  auto yv = [&](int j) { return (float *)(yseq + (size_t)j * yslot); };
+  auto yz = [&](int j) { return yv(j) + (size_t)k * ps; };
+  auto yq = [&](int j) { return yv(j) + (size_t)2 * k * ps; };
+  auto yp = [&](int j) { return yv(j) + (size_t)(2 * k + 1) * ps; };
+  for (int c = U.ncp - 1; c >= 0; c--) {
+    const int n = std::min(C, K - c * C);
+    const char *ck = w + U.ckpt + (size_t)c * (8 * k + 1) * pl;
+    HIPCHK(hipMemcpyAsync(uslot(0), ck, 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "restore");
+    HIPCHK(hipMemcpyAsync(sslot(0), ck + 2 * k * pl, 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "restore");
+    HIPCHK(hipMemcpyAsync(yv(0), ck + 4 * k * pl, yslot, hipMemcpyDeviceToDevice, P->st), "restore");
+    // replay the segment, keeping every state (same launch configuration as the forward pass)
+    for (int j = 0; j + 1 < n; j++) {
+      HIPCHK(hipMemcpyAsync(sslot(j + 2), sslot(j), k * pl, hipMemcpyDeviceToDevice, P->st), "replay");
+      HIPCHK(hipMemcpyAsync(yv(j + 1), yv(j), (2 * k + 1) * pl, hipMemcpyDeviceToDevice, P->st), "replay");
+      IterPtrs<float> R = iter_ptrs_f(P);
+      R.u = uslot(j + 1);
+      R.up = uslot(j);
+      R.un = uslot(j + 2);
+      R.s = sslot(j + 1);
+      R.sp = sslot(j + 2);
+      R.v = yv(j + 1);
+      R.z = yz(j + 1);
+      R.qd = yq(j + 1);
+      R.pin = yp(j);
+      R.pout = yp(j + 1);
+      HIPCHK(launch_pdhg_iter(P->piece, P->add, false, P->ucfg, P->A, &R, P->st), "replay iteration");
+    }
+    for (int j = n - 1; j >= 0; j--) {
+      AdjState X;
+      X.u = uslot(j + 1);
+      X.up = uslot(j);
+      X.s = sslot(j + 1);
+      X.sp = sslot(j);
+      X.v = yv(j);
+      X.z = yz(j);
+      X.px = yp(j);
+      X.py = yp(j) + (size_t)k * ps;
+      HIPCHK(launch_adj_dual(P->piece, P->add, X, B, Q, P->A, P->st), "adjoint (dual steps)");
+      HIPCHK(launch_adj_primal(B, P->A, P->st), "adjoint (primal step)");
+    }
+  }
+  HIPCHK(launch_adj_finish(Q.cbar, Q.wbar, P->add ? k + 1 : 0, grad_f, grad_w, N, ps, (float)(1.0 / P->scale),
+                           P->st),
+         "gradients");
+  double *lsum = (double *)(w + U.lsum);
+  HIPCHK(launch_sum_double(Q.lbar, N, lsum, P->st), "lambda reduction");
+  double hl = 0.0;
+  HIPCHK(hipMemcpyAsync(&hl, lsum, sizeof(double), hipMemcpyDeviceToHost, P->st), "lambda copy");
+  HIPCHK(hipStreamSynchronize(P->st), "backward sync");
+  if (grad_lambda) *grad_lambda = hl * P->scale;
+  return SL_OK;
 }
 
 sl_status sl_set_tiling(sl_problem P, int32_t label_groups, int32_t tile_rows) {

@@ -120,3 +120,28 @@ hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterA
 hipError_t launch_pack_state(const void *const *planes, const int *bf16, int nplanes,
                              long long N, long long ps, float *dst, int unpack,
                              hipStream_t st);
+
+// Reverse pass (adjoint.hip): one state of the unrolled forward pass (read only), the
+// adjoint of a state (updated in place; q is one plane) and the accumulators of the
+// parameter adjoints (data centre c per pixel, additive values w per label and pixel,
+// lambda per pixel in double).
+struct AdjState {
+  const float *u, *up, *s, *sp, *v, *z, *px, *py;
+};
+struct AdjBuf {
+  float *u, *up, *s, *sp, *v, *z, *px, *py, *q;
+};
+struct AdjAcc {
+  const float *fn, *wadd;
+  const unsigned *sinfo;
+  float *cbar, *wbar;
+  double *lbar;
+};
+hipError_t launch_adj_dual(int piece, bool add, const AdjState &X, const AdjBuf &B, const AdjAcc &Q,
+                           const IterArgs &A, hipStream_t st);
+hipError_t launch_adj_primal(const AdjBuf &B, const IterArgs &A, hipStream_t st);
+hipError_t launch_adj_readout(const float *gu, const float *u, float *ub, const IterArgs &A, float scale,
+                              hipStream_t st);
+hipError_t launch_adj_finish(const float *cbar, const float *wbar, int nw, float *gf, float *gw, long long N,
+                             long long ps, float iscale, hipStream_t st);
+hipError_t launch_sum_double(const double *a, long long n, double *out, hipStream_t st);

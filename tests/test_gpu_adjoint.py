@@ -1,0 +1,182 @@
+"""Unrolled differentiation on the GPU (sl_unrolled_forward / sl_unrolled_backward and the
+torch.autograd.Function) against the FP64 oracle's reverse pass. GPU only.
+
+Tolerances. The FP32 iterates agree with the FP64 oracle to about 1e-7 relative; the
+adjoint recursion adds rounding of order K * 2^-24 per step count. Where a projection input
+lies within rounding of the boundary between two parts of a graph (segment / kink, ball
+surface), FP32 and FP64 may pick different parts, which changes that entry's local Jacobian;
+such points are rare and their effect stays local. Held to: relative L2 error of the f and w
+gradients <= 1e-3 (2e-3 for the 200-iteration 256 x 256 workload) with every entry within
+2e-2 of the largest magnitude, the lambda gradient within 1e-4 relative (measured: 2e-7 ..
+9e-4, lambda 1e-6 .. 6e-6).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1512_01383_amd as S  # noqa: E402
+from paper_1512_01383_amd.autograd import unrolled_solve  # noqa: E402
+
+
+def _tq_w(L, H, Wd, seed, rng):
+    wl = W.truncated_quadratic(L=L, H=H, W=Wd, seed=seed)
+    wl.tau = wl.gamma.copy()
+    wl.samples = rng.normal(0, 0.02, (L, H, Wd)).astype(np.float32)
+    return wl
+
+
+def _quad_w(H, Wd, rng):
+    gam = np.array([0.0, 0.3, 0.5, 1.0])
+    return W.Workload("qw", H, Wd, gam, W.QUAD, 0.3, f=rng.uniform(0, 1, (H, Wd)).astype(np.float32),
+                      a=2.0, tau=gam.copy(), samples=rng.normal(0, 0.1, (4, H, Wd)).astype(np.float32))
+
+
+def _cases():
+    rng = np.random.default_rng(5)
+    return [("quad_w", _quad_w(20, 66, rng), 25, 7),
+            ("tq_w_L6", _tq_w(6, 40, 70, 3, rng), 40, 7),
+            ("tq_w_L8", _tq_w(8, 33, 130, 4, rng), 60, 20),
+            ("tq_L5_no_w", W.truncated_quadratic(L=5, H=9, W=131, seed=12), 30, 8)]
+
+
+CASES = _cases()
+
+
+def _gpu_grads(wl, K, C, g):
+    p = S.Problem.from_workload(wl)
+    p.unrolled_forward(K, C)
+    _, u = p.read_u()
+    gu = 2.0 * (u - torch.as_tensor(g, dtype=torch.float32, device=u.device))
+    gf, gl, gw = p.unrolled_backward(gu)
+    torch.cuda.synchronize()
+    out = (u.cpu().numpy(), gf.cpu().numpy(), gl, None if gw is None else gw.cpu().numpy())
+    p.close()
+    return out
+
+
+def _check_close(got, ref, name, l2=1e-3):
+    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+    worst = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
+    print(f"{name}: rel L2 {err:.2e}, worst entry {worst:.2e} of max", flush=True)
+    assert err <= l2 and worst <= 2e-2, (name, err, worst)
+
+
+@pytest.mark.parametrize("name,wl,K,C", CASES, ids=[c[0] for c in CASES])
+def test_gradients_match_oracle_reverse_pass(orc, name, wl, K, C):
+    rng = np.random.default_rng(99)
+    g = rng.uniform(0, 1, (wl.H, wl.W))
+    o = orc.Problem(wl)
+    o.unrolled_forward(K)
+    _, uo = o.read_u()
+    print(f"case {name}: {wl.H}x{wl.W} L={wl.L} K={K} C={C}", flush=True)
+    u, gf, gl, gw = _gpu_grads(wl, K, C, g)
+    assert np.abs(u - uo).max() <= 1e-5
+    # the loss adjoint is taken at the GPU's own u (a function of the GPU forward pass)
+    gfo, glo, gwo = o.unrolled_backward(2.0 * (u.astype(np.float64) - g))
+    _check_close(gf, gfo, "grad f")
+    assert abs(gl - glo) <= 1e-4 * abs(glo), (gl, glo)
+    if wl.tau is not None:
+        _check_close(gw, gwo, "grad w")
+    else:
+        assert gw is None and gwo is None
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    """The replay from a checkpoint reproduces the forward states bit for bit, so every
+    checkpoint interval gives the same gradients."""
+    rng = np.random.default_rng(1)
+    wl = _tq_w(6, 24, 70, 8, rng)
+    g = rng.uniform(0, 1, (wl.H, wl.W))
+    ref = _gpu_grads(wl, 23, 5, g)
+    for C in (1, 4, 23):
+        got = _gpu_grads(wl, 23, C, g)
+        assert np.array_equal(got[1], ref[1]) and got[2] == ref[2] and np.array_equal(got[3], ref[3]), C
+
+
+def test_backward_is_reproducible_and_leaves_state():
+    rng = np.random.default_rng(2)
+    wl = _tq_w(5, 30, 64, 6, rng)
+    g = torch.as_tensor(rng.uniform(0, 1, (wl.H, wl.W)), dtype=torch.float32, device="cuda:0")
+    p = S.Problem.from_workload(wl)
+    p.unrolled_forward(15, 4)
+    ul0, u = p.read_u()
+    a = p.unrolled_backward(2 * (u - g))
+    b = p.unrolled_backward(2 * (u - g))
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and a[1] == b[1] and torch.equal(a[2], b[2])
+    ul1, _ = p.read_u()
+    assert torch.equal(ul0, ul1)          # the backward pass does not touch the iterate
+    p.close()
+
+
+def test_autograd_function_matches_c_abi(orc):
+    rng = np.random.default_rng(3)
+    wl = _tq_w(8, 32, 48, 7, rng)
+    dev = torch.device("cuda:0")
+    f = torch.as_tensor(wl.f, device=dev).requires_grad_(True)
+    lam = torch.tensor(wl.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    w = torch.as_tensor(wl.samples, device=dev).requires_grad_(True)
+    tgt = torch.as_tensor(rng.uniform(0, 1, (wl.H, wl.W)), dtype=torch.float32, device=dev)
+    u = unrolled_solve(f, lam, w, gamma=wl.gamma, a=wl.a, nu=wl.nu, K=30, C=10)
+    loss = ((u - tgt) ** 2).sum()
+    loss.backward()
+    u2, gf, gl, gw = _gpu_grads(wl, 30, 10, tgt.cpu().numpy())
+    assert np.array_equal(u.detach().cpu().numpy(), u2)
+    assert np.array_equal(f.grad.cpu().numpy(), gf)
+    assert np.array_equal(w.grad.cpu().numpy(), gw)
+    assert lam.grad.item() == gl
+
+
+def test_unrolled_errors():
+    rng = np.random.default_rng(4)
+    wl = _tq_w(5, 8, 20, 2, rng)
+    p = S.Problem.from_workload(wl)
+    gu = torch.zeros((wl.H, wl.W), device="cuda:0")
+    with pytest.raises(S.SublabelError):
+        p.unrolled_backward(gu)                    # no forward pass
+    with pytest.raises(S.SublabelError):
+        p.unrolled_forward(5, 6)                   # C > K
+    p.unrolled_forward(5, 2)
+    p.run(1)
+    with pytest.raises(S.SublabelError):
+        p.unrolled_backward(gu)                    # iterations since the forward pass
+    p.close()
+    pb = S.Problem.from_workload(wl, storage="bf16")
+    with pytest.raises(S.SublabelError):
+        pb.unrolled_forward(5, 2)
+    pb.close()
+    M = 9
+    smp = W.Workload("s", 6, 7, np.array([0.0, 4.0, 8.0]), W.SAMPLED, 0.3, tau=np.arange(float(M)),
+                     samples=rng.uniform(0, 1, (M, 6, 7)).astype(np.float32))
+    ps = S.Problem.from_workload(smp)
+    with pytest.raises(S.SublabelError):
+        ps.unrolled_forward(4, 2)
+    ps.close()
+
+
+@pytest.mark.timeout(300)
+def test_differentiation_workload_full_size(orc):
+    """256x256, L = 8, K = 200 unrolled iterations, checkpoint every 20: the gradients of the
+    squared error against the clean image, w.r.t. f, lambda and the 8 x 256 x 256 additive
+    values, against the oracle's reverse pass over the same 200 iterations."""
+    orc.set_threads(16)
+    wl = W.differentiation()
+    u, gf, gl, gw = _gpu_grads(wl, 200, 20, wl.target)
+    o = orc.Problem(wl)
+    o.unrolled_forward(200)
+    _, uo = o.read_u()
+    assert np.abs(u - uo).max() <= 1e-5
+    gfo, glo, gwo = o.unrolled_backward(2.0 * (u.astype(np.float64) - wl.target))
+    # 200 iterations over 458k pixel-labels meet more part-boundary decisions (p on the
+    # ball surface in flat regions): measured rel L2 5.6e-4 (f) and 8.9e-4 (w)
+    _check_close(gf, gfo, "grad f", l2=2e-3)
+    _check_close(gw, gwo, "grad w", l2=2e-3)
+    assert abs(gl - glo) <= 1e-4 * abs(glo), (gl, glo)
