@@ -17,12 +17,12 @@
 // K); kernel 2 (k_adj_primal) does 5, walking upwards (prefix sums of K^T). Both update the
 // adjoint state in place: kernel 1 reads the u / s adjoints at neighbours and writes only
 // the dual adjoints, kernel 2 reads dual adjoints at neighbours and writes only u / s ones.
+#include <algorithm>
+
 #include "device_math.hpp"
 #include "internal.hpp"
 
 namespace {
-
-constexpr int TW = 64, TH = 4;
 
 // ------------------------------------------------------------------ projection adjoints
 
@@ -263,39 +263,62 @@ __device__ __forceinline__ void tq_chain_vjp(float a, float c, float nu, float g
   pl.vjp(yb, wb, y0b, w0b, cb);
 }
 
-__device__ __forceinline__ int tile_of_block() {
-  const int nb = (int)gridDim.x;
-  const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
-  const int per = nb >> 3, rem = nb & 7;
-  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-}
-
 __device__ __forceinline__ float tau_of(int r, int c, int H, int W) {
   const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
   return 1.f / (1.f + (float)deg);
 }
 
 // ------------------------------------------------------------------ kernel 1: steps 1-4
+//
+// A block covers 64 consecutive pixels (one wavefront) times T label chunks (one wavefront
+// per chunk), so small images still give enough wavefronts. The label coupling (suffix sums
+// of h sbar and h Kbar_s, the per-pixel sums of the parameter adjoints, the additive value
+// shared by two neighbouring chunks) goes through LDS in a fixed order.
 
-template <int PIECE, bool ADD>
-__global__ __launch_bounds__(TW *TH) void k_adj_dual(AdjState X, AdjBuf B, AdjAcc Q, IterArgs A) {
+template <int PIECE, bool ADD, int T>
+__global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAcc Q, IterArgs A) {
+  __shared__ float ex_sb[T][64], ex_ks[T][64], ex_cb[T][64], ex_lb[T][64], ex_w[T][64];
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps;
-  const int ntc = (W + TW - 1) / TW;
-  const int tile = tile_of_block();
-  const int r = (tile / ntc) * TH + (int)(threadIdx.x >> 6);
-  const int c = (tile % ntc) * TW + (int)(threadIdx.x & 63);
-  if (r >= H || c >= W) return;
-  const long long x = (long long)r * W + c;
+  const int lane = (int)(threadIdx.x & 63);
+  const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int xi = (int)blockIdx.x * 64 + lane;
+  const bool in = xi < H * W;
+  const int r = in ? xi / W : 0, c = in ? xi - r * W : 0;
+  const long long x = in ? xi : 0;
   const bool hr = c < W - 1, hd = r < H - 1;
   const long long xr = hr ? x + 1 : x, xd = hd ? x + W : x;
   const float tau_u = tau_of(r, c, H, W);
   const float tau_r = hr ? tau_of(r, c + 1, H, W) : 0.f, tau_d = hd ? tau_of(r + 1, c, H, W) : 0.f;
-  const float fc = ldv(Q.fn, x);
+  const int ch = (k + T - 1) / T;
+  const int i0 = min(k, t * ch), i1 = min(k, i0 + ch);
 
-  // straddling truncated-quadratic intervals of this pixel (as the forward pass uses them)
+  // phase 1: this chunk's sums of h sbar and h Kbar_s
+  float tsb = 0.f, tks = 0.f;
+  if (in)
+    for (int i = i0; i < i1; i++) {
+      const size_t o = (size_t)i * ps;
+      tsb += A.h[i] * (2.f * X.s[o + x] - X.sp[o + x]);
+      tks += A.h[i] * (-A.taus[i] * B.s[o + x]);
+    }
+  ex_sb[t][lane] = tsb;
+  ex_ks[t][lane] = tks;
+  __syncthreads();
+  float suf_sb = 0.f, suf_ks = 0.f, tot_ks = 0.f;
+#pragma unroll
+  for (int g = 0; g < T; g++) {
+    const float eks = ex_ks[g][lane];
+    tot_ks += eks;
+    if (g > t) {
+      suf_sb += ex_sb[g][lane];
+      suf_ks += eks;
+    }
+  }
+
+  // phase 2: the chunk's labels, downwards
+  const float fc = in ? ldv(Q.fn, x) : 0.f;
   int st0 = -1, st1 = -1, ml0 = 0, mr0 = 0, ml1 = 0, mr1 = 0;
-  if (PIECE == SLI_TRUNC) {
+  if (PIECE == SLI_TRUNC && in) {
     const unsigned info = Q.sinfo[x];
     const unsigned f0 = info, f1 = info >> 13;
     if ((f0 & 31u) != 31u) {
@@ -309,91 +332,121 @@ __global__ __launch_bounds__(TW *TH) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
       mr1 = (int)((f1 >> 9) & 15u);
     }
   }
-
-  float suf_sb = 0.f, suf_ks = 0.f;     // sum_{j > i} h_j sbar_j and h_j Kbar_s,j
   float cb_acc = 0.f, lb_acc = 0.f;
-  float wb_up = 0.f;                     // adjoint of w_{i+1} collected so far
-  float w_up = ADD ? Q.wadd[(size_t)k * ps + x] : 0.f;
-  for (int i = k - 1; i >= 0; i--) {
-    const size_t o = (size_t)i * ps;
-    const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
-    // forward quantities at this state
-    const float ub = 2.f * X.u[o + x] - X.up[o + x];
-    const float sb = 2.f * X.s[o + x] - X.sp[o + x];
-    const float gx = hr ? (2.f * X.u[o + xr] - X.up[o + xr]) - ub : 0.f;
-    const float gy = hd ? (2.f * X.u[o + xd] - X.up[o + xd]) - ub : 0.f;
-    const float v0 = X.v[o + x] + A.sig[i] * (ub + suf_sb - g0 * sb);
-    const float z0 = X.z[o + x] + A.sig[i] * sb;
-    const float ax = X.px[o + x] + A.sig_p * gx, ay = X.py[o + x] + A.sig_p * gy;
-    suf_sb += hi * sb;
-    // step 1: K applied to -T (u', s') adjoints
-    const float Ku = -tau_u * B.u[o + x];
-    const float Ks = -A.taus[i] * B.s[o + x];
-    const float vbt = B.v[o + x] + Ku - g0 * Ks + suf_ks;
-    const float zbt = B.z[o + x] + Ks;
-    const float pbx = B.px[o + x] + (hr ? -tau_r * B.u[o + xr] - Ku : 0.f);
-    const float pby = B.py[o + x] + (hd ? -tau_d * B.u[o + xd] - Ku : 0.f);
-    suf_ks += hi * Ks;
-    // step 3: ball
-    float abx, aby, rb;
-    ball_vjp(ax, ay, A.lam * hi, pbx, pby, abx, aby, rb);
-    lb_acc += hi * rb;
-    // step 4: epigraph, in the coordinates shifted by the additive linear term
-    float y = v0 * ih, w = z0 * ih;
-    float bs = 0.f, cs = 0.f, w_lo = 0.f;
-    if (ADD) {
-      w_lo = Q.wadd[o + x];
-      bs = (w_up - w_lo) * ih;
-      cs = -w_lo + bs * g0;
-      y -= bs;
-      w -= cs;
+  float top = 0.f, wb_low = 0.f;        // additive-value adjoints at the chunk's ends
+  float w_up = (ADD && in && i0 < i1) ? Q.wadd[(size_t)i1 * ps + x] : 0.f;
+  if (in)
+    for (int i = i1 - 1; i >= i0; i--) {
+      const size_t o = (size_t)i * ps;
+      const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
+      // forward quantities at this state
+      const float ub = 2.f * X.u[o + x] - X.up[o + x];
+      const float sb = 2.f * X.s[o + x] - X.sp[o + x];
+      const float gx = hr ? (2.f * X.u[o + xr] - X.up[o + xr]) - ub : 0.f;
+      const float gy = hd ? (2.f * X.u[o + xd] - X.up[o + xd]) - ub : 0.f;
+      const float v0 = X.v[o + x] + A.sig[i] * (ub + suf_sb - g0 * sb);
+      const float z0 = X.z[o + x] + A.sig[i] * sb;
+      const float ax = X.px[o + x] + A.sig_p * gx, ay = X.py[o + x] + A.sig_p * gy;
+      suf_sb += hi * sb;
+      // step 1: K applied to -T (u', s') adjoints
+      const float Ku = -tau_u * B.u[o + x];
+      const float Ks = -A.taus[i] * B.s[o + x];
+      const float vbt = B.v[o + x] + Ku - g0 * Ks + suf_ks;
+      const float zbt = B.z[o + x] + Ks;
+      const float pbx = B.px[o + x] + (hr ? -tau_r * B.u[o + xr] - Ku : 0.f);
+      const float pby = B.py[o + x] + (hd ? -tau_d * B.u[o + xd] - Ku : 0.f);
+      suf_ks += hi * Ks;
+      // step 3: ball
+      float abx, aby, rb;
+      ball_vjp(ax, ay, A.lam * hi, pbx, pby, abx, aby, rb);
+      lb_acc += hi * rb;
+      // step 4: epigraph, in the coordinates shifted by the additive linear term
+      float y = v0 * ih, w = z0 * ih;
+      float bs = 0.f, cs = 0.f, w_lo = 0.f;
+      if (ADD) {
+        w_lo = Q.wadd[o + x];
+        bs = (w_up - w_lo) * ih;
+        cs = -w_lo + bs * g0;
+        y -= bs;
+        w -= cs;
+      }
+      const float yb = hi * vbt, wb = hi * zbt;
+      float y0b, w0b, cb = 0.f;
+      if (PIECE == SLI_QUAD) {
+        quad_vjp(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b, cb);
+      } else if (i == st0 || i == st1) {
+        const int ml = i == st0 ? ml0 : ml1, mr = i == st0 ? mr0 : mr1;
+        tq_chain_vjp(A.a, fc, A.nu, g0, g1, ml, mr, y, w, yb, wb, y0b, w0b, cb);
+      } else if (fc - A.del <= g0 && g1 <= fc + A.del) {
+        quad_vjp(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b, cb);
+      } else {
+        flat_vjp(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b);
+      }
+      cb_acc += cb;
+      if (ADD) {
+        // out = Proj(in - shift) + shift: the shift's adjoint is out_b - in_b
+        const float bsb = yb - y0b, csb = wb - w0b;
+        const float upper = bsb * ih + csb * g0 * ih;          // to w_{i+1}
+        const float lower = -bsb * ih - csb * (1.f + g0 * ih);  // to w_i
+        if (i == i1 - 1)
+          top = upper;
+        else
+          Q.wbar[(size_t)(i + 1) * ps + x] += upper + wb_low;
+        wb_low = lower;
+        w_up = w_lo;
+      }
+      B.v[o + x] = y0b * ih;
+      B.z[o + x] = w0b * ih;
+      B.px[o + x] = abx;
+      B.py[o + x] = aby;
     }
-    const float yb = hi * vbt, wb = hi * zbt;
-    float y0b, w0b, cb = 0.f;
-    if (PIECE == SLI_QUAD) {
-      quad_vjp(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b, cb);
-    } else if (i == st0 || i == st1) {
-      const int ml = i == st0 ? ml0 : ml1, mr = i == st0 ? mr0 : mr1;
-      tq_chain_vjp(A.a, fc, A.nu, g0, g1, ml, mr, y, w, yb, wb, y0b, w0b, cb);
-    } else if (fc - A.del <= g0 && g1 <= fc + A.del) {
-      quad_vjp(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b, cb);
-    } else {
-      flat_vjp(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b);
+  ex_cb[t][lane] = cb_acc;
+  ex_lb[t][lane] = lb_acc;
+  ex_w[t][lane] = wb_low;
+  __syncthreads();
+  if (!in) return;
+  if (ADD && i0 < i1) Q.wbar[(size_t)i1 * ps + x] += top + (i1 < k ? ex_w[t + 1][lane] : 0.f);
+  if (t == 0) {
+    float cs_ = 0.f, ls_ = 0.f;
+#pragma unroll
+    for (int g = 0; g < T; g++) {
+      cs_ += ex_cb[g][lane];
+      ls_ += ex_lb[g][lane];
     }
-    cb_acc += cb;
-    if (ADD) {
-      // out = Proj(in - shift) + shift: the shift's adjoint is out_b - in_b
-      const float bsb = yb - y0b, csb = wb - w0b;
-      wb_up += bsb * ih + csb * g0 * ih;
-      Q.wbar[(size_t)(i + 1) * ps + x] += wb_up;
-      wb_up = -bsb * ih - csb * (1.f + g0 * ih);
-      w_up = w_lo;
-    }
-    B.v[o + x] = y0b * ih;
-    B.z[o + x] = w0b * ih;
-    B.px[o + x] = abx;
-    B.py[o + x] = aby;
+    if (ADD) Q.wbar[x] += ex_w[0][lane];
+    B.q[x] -= tot_ks;               // step 2: q' = q + sigma_q (K_q xbar - 1), K_q = -sum h s
+    Q.cbar[x] += cs_;
+    Q.lbar[x] += (double)ls_;
   }
-  if (ADD) Q.wbar[x] += wb_up;
-  B.q[x] -= suf_ks;                 // step 2: q' = q + sigma_q (K_q xbar - 1), K_q = -sum h s
-  Q.cbar[x] += cb_acc;
-  Q.lbar[x] += (double)lb_acc;
 }
 
 // ------------------------------------------------------------------ kernel 2: step 5
 
-__global__ __launch_bounds__(TW *TH) void k_adj_primal(AdjBuf B, IterArgs A) {
+template <int T>
+__global__ __launch_bounds__(64 * T) void k_adj_primal(AdjBuf B, IterArgs A) {
+  __shared__ float ex_v[T][64];
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps;
-  const int ntc = (W + TW - 1) / TW;
-  const int tile = tile_of_block();
-  const int r = (tile / ntc) * TH + (int)(threadIdx.x >> 6);
-  const int c = (tile % ntc) * TW + (int)(threadIdx.x & 63);
-  if (r >= H || c >= W) return;
-  const long long x = (long long)r * W + c;
+  const int lane = (int)(threadIdx.x & 63);
+  const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int xi = (int)blockIdx.x * 64 + lane;
+  const bool in = xi < H * W;
+  const int r = in ? xi / W : 0, c = in ? xi - r * W : 0;
+  const long long x = in ? xi : 0;
+  const int ch = (k + T - 1) / T;
+  const int i0 = min(k, t * ch), i1 = min(k, i0 + ch);
+  float tv = 0.f;
+  if (in)
+    for (int i = i0; i < i1; i++) tv += A.sig[i] * B.v[(size_t)i * ps + x];
+  ex_v[t][lane] = tv;
+  __syncthreads();
+  if (!in) return;
+  float pre = 0.f;   // sum_{j < i} Kbar_v,j
+#pragma unroll
+  for (int g = 0; g < T; g++)
+    if (g < t) pre += ex_v[g][lane];
   const float Kq = A.sig_q * B.q[x];
-  float pre = 0.f;
-  for (int i = 0; i < k; i++) {
+  for (int i = i0; i < i1; i++) {
     const size_t o = (size_t)i * ps;
     const float Kv = A.sig[i] * B.v[o + x];
     const float Kz = A.sig[i] * B.z[o + x];
@@ -410,6 +463,18 @@ __global__ __launch_bounds__(TW *TH) void k_adj_primal(AdjBuf B, IterArgs A) {
     B.up[o + x] = -ubb;
     B.s[o + x] = st + 2.f * sbb;
     B.sp[o + x] = -sbb;
+  }
+}
+
+// two device-to-device copies of whole planes in one launch (replay bookkeeping)
+__global__ void k_copy2(const float4 *s0, float4 *d0, long long n0, const float4 *s1, float4 *d1,
+                        long long n1) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n0 + n1; j += stride) {
+    if (j < n0)
+      d0[j] = s0[j];
+    else
+      d1[j - n0] = s1[j - n0];
   }
 }
 
@@ -452,28 +517,63 @@ __global__ __launch_bounds__(1024) void k_sum_double(const double *a, long long 
 
 }  // namespace
 
-hipError_t launch_adj_dual(int piece, bool add, const AdjState &X, const AdjBuf &B, const AdjAcc &Q,
-                           const IterArgs &A, hipStream_t st) {
-  const int nt = ((A.W + TW - 1) / TW) * ((A.H + TH - 1) / TH);
+// label chunks per pixel: enough wavefronts for the chip (>= 4096) on small images
+int adj_chunks(const IterArgs &A) {
+  const long long waves = ((long long)A.H * A.W + 63) / 64;
+  int T = 1;
+  while (T < 8 && T < A.k && waves * T < 4096) T *= 2;
+  return T;
+}
+
+template <int T>
+hipError_t adj_dual_t(int piece, bool add, const AdjState &X, const AdjBuf &B, const AdjAcc &Q,
+                      const IterArgs &A, hipStream_t st) {
+  const unsigned nb = (unsigned)(((long long)A.H * A.W + 63) / 64);
   if (piece == SLI_QUAD) {
     if (add)
-      hipLaunchKernelGGL((k_adj_dual<SLI_QUAD, true>), dim3(nt), dim3(TW * TH), 0, st, X, B, Q, A);
+      hipLaunchKernelGGL((k_adj_dual<SLI_QUAD, true, T>), dim3(nb), dim3(64 * T), 0, st, X, B, Q, A);
     else
-      hipLaunchKernelGGL((k_adj_dual<SLI_QUAD, false>), dim3(nt), dim3(TW * TH), 0, st, X, B, Q, A);
+      hipLaunchKernelGGL((k_adj_dual<SLI_QUAD, false, T>), dim3(nb), dim3(64 * T), 0, st, X, B, Q, A);
   } else if (piece == SLI_TRUNC) {
     if (add)
-      hipLaunchKernelGGL((k_adj_dual<SLI_TRUNC, true>), dim3(nt), dim3(TW * TH), 0, st, X, B, Q, A);
+      hipLaunchKernelGGL((k_adj_dual<SLI_TRUNC, true, T>), dim3(nb), dim3(64 * T), 0, st, X, B, Q, A);
     else
-      hipLaunchKernelGGL((k_adj_dual<SLI_TRUNC, false>), dim3(nt), dim3(TW * TH), 0, st, X, B, Q, A);
+      hipLaunchKernelGGL((k_adj_dual<SLI_TRUNC, false, T>), dim3(nb), dim3(64 * T), 0, st, X, B, Q, A);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+hipError_t launch_adj_dual(int piece, bool add, const AdjState &X, const AdjBuf &B, const AdjAcc &Q,
+                           const IterArgs &A, hipStream_t st) {
+  switch (adj_chunks(A)) {
+    case 1: return adj_dual_t<1>(piece, add, X, B, Q, A, st);
+    case 2: return adj_dual_t<2>(piece, add, X, B, Q, A, st);
+    case 4: return adj_dual_t<4>(piece, add, X, B, Q, A, st);
+    default: return adj_dual_t<8>(piece, add, X, B, Q, A, st);
+  }
+}
+
 hipError_t launch_adj_primal(const AdjBuf &B, const IterArgs &A, hipStream_t st) {
-  const int nt = ((A.W + TW - 1) / TW) * ((A.H + TH - 1) / TH);
-  hipLaunchKernelGGL(k_adj_primal, dim3(nt), dim3(TW * TH), 0, st, B, A);
+  const unsigned nb = (unsigned)(((long long)A.H * A.W + 63) / 64);
+  switch (adj_chunks(A)) {
+    case 1: hipLaunchKernelGGL(k_adj_primal<1>, dim3(nb), dim3(64), 0, st, B, A); break;
+    case 2: hipLaunchKernelGGL(k_adj_primal<2>, dim3(nb), dim3(128), 0, st, B, A); break;
+    case 4: hipLaunchKernelGGL(k_adj_primal<4>, dim3(nb), dim3(256), 0, st, B, A); break;
+    default: hipLaunchKernelGGL(k_adj_primal<8>, dim3(nb), dim3(512), 0, st, B, A); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2(const float *s0, float *d0, size_t n0, const float *s1, float *d1, size_t n1,
+                        hipStream_t st) {
+  const long long q0 = (long long)(n0 / 4), q1 = (long long)(n1 / 4);
+  const long long tot = q0 + q1;
+  unsigned nb = (unsigned)std::min<long long>((tot + 255) / 256, 4096);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy2, dim3(nb), dim3(256), 0, st, (const float4 *)s0, (float4 *)d0, q0,
+                     (const float4 *)s1, (float4 *)d1, q1);
   return hipGetLastError();
 }
 

@@ -1132,8 +1132,9 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
     HIPCHK(hipMemcpyAsync(yv(0), ck + 4 * k * pl, yslot, hipMemcpyDeviceToDevice, P->st), "restore");
     // replay the segment, keeping every state (same launch configuration as the forward pass)
     for (int j = 0; j + 1 < n; j++) {
-      HIPCHK(hipMemcpyAsync(sslot(j + 2), sslot(j), k * pl, hipMemcpyDeviceToDevice, P->st), "replay");
-      HIPCHK(hipMemcpyAsync(yv(j + 1), yv(j), (2 * k + 1) * pl, hipMemcpyDeviceToDevice, P->st), "replay");
+      HIPCHK(launch_copy2(sslot(j), sslot(j + 2), (size_t)k * ps, yv(j), yv(j + 1), (size_t)(2 * k + 1) * ps,
+                          P->st),
+             "replay");
       IterPtrs<float> R = iter_ptrs_f(P);
       R.u = uslot(j + 1);
       R.up = uslot(j);

@@ -145,3 +145,6 @@ hipError_t launch_adj_readout(const float *gu, const float *u, float *ub, const 
 hipError_t launch_adj_finish(const float *cbar, const float *wbar, int nw, float *gf, float *gw, long long N,
                              long long ps, float iscale, hipStream_t st);
 hipError_t launch_sum_double(const double *a, long long n, double *out, hipStream_t st);
+// n0, n1: float counts, multiples of 4 (whole planes), 16-byte aligned
+hipError_t launch_copy2(const float *s0, float *d0, size_t n0, const float *s1, float *d1, size_t n1,
+                        hipStream_t st);
