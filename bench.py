@@ -140,19 +140,24 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # time to a 1e-3 certified relative gap from a fresh start
+    # time to a 1e-3 certified relative gap from a fresh start: adaptive step balance
+    # (residual balancing at every check) and, for reference, the fixed default steps
     gap = None
     if not args.no_gap:
-        g2 = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        done = g2.run_to_gap(1e-3, args.gap_max_iters)
-        t_gap = time.perf_counter() - t0
-        rep = g2.energy()
-        gap = {"seconds": t_gap, "iterations": done, "rel_gap": rep["rel_gap"],
-               "reached": rep["rel_gap"] <= 1e-3, "primal_ub": rep["primal_ub"],
-               "dual_lb": rep["dual_lb"], "e_nonconvex": rep["e_nonconvex"]}
-        g2.close()
+        gap = {}
+        for mode in ("adaptive", "fixed"):
+            g2 = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY,
+                                         device=dev, adaptive=(mode == "adaptive"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done = g2.run_to_gap(1e-3, args.gap_max_iters)
+            t_gap = time.perf_counter() - t0
+            rep = g2.energy()
+            gap[mode] = {"seconds": t_gap, "iterations": done, "rel_gap": rep["rel_gap"],
+                         "reached": rep["rel_gap"] <= 1e-3, "primal_ub": rep["best_primal"],
+                         "dual_lb": rep["best_dual"], "e_nonconvex": rep["e_nonconvex"],
+                         "step_balance": g2.get_step_balance()}
+            g2.close()
 
     cpu = None
     if not args.no_cpu:

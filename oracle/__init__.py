@@ -38,7 +38,7 @@ class _Desc(C.Structure):
                 ("f", C.POINTER(C.c_float)), ("a", C.c_double), ("nu", C.c_double),
                 ("M", C.c_int32), ("tau", C.POINTER(C.c_double)),
                 ("samples", C.POINTER(C.c_float)), ("lam", C.c_double),
-                ("normalize", C.c_int32), ("n_sub", C.c_int32)]
+                ("normalize", C.c_int32), ("n_sub", C.c_int32), ("step_balance", C.c_double)]
 
 
 class Report(C.Structure):
@@ -91,6 +91,7 @@ def lib():
         L.or_lower_hull.restype = C.c_int
         L.or_proj_simplex.argtypes = [C.c_int, _dp, _dp]
         L.or_proj_ball.argtypes = [_dp, _dp, C.c_double]
+        L.or_residual_norms.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_unrolled_forward.argtypes = [C.c_void_p, C.c_int]
         L.or_unrolled_backward.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_step_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
@@ -204,7 +205,7 @@ STATE_ORDER = ("u", "u_prev", "s", "s_prev", "v", "z", "px", "py", "qd")
 class Problem:
     """FP64 oracle instance built from a ``workloads.Workload``."""
 
-    def __init__(self, wl, normalize: bool = True, n_sub: int = 16):
+    def __init__(self, wl, normalize: bool = True, n_sub: int = 16, step_balance: float = 1.0):
         self.wl = wl
         self.k = wl.k
         self.H, self.W = wl.H, wl.W
@@ -230,6 +231,7 @@ class Problem:
         d.lam = float(wl.lam)
         d.normalize = 1 if normalize else 0
         d.n_sub = n_sub
+        d.step_balance = float(step_balance)
         h = lib().or_create(C.byref(d))
         if not h:
             raise ValueError(lib().or_last_error().decode())
@@ -304,6 +306,14 @@ class Problem:
         svz, ts, tu = np.empty(k), np.empty(k), np.empty(N)
         lib().or_steps(self.h, C.byref(sp), _p(svz), C.byref(sq), _p(tu), _p(ts))
         return sp.value, svz, sq.value, tu, ts
+
+    def residual_norms(self, before: dict, after: dict):
+        """l1 norms (primal, dual) of the residuals between two consecutive states."""
+        a = np.ascontiguousarray(np.concatenate([_f64(before[n]).reshape(-1) for n in STATE_ORDER]))
+        b = np.ascontiguousarray(np.concatenate([_f64(after[n]).reshape(-1) for n in STATE_ORDER]))
+        rp, rd = C.c_double(), C.c_double()
+        lib().or_residual_norms(self.h, _p(a), _p(b), C.byref(rp), C.byref(rd))
+        return rp.value, rd.value
 
     # ---- reverse pass
     def unrolled_forward(self, K: int):

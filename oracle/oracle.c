@@ -493,18 +493,18 @@ void or_apply_KT(const or_problem *P, const double *v, const double *q, const do
 /* diagonal preconditioning (Pock-Chambolle, alpha = 1): inverse absolute row / column
  * sums of K; v_i and z_i share the smaller step so that the joint epigraph projection is
  * the proximal map in the scaled metric. */
-static void compute_steps(or_problem *P) {
+static void compute_steps(or_problem *P, double cb) {
   const int k = P->k;
-  P->sig_p = 0.5;
+  P->sig_p = 0.5 * cb;
   for (int i = 0; i < k; i++) {
-    P->sig_vz[i] = 1.0 / (1.0 + fabs(P->gam[i]) + (P->gam[k] - P->gam[i + 1]));
-    P->tau_s[i] = 1.0 / (1.0 + fabs(P->gam[i]) + (i + 1) * P->h[i]);
+    P->sig_vz[i] = cb / (1.0 + fabs(P->gam[i]) + (P->gam[k] - P->gam[i + 1]));
+    P->tau_s[i] = 1.0 / (cb * (1.0 + fabs(P->gam[i]) + (i + 1) * P->h[i]));
   }
-  P->sig_q = 1.0 / (P->gam[k] - P->gam[0]);
+  P->sig_q = cb / (P->gam[k] - P->gam[0]);
   for (int r = 0; r < P->H; r++)
     for (int c = 0; c < P->W; c++) {
       int deg = (c < P->W - 1) + (c > 0) + (r < P->H - 1) + (r > 0);
-      P->tau_u[(int64_t)r * P->W + c] = 1.0 / (1.0 + deg);
+      P->tau_u[(int64_t)r * P->W + c] = 1.0 / (cb * (1.0 + deg));
     }
 }
 
@@ -641,7 +641,8 @@ or_problem *or_create(const or_desc *d) {
   P->tau_u = (double *)malloc(sizeof(double) * N);
   P->sig_vz = (double *)malloc(sizeof(double) * k);
   P->tau_s = (double *)malloc(sizeof(double) * k);
-  compute_steps(P);
+  if (d->step_balance < 0.0 || !isfinite(d->step_balance)) FAIL("step_balance must be finite and >= 0");
+  compute_steps(P, d->step_balance > 0.0 ? d->step_balance : 1.0);
   return P;
 }
 
@@ -1197,4 +1198,42 @@ int or_unrolled_backward(or_problem *P, const double *gu, double *gf, double *gl
   free(gc);
   free(gwn);
   return rc;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* residuals of one iteration (adaptive step balancing)                               */
+
+void or_residual_norms(const or_problem *P, const double *before, const double *after,
+                       double *rp, double *rd) {
+  const int k = P->k;
+  const int64_t N = P->N, kN = (int64_t)k * N, S = 8 * kN + N;
+  double *d = (double *)malloc(sizeof(double) * S);
+  double *Ku = (double *)malloc(sizeof(double) * kN), *Ks = (double *)malloc(sizeof(double) * kN);
+  double *Kv = (double *)malloc(sizeof(double) * kN), *Kz = (double *)malloc(sizeof(double) * kN);
+  double *Kpx = (double *)malloc(sizeof(double) * kN), *Kpy = (double *)malloc(sizeof(double) * kN);
+  double *Kq = (double *)malloc(sizeof(double) * N);
+  for (int64_t e = 0; e < S; e++) d[e] = before[e] - after[e];
+  const double *du = d, *ds = d + 2 * kN, *dv = d + 4 * kN, *dz = d + 5 * kN;
+  const double *dpx = d + 6 * kN, *dpy = d + 7 * kN, *dq = d + 8 * kN;
+  or_apply_KT(P, dv, dq, dpx, dpy, dz, Ku, Ks);
+  or_apply_K(P, du, ds, Kv, Kq, Kpx, Kpy, Kz);
+  double p = 0.0, q = 0.0;
+  for (int i = 0; i < k; i++)
+    for (int64_t x = 0; x < N; x++) {
+      int64_t e = i * N + x;
+      p += fabs(du[e] / P->tau_u[x] - Ku[e]) + fabs(ds[e] / P->tau_s[i] - Ks[e]);
+      q += fabs(dv[e] / P->sig_vz[i] - Kv[e]) + fabs(dz[e] / P->sig_vz[i] - Kz[e]) +
+           fabs(dpx[e] / P->sig_p - Kpx[e]) + fabs(dpy[e] / P->sig_p - Kpy[e]);
+    }
+  for (int64_t x = 0; x < N; x++) q += fabs(dq[x] / P->sig_q - Kq[x]);
+  *rp = p;
+  *rd = q;
+  free(d);
+  free(Ku);
+  free(Ks);
+  free(Kv);
+  free(Kz);
+  free(Kpx);
+  free(Kpy);
+  free(Kq);
 }

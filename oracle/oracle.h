@@ -36,6 +36,7 @@ typedef struct {
   double lambda;            /* TV weight                                               */
   int32_t normalize;        /* 1: iterate on labels mapped affinely onto [0,1]         */
   int32_t n_sub;            /* samples per straddling truncated-quadratic interval     */
+  double step_balance;      /* dual steps times c, primal steps divided by c (0: c = 1) */
 } or_desc;
 
 typedef struct {
@@ -89,6 +90,13 @@ void or_proj_epi_quad_vjp(double a, double c, double d, double g0, double g1, do
                           double *cb, double *db);
 void or_proj_epi_pl_vjp(int n, const double *t, const double *r, double y0, double w0,
                         double yb, double wb, double *y0b, double *w0b, double *rb);
+
+/* l1 norms of the primal and dual residuals of one iteration (residual balancing of the
+ * adaptive primal-dual method cited in Sec. 4): with dx = x_before - x_after and
+ * dy = y_before - y_after, r_p = T^-1 dx - K^T dy and r_d = Sigma^-1 dy - K dx. The states
+ * are in the or_get_state layout. */
+void or_residual_norms(const or_problem *P, const double *before, const double *after,
+                       double *rp, double *rd);
 
 /* primitives */
 void or_grad(int H, int W, const double *u, double *gx, double *gy);

@@ -96,6 +96,10 @@ def lib():
         L.sl_unrolled_workspace_size.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(sz)]
         L.sl_unrolled_forward.argtypes = [vp, C.c_int32, C.c_int32, vp, sz]
         L.sl_unrolled_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
+        L.sl_residuals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.sl_set_residual_target.argtypes = [vp, C.c_double]
+        L.sl_set_step_balance.argtypes = [vp, C.c_double]
+        L.sl_get_step_balance.argtypes = [vp, C.POINTER(C.c_double)]
         L.sl_destroy.argtypes = [vp]
         L.sl_destroy.restype = None
         for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
@@ -103,7 +107,8 @@ def lib():
                      "sl_set_tiling", "sl_get_tiling", "sl_batch_workspace_size", "sl_batch_create",
                      "sl_batch_energy", "sl_batch_read_u", "sl_batch_info", "sl_set_graphs",
                      "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
-                     "sl_unrolled_backward"):
+                     "sl_unrolled_backward", "sl_set_step_balance", "sl_get_step_balance",
+                     "sl_residuals", "sl_set_residual_target"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -127,7 +132,7 @@ def _dev_f32(a, device):
 
 
 def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
-               check_every, device):
+               check_every, device, adaptive=False):
     """Fill a Desc; device copies of the inputs are kept on ``obj._keep``."""
     obj.H, obj.W = int(H), int(W)
     obj.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
@@ -152,7 +157,7 @@ def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, norm
     d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
     d.check_every = int(check_every)
     d.normalize_labels = 1 if normalize else 0
-    d.adaptive_steps = 0
+    d.adaptive_steps = 1 if adaptive else 0
     return d
 
 
@@ -166,13 +171,14 @@ class Problem:
 
     def __init__(self, H: int, W: int, gamma, rho: int, lam: float, f=None, a: float = 1.0,
                  nu: float = 0.0, tau=None, samples=None, storage: str = "fp32",
-                 normalize: bool = True, check_every: int = 50, device=None):
+                 normalize: bool = True, check_every: int = 50, device=None,
+                 adaptive: bool = False):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()
         self._keep = {}
         d = _make_desc(self, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
-                       check_every, self.device)
+                       check_every, self.device, adaptive)
         self.desc = d
         nbytes = C.c_size_t()
         _check(L_.sl_workspace_size(C.byref(d), C.byref(nbytes)))
@@ -252,6 +258,25 @@ class Problem:
                                           C_.c_void_p(gw.data_ptr() if gw is not None else 0)))
         return gf, gl.value, gw
 
+    def residuals(self):
+        """Run one iteration; return the l1 norms (primal, dual) of its residuals."""
+        rp, rd = C_.c_double(), C_.c_double()
+        _check(lib().sl_residuals(self.h, C_.byref(rp), C_.byref(rd)))
+        return rp.value, rd.value
+
+    def set_residual_target(self, s: float):
+        """Target ratio of primal to dual residual for the adaptive balance (default 1)."""
+        _check(lib().sl_set_residual_target(self.h, float(s)))
+
+    def set_step_balance(self, c: float):
+        """Scale the dual steps by c and the primal steps by 1/c (c = 1 by default)."""
+        _check(lib().sl_set_step_balance(self.h, float(c)))
+
+    def get_step_balance(self) -> float:
+        c = C_.c_double()
+        _check(lib().sl_get_step_balance(self.h, C_.byref(c)))
+        return c.value
+
     def autotune(self, iters: int = 20, cache: Optional[str] = None):
         """Pick the fastest tiling (resets the iteration state); returns (groups, rows)."""
         g, t = C.c_int32(), C.c_int32()
@@ -285,7 +310,7 @@ class BatchProblem(Problem):
     iteration (sl_batch_create). ``instances`` are ``workloads.Workload``-like objects."""
 
     def __init__(self, instances, storage: str = "fp32", normalize: bool = True,
-                 check_every: int = 48, device=None):
+                 check_every: int = 48, device=None, adaptive: bool = False):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()
@@ -295,7 +320,7 @@ class BatchProblem(Problem):
             it = _Inst()
             descs[j] = _make_desc(it, wl.H, wl.W, wl.gamma, wl.rho, wl.lam, wl.f, wl.a, wl.nu,
                                   wl.tau, wl.samples, storage, normalize, check_every,
-                                  self.device)
+                                  self.device, adaptive)
             self._insts.append(it)
         self.n = len(instances)
         nbytes = C.c_size_t()

@@ -263,9 +263,9 @@ __device__ __forceinline__ void tq_chain_vjp(float a, float c, float nu, float g
   pl.vjp(yb, wb, y0b, w0b, cb);
 }
 
-__device__ __forceinline__ float tau_of(int r, int c, int H, int W) {
+__device__ __forceinline__ float tau_of(int r, int c, int H, int W, float tau_c) {
   const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
-  return 1.f / (1.f + (float)deg);
+  return tau_c / (1.f + (float)deg);
 }
 
 // ------------------------------------------------------------------ kernel 1: steps 1-4
@@ -288,8 +288,9 @@ __global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
   const long long x = in ? xi : 0;
   const bool hr = c < W - 1, hd = r < H - 1;
   const long long xr = hr ? x + 1 : x, xd = hd ? x + W : x;
-  const float tau_u = tau_of(r, c, H, W);
-  const float tau_r = hr ? tau_of(r, c + 1, H, W) : 0.f, tau_d = hd ? tau_of(r + 1, c, H, W) : 0.f;
+  const float tau_u = tau_of(r, c, H, W, A.tau_c);
+  const float tau_r = hr ? tau_of(r, c + 1, H, W, A.tau_c) : 0.f;
+  const float tau_d = hd ? tau_of(r + 1, c, H, W, A.tau_c) : 0.f;
   const int ch = (k + T - 1) / T;
   const int i0 = min(k, t * ch), i1 = min(k, i0 + ch);
 

@@ -45,6 +45,7 @@ struct Layout {
   size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_forig, off_w, off_cost, off_tau,
       off_taud, off_sinfo;
   size_t off_monu, off_monb, off_part1, off_part2, off_fin, off_flag, total;
+  size_t off_ysave, off_rpart, off_rfin;  // step control: duals before an iteration, residual sums
   size_t state_lo, state_hi;  // contiguous range holding u, s, v, z, p, qd
 };
 
@@ -83,6 +84,14 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   L.off_part2 = take((size_t)nb_mon * SLI_NMON * 8);
   L.off_fin = take(SLI_NMON * 8);
   L.off_flag = take(16);
+  L.off_ysave = take(2 * k * pd + pf);
+  {
+    IterArgs A{};
+    A.H = d->H;
+    A.W = d->W;
+    L.off_rpart = take((size_t)residual_blocks(A) * 16);
+  }
+  L.off_rfin = take(16);
   L.total = o;
   return L;
 }
@@ -110,7 +119,8 @@ sl_status validate(const sl_problem_desc *d) {
   if (d->check_every < 0) return fail(SL_ERR_INVALID_ARG, "check_every must be >= 0");
   if (d->normalize_labels != 0 && d->normalize_labels != 1)
     return fail(SL_ERR_INVALID_ARG, "normalize_labels must be 0 or 1");
-  if (d->adaptive_steps != 0) return fail(SL_ERR_UNSUPPORTED, "adaptive steps are not built");
+  if (d->adaptive_steps != 0 && d->adaptive_steps != 1)
+    return fail(SL_ERR_INVALID_ARG, "adaptive_steps must be 0 or 1");
   if (d->rho != SL_RHO_SAMPLED) {
     if (!d->f) return fail(SL_ERR_INVALID_ARG, "f is NULL");
     if (!(d->a > 0.0) || !isfinite(d->a)) return fail(SL_ERR_INVALID_ARG, "a must be > 0");
@@ -161,6 +171,11 @@ struct sl_problem_ {
   IterArgs A{};
   MonArgs D{};
   double shift = 0, scale = 1, lam = 0;
+  double step_c = 1.0;  // balance of dual against primal steps (sigma * c, tau / c)
+  double adapt_alpha = 0.5;  // current relative change of the balance (adaptive steps)
+  double adapt_s = 0.003;    // target ratio of the primal to the dual residual
+  int64_t adapt_count = 0;   // balance changes made so far
+  std::vector<double> gamma_in, tau_in;  // the caller's labels and sample positions (copies)
   hipStream_t st = nullptr;
   Layout lay{};
   char *ws = nullptr;
@@ -197,6 +212,7 @@ struct sl_problem_ {
   // unrolled differentiation: caller's workspace of checkpoints, replay states and adjoints
   char *uws = nullptr;
   int uK = 0, uC = 0, ucfg = 0;
+  IterArgs uA{};        // parameters of the forward pass (the replay and adjoint use these)
   int64_t u_end = -1;
 
   ~sl_problem_() {
@@ -214,14 +230,17 @@ struct sl_problem_ {
 
 namespace {
 
+// Iteration and monitor parameters from the problem description (labels and sample
+// positions from the copies kept in the handle; the caller's pointers are not kept).
 void fill_args(sl_problem_ *P) {
   const sl_problem_desc *d = &P->d;
+  const double *gamma = P->gamma_in.data(), *tau = P->tau_in.data();
   IterArgs &A = P->A;
   const int L = d->L, k = L - 1;
-  P->shift = d->normalize_labels ? d->gamma[0] : 0.0;
-  P->scale = d->normalize_labels ? d->gamma[L - 1] - d->gamma[0] : 1.0;
+  P->shift = d->normalize_labels ? gamma[0] : 0.0;
+  P->scale = d->normalize_labels ? gamma[L - 1] - gamma[0] : 1.0;
   std::vector<double> g(L), h(k);
-  for (int j = 0; j < L; j++) g[j] = (d->gamma[j] - P->shift) / P->scale;
+  for (int j = 0; j < L; j++) g[j] = (gamma[j] - P->shift) / P->scale;
   for (int i = 0; i < k; i++) h[i] = g[i + 1] - g[i];
   A.H = d->H;
   A.W = d->W;
@@ -238,15 +257,18 @@ void fill_args(sl_problem_ *P) {
   D.a = d->rho != SL_RHO_SAMPLED ? d->a * P->scale * P->scale : 0.0;
   D.nu = d->nu;
   A.lam = (float)P->lam;
-  // diagonal preconditioning: inverse absolute row / column sums of the operator
-  A.sig_p = 0.5f;
-  A.sig_q = (float)(1.0 / (g[k] - g[0]));
+  // diagonal preconditioning: inverse absolute row / column sums of the operator, the dual
+  // steps scaled by the balance c and the primal ones by 1/c (c = 1: the plain choice)
+  const double cb = P->step_c;
+  A.sig_p = (float)(0.5 * cb);
+  A.sig_q = (float)(cb / (g[k] - g[0]));
+  A.tau_c = (float)(1.0 / cb);
   for (int j = 0; j < L; j++) A.gam[j] = (float)g[j];
   for (int i = 0; i < k; i++) {
     A.h[i] = (float)h[i];
     A.ih[i] = (float)(1.0 / h[i]);
-    A.sig[i] = (float)(1.0 / (1.0 + fabs(g[i]) + (g[k] - g[i + 1])));
-    A.taus[i] = (float)(1.0 / (1.0 + fabs(g[i]) + (i + 1) * h[i]));
+    A.sig[i] = (float)(cb / (1.0 + fabs(g[i]) + (g[k] - g[i + 1])));
+    A.taus[i] = (float)(1.0 / (cb * (1.0 + fabs(g[i]) + (i + 1) * h[i])));
     A.ig0[i] = (float)(1.0 / (1.0 + g[i] * g[i]));
     A.ig1[i] = (float)(1.0 / (1.0 + g[i + 1] * g[i + 1]));
   }
@@ -260,12 +282,12 @@ void fill_args(sl_problem_ *P) {
     P->tau_host.resize(d->M);
     P->taud_host.resize(d->M);
     for (int m = 0; m < d->M; m++) {
-      P->taud_host[m] = (d->tau[m] - P->shift) / P->scale;
+      P->taud_host[m] = (tau[m] - P->shift) / P->scale;
       P->tau_host[m] = (float)P->taud_host[m];
     }
     for (int j = 0; j < L; j++)
       for (int m = 0; m < d->M; m++)
-        if (d->tau[m] == d->gamma[j]) A.sidx[j] = m;
+        if (tau[m] == gamma[j]) A.sidx[j] = m;
   }
 }
 
@@ -554,6 +576,62 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
   return SL_OK;
 }
 
+// One iteration with the residual norms of its step (primal, dual; l1, FP64).
+sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
+  const int k = P->A.k;
+  const size_t pdb = (size_t)P->lay.ps * P->esz(), pfb = (size_t)P->lay.ps * 4;
+  char *ys = P->ws + P->lay.off_ysave;
+  HIPCHK(launch_copy2((const float *)(P->ws + P->lay.off_v), (float *)ys, k * pdb / 4,
+                      (const float *)(P->ws + P->lay.off_z), (float *)(ys + k * pdb), k * pdb / 4, P->st),
+         "save duals");
+  HIPCHK(launch_copy2((const float *)(P->ws + P->lay.off_qd), (float *)(ys + 2 * k * pdb), pfb / 4, nullptr,
+                      nullptr, 0, P->st),
+         "save duals");
+  sl_status s = enqueue_iters(P, 1);
+  if (s != SL_OK) return s;
+  ResPtrs R;
+  R.u = P->ubuf(P->iu);
+  R.up = P->ubuf((P->iu + 2) % 3);
+  R.s = P->sbuf(P->is);
+  R.sp = P->sbuf(1 - P->is);
+  R.q = (const float *)(P->ws + P->lay.off_qd);
+  R.qo = (const float *)(ys + 2 * k * pdb);
+  R.v = P->ws + P->lay.off_v;
+  R.z = P->ws + P->lay.off_z;
+  R.vo = ys;
+  R.zo = ys + k * pdb;
+  R.p = P->pbuf(P->ip);
+  R.po = P->pbuf(1 - P->ip);
+  R.part = (double *)(P->ws + P->lay.off_rpart);
+  double *fin = (double *)(P->ws + P->lay.off_rfin);
+  HIPCHK(launch_residuals(P->bf16, R, P->A, fin, P->st), "residuals");
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, fin, sizeof h, hipMemcpyDeviceToHost, P->st), "residual copy");
+  HIPCHK(hipStreamSynchronize(P->st), "residual sync");
+  *rp = h[0];
+  *rd = h[1];
+  return SL_OK;
+}
+
+// Residual balancing: a primal residual more than 1.5 times s times the dual one enlarges
+// the primal steps (c *= 1 - alpha), one below s times the dual one divided by 1.5 enlarges
+// the dual steps (c /= 1 - alpha); every change shrinks alpha by 0.95 (alpha starts at 0.5).
+void adapt_balance(sl_problem_ *P, double rp, double rd) {
+  const double delta = 1.5, eta = 0.95;
+  const double sd = P->adapt_s * rd;
+  double c = P->step_c;
+  if (rp > delta * sd)
+    c *= 1.0 - P->adapt_alpha;
+  else if (rp * delta < sd)
+    c /= 1.0 - P->adapt_alpha;
+  else
+    return;
+  P->adapt_alpha *= eta;
+  P->adapt_count++;
+  P->step_c = std::min(4096.0, std::max(1.0 / 4096.0, c));
+  fill_args(P);
+}
+
 struct ULayout {
   int ncp;
   size_t ckpt, useq, sseq, yseq, adj, cbar, wbar, lbar, lsum, total;
@@ -682,14 +760,9 @@ static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes
   P->piece = desc->rho == SL_RHO_QUAD ? SLI_QUAD : desc->rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : SLI_SAMPLED;
   P->add = desc->rho != SL_RHO_SAMPLED && desc->samples != nullptr;
   P->check_every = desc->check_every > 0 ? desc->check_every : 50;
-  {
-    // keep pointers for fill_args
-    sl_problem_desc dd = *desc;
-    sl_problem_desc keep = P->d;
-    P->d = dd;
-    fill_args(P);
-    P->d = keep;
-  }
+  P->gamma_in.assign(desc->gamma, desc->gamma + desc->L);
+  if (desc->tau) P->tau_in.assign(desc->tau, desc->tau + desc->M);
+  fill_args(P);
   P->maxlds = maxlds;
   P->cfg = auto_cfg(P);
   if (P->cfg < 0) {
@@ -771,8 +844,14 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
   sl_report r;
   while (n < max_iters) {
     int chunk = std::min(P->check_every, max_iters - n);
-    sl_status s = enqueue_iters(P, chunk);
+    sl_status s = enqueue_iters(P, P->d.adaptive_steps ? chunk - 1 : chunk);
     if (s != SL_OK) return s;
+    if (P->d.adaptive_steps) {
+      // the check interval's last iteration measures the residuals that steer the balance
+      double rp = 0.0, rd = 0.0;
+      if ((s = iterate_with_residuals(P, &rp, &rd)) != SL_OK) return s;
+      adapt_balance(P, rp, rd);
+    }
     n += chunk;
     if ((s = monitor(P, &r)) != SL_OK) {
       if (done) *done = n;
@@ -856,6 +935,9 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   if (s != SL_OK) return s;
   if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
   if (bytes < need) return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, need);
+  for (int i = 0; i < n; i++)
+    if (descs[i].adaptive_steps)
+      return fail(SL_ERR_UNSUPPORTED, "instance %d: adaptive steps in a batch are not built", i);
   for (int i = 1; i < n; i++)
     if (descs[i].rho != descs[0].rho || descs[i].storage != descs[0].storage ||
         (descs[i].samples != nullptr) != (descs[0].samples != nullptr))
@@ -1079,6 +1161,7 @@ sl_status sl_unrolled_forward(sl_problem P, int32_t K, int32_t C, void *ws, size
   P->uK = K;
   P->uC = C;
   P->ucfg = P->cfg;
+  P->uA = P->A;
   P->u_end = P->iters;
   return SL_OK;
 }
@@ -1089,7 +1172,7 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
   if (!P->uws || P->iters != P->u_end)
     return fail(SL_ERR_INVALID_ARG, "needs sl_unrolled_forward immediately before (no iterations since)");
   if (grad_w && !P->add) return fail(SL_ERR_INVALID_ARG, "grad_w needs a problem with additive values");
-  const int K = P->uK, C = P->uC, k = P->A.k;
+  const int K = P->uK, C = P->uC, k = P->uA.k;
   const ULayout U = unrolled_layout(P, K, C);
   char *w = P->uws;
   const long long ps = P->lay.ps, N = P->lay.N;
@@ -1113,7 +1196,7 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
   Q.wbar = (float *)(w + U.wbar);
   Q.lbar = (double *)(w + U.lbar);
   HIPCHK(launch_fill_zero(w + U.adj, U.lsum - U.adj, P->st), "zero adjoints");
-  HIPCHK(launch_adj_readout(grad_u, P->ubuf(P->iu), B.u, P->A, (float)P->scale, P->st), "read-out adjoint");
+  HIPCHK(launch_adj_readout(grad_u, P->ubuf(P->iu), B.u, P->uA, (float)P->scale, P->st), "read-out adjoint");
 
   float *useq = (float *)(w + U.useq), *sseq = (float *)(w + U.sseq);
   char *yseq = w + U.yseq;
@@ -1146,7 +1229,7 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
       R.qd = yq(j + 1);
       R.pin = yp(j);
       R.pout = yp(j + 1);
-      HIPCHK(launch_pdhg_iter(P->piece, P->add, false, P->ucfg, P->A, &R, P->st), "replay iteration");
+      HIPCHK(launch_pdhg_iter(P->piece, P->add, false, P->ucfg, P->uA, &R, P->st), "replay iteration");
     }
     for (int j = n - 1; j >= 0; j--) {
       AdjState X;
@@ -1158,8 +1241,8 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
       X.z = yz(j);
       X.px = yp(j);
       X.py = yp(j) + (size_t)k * ps;
-      HIPCHK(launch_adj_dual(P->piece, P->add, X, B, Q, P->A, P->st), "adjoint (dual steps)");
-      HIPCHK(launch_adj_primal(B, P->A, P->st), "adjoint (primal step)");
+      HIPCHK(launch_adj_dual(P->piece, P->add, X, B, Q, P->uA, P->st), "adjoint (dual steps)");
+      HIPCHK(launch_adj_primal(B, P->uA, P->st), "adjoint (primal step)");
     }
   }
   HIPCHK(launch_adj_finish(Q.cbar, Q.wbar, P->add ? k + 1 : 0, grad_f, grad_w, N, ps, (float)(1.0 / P->scale),
@@ -1171,6 +1254,46 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
   HIPCHK(hipMemcpyAsync(&hl, lsum, sizeof(double), hipMemcpyDeviceToHost, P->st), "lambda copy");
   HIPCHK(hipStreamSynchronize(P->st), "backward sync");
   if (grad_lambda) *grad_lambda = hl * P->scale;
+  return SL_OK;
+}
+
+sl_status sl_set_step_balance(sl_problem P, double c) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (!(c > 0.0) || !isfinite(c)) return fail(SL_ERR_INVALID_ARG, "the balance must be finite and > 0");
+  if (P->is_batch) {
+    for (size_t i = 0; i < P->sub.size(); i++) {
+      P->sub[i]->step_c = c;
+      fill_args(P->sub[i]);
+      P->args_host[i] = P->sub[i]->A;
+    }
+    P->step_c = c;
+    HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
+                          hipMemcpyHostToDevice, P->st),
+           "batch parameters");
+    HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
+    return SL_OK;
+  }
+  P->step_c = c;
+  fill_args(P);
+  return SL_OK;
+}
+
+sl_status sl_set_residual_target(sl_problem P, double s) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (!(s > 0.0) || !isfinite(s)) return fail(SL_ERR_INVALID_ARG, "the target must be finite and > 0");
+  P->adapt_s = s;
+  return SL_OK;
+}
+
+sl_status sl_residuals(sl_problem P, double *primal, double *dual) {
+  if (!P || !primal || !dual) return fail(SL_ERR_INVALID_ARG, "NULL argument");
+  if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "residuals of a batch are not built");
+  return iterate_with_residuals(P, primal, dual);
+}
+
+sl_status sl_get_step_balance(sl_problem P, double *c) {
+  if (!P || !c) return fail(SL_ERR_INVALID_ARG, "NULL argument");
+  *c = P->step_c;
   return SL_OK;
 }
 

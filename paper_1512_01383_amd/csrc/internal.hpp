@@ -31,6 +31,7 @@ struct IterArgs {
   int H, W, k, M;
   long long ps;           // plane stride (elements)
   float sig_p, sig_q;     // steps of p and q
+  float tau_c;            // scale of the primal steps (tau_u(x) = tau_c / (1 + deg(x)))
   float lam;              // lambda in normalised label units
   float a, ia, nu, del;   // quadratic coefficient, its inverse, truncation, band half-width
   float gam[SLI_MAXK + 1];
@@ -148,3 +149,13 @@ hipError_t launch_sum_double(const double *a, long long n, double *out, hipStrea
 // n0, n1: float counts, multiples of 4 (whole planes), 16-byte aligned
 hipError_t launch_copy2(const float *s0, float *d0, size_t n0, const float *s1, float *d1, size_t n1,
                         hipStream_t st);
+
+// Residuals of one iteration (steps.hip): the state after it, the duals before it (v, z, q
+// saved, p from the other buffer); part holds residual_blocks(A) pairs of doubles.
+struct ResPtrs {
+  const float *u, *up, *s, *sp, *q, *qo;
+  const void *v, *z, *vo, *zo, *p, *po;  // storage type per `bf16`
+  double *part;
+};
+int residual_blocks(const IterArgs &A);
+hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st);

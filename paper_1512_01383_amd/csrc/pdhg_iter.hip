@@ -61,7 +61,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   const long long xo = (long long)r * W + c;
   const unsigned xb = (unsigned)xo * 4u, db = (unsigned)xo * (unsigned)sizeof(DT);
   const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
-  const float tau_u = 1.f / (1.f + (float)deg);
+  const float tau_u = A.tau_c / (1.f + (float)deg);
 
   // this group's label chunk
   const int chn = (k + G - 1) / G;

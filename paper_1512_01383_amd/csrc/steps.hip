@@ -1,0 +1,118 @@
+// steps.hip -- residuals of one primal-dual iteration for the step control (Sec. 4 uses
+// the adaptive primal-dual method, which balances the primal and dual residuals by
+// rescaling the steps).
+//
+// With dx = x_k - x_{k+1} and dy = y_k - y_{k+1} (x = (u, s), y = (v, z, p, q)):
+//   r_p = T^-1 dx - K^T dy,   r_d = Sigma^-1 dy - K dx,
+// and the kernel sums |r_p| and |r_d| over all entries (FP64 accumulation, fixed order:
+// every thread owns a fixed set of pixels, blocks write partial sums, one block adds them).
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace {
+
+constexpr int RB = 256;
+
+template <typename DT>
+__global__ __launch_bounds__(RB) void k_residuals(ResPtrs R, IterArgs A) {
+  __shared__ double sp_[RB], sd_[RB];
+  const DT *v = (const DT *)R.v, *z = (const DT *)R.z, *vo = (const DT *)R.vo, *zo = (const DT *)R.zo;
+  const DT *p = (const DT *)R.p, *po = (const DT *)R.po;
+  const int H = A.H, W = A.W, k = A.k;
+  const long long ps = A.ps, N = (long long)H * W;
+  double accp = 0.0, accd = 0.0;
+  for (long long x = (long long)blockIdx.x * RB + threadIdx.x; x < N; x += (long long)gridDim.x * RB) {
+    const int r = (int)(x / W), c = (int)(x - (long long)r * W);
+    const bool hr = c < W - 1, hl = c > 0, hd = r < H - 1, hu = r > 0;
+    const int deg = hr + hl + hd + hu;
+    const float tau_u = A.tau_c / (1.f + (float)deg);
+    float T = 0.f;
+    for (int i = 0; i < k; i++) {
+      const size_t o = (size_t)i * ps;
+      T += A.h[i] * (R.sp[o + x] - R.s[o + x]);
+    }
+    const float dq = R.qo[x] - R.q[x];
+    float suf = T, pre = 0.f;
+    for (int i = 0; i < k; i++) {
+      const size_t o = (size_t)i * ps, oy = (size_t)(k + i) * ps;
+      const float du = R.up[o + x] - R.u[o + x];
+      const float ds = R.sp[o + x] - R.s[o + x];
+      const float dv = ldv(vo, o + x) - ldv(v, o + x);
+      const float dz = ldv(zo, o + x) - ldv(z, o + x);
+      const float dpx = ldv(po, o + x) - ldv(p, o + x);
+      const float dpy = ldv(po, oy + x) - ldv(p, oy + x);
+      float div = 0.f;
+      if (hr) div += dpx;
+      if (hl) div -= ldv(po, o + x - 1) - ldv(p, o + x - 1);
+      if (hd) div += dpy;
+      if (hu) div -= ldv(po, oy + x - W) - ldv(p, oy + x - W);
+      const float gx = hr ? (R.up[o + x + 1] - R.u[o + x + 1]) - du : 0.f;
+      const float gy = hd ? (R.up[o + x + W] - R.u[o + x + W]) - du : 0.f;
+      suf -= A.h[i] * ds;
+      const float rpu = du / tau_u - (dv - div);
+      const float rps = ds / A.taus[i] - (dz - A.h[i] * dq + A.h[i] * pre - A.gam[i] * dv);
+      pre += dv;
+      const float rdv = dv / A.sig[i] - (du - A.gam[i] * ds + suf);
+      const float rdz = dz / A.sig[i] - ds;
+      const float rdx = dpx / A.sig_p - gx, rdy = dpy / A.sig_p - gy;
+      accp += (double)fabsf(rpu) + (double)fabsf(rps);
+      accd += (double)fabsf(rdv) + (double)fabsf(rdz) + (double)fabsf(rdx) + (double)fabsf(rdy);
+    }
+    accd += (double)fabsf(dq / A.sig_q + T);
+  }
+  sp_[threadIdx.x] = accp;
+  sd_[threadIdx.x] = accd;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sp_[threadIdx.x] += sp_[threadIdx.x + s];
+      sd_[threadIdx.x] += sd_[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    R.part[2 * blockIdx.x] = sp_[0];
+    R.part[2 * blockIdx.x + 1] = sd_[0];
+  }
+}
+
+__global__ __launch_bounds__(RB) void k_sum_pairs(const double *part, int nb, double *out) {
+  __shared__ double a[RB], b[RB];
+  double x = 0.0, y = 0.0;
+  for (int j = threadIdx.x; j < nb; j += RB) {
+    x += part[2 * j];
+    y += part[2 * j + 1];
+  }
+  a[threadIdx.x] = x;
+  b[threadIdx.x] = y;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      a[threadIdx.x] += a[threadIdx.x + s];
+      b[threadIdx.x] += b[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a[0];
+    out[1] = b[0];
+  }
+}
+
+}  // namespace
+
+int residual_blocks(const IterArgs &A) {
+  const long long N = (long long)A.H * A.W;
+  const long long nb = (N + RB - 1) / RB;
+  return (int)(nb < 1024 ? nb : 1024);
+}
+
+hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st) {
+  const int nb = residual_blocks(A);
+  if (bf16)
+    hipLaunchKernelGGL(k_residuals<uint16_t>, dim3(nb), dim3(RB), 0, st, R, A);
+  else
+    hipLaunchKernelGGL(k_residuals<float>, dim3(nb), dim3(RB), 0, st, R, A);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, st, (const double *)R.part, nb, out);
+  return hipGetLastError();
+}
