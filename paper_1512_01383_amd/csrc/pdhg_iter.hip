@@ -43,6 +43,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   __shared__ float pxs[G][TH + 1][TW + 1];
   __shared__ float pys[G][TH + 1][TW + 1];
   __shared__ float ex[G][NP];      // per-chunk partial sums (reused: sbar sums, then v sums)
+  __shared__ float stv[G > 1 ? 2 : 1][NP], stz[G > 1 ? 2 : 1][NP];  // straddle results (G > 1)
   float *lsb = dyn;               // [k][NP] sbar
   float *lsa = dyn + A.k * NP;    // [k][NP] s, then the partial s update
 
@@ -95,19 +96,38 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   float suf = base + Tc;   // sum_{j >= i0} h_j sbar_j
 
   // ---- straddling truncated-quadratic intervals (at most two per pixel; their labels and
-  // hull tangent range come precomputed), projected ahead of the label walk
+  // hull tangent range come precomputed), projected ahead of the label walk. Slot 0 is
+  // done by group 0 and slot 1 by group 1 for every pixel of the tile (one group does both
+  // when G = 1), whichever group owns the label; the owner picks the result up from LDS.
+  // The suffix sum is formed exactly as the owner's walk forms it.
   int si0 = -1, si1 = -1;
-  float sv0 = 0.f, sz0 = 0.f, sv1 = 0.f, sz1 = 0.f;
+  float sv0 = 0.f, sz0 = 0.f, sv1 = 0.f, sz1 = 0.f;   // G = 1: the results stay in registers
   if (PIECE == SLI_TRUNC && in) {
     const unsigned info = ldb(P.sinfo, xb);
+    if (G > 1) {
+      if ((info & 31u) != 31u) si0 = (int)(info & 31u);
+      if (((info >> 13) & 31u) != 31u) si1 = (int)((info >> 13) & 31u);
+    }
 #pragma unroll
     for (int slot = 0; slot < 2; slot++) {
+      if (G > 1 && slot != grp) continue;
       const unsigned f = info >> (13 * slot);
       const int i = (int)(f & 31u);
-      if (i < i0 || i >= i1) continue;
+      if (G == 1 ? (i < i0 || i >= i1) : i == 31) continue;
       const int ml = (int)((f >> 5) & 15u), mr = (int)((f >> 9) & 15u);
-      float run = suf;   // sum_{j > i} h_j sbar_j, accumulated in the walk's order
-      for (int j = i0; j <= i; j++) run -= A.h[j] * lsb[j * NP + lt];
+      float run;                        // the owner's sum_{j > i} h_j sbar_j, formed as its walk does
+      if (G == 1) {
+        run = suf;
+        for (int j = i0; j <= i; j++) run -= A.h[j] * lsb[j * NP + lt];
+      } else {
+        const int og = i / chn;         // group owning label i
+        float ob = 0.f;
+#pragma unroll
+        for (int g = 0; g < G; g++)
+          if (g > og) ob += ex[g][lt];
+        run = ob + ex[og][lt];
+        for (int j = og * chn; j <= i; j++) run -= A.h[j] * lsb[j * NP + lt];
+      }
       const float g0 = A.gam[i], g1 = A.gam[i + 1];
       const float sb = lsb[i * NP + lt];
       const float ub = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
@@ -127,14 +147,19 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
         y += bs;
         w += cs;
       }
-      if (slot == 0) {
-        si0 = i;
-        sv0 = A.h[i] * y;
-        sz0 = A.h[i] * w;
+      if (G == 1) {
+        if (slot == 0) {
+          si0 = i;
+          sv0 = A.h[i] * y;
+          sz0 = A.h[i] * w;
+        } else {
+          si1 = i;
+          sv1 = A.h[i] * y;
+          sz1 = A.h[i] * w;
+        }
       } else {
-        si1 = i;
-        sv1 = A.h[i] * y;
-        sz1 = A.h[i] * w;
+        stv[slot][lt] = A.h[i] * y;
+        stz[slot][lt] = A.h[i] * w;
       }
     }
   }
@@ -252,11 +277,11 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       float whi = 0.f;
       if (ADD) whi = ldb(P.wadd + (size_t)((i + 1)) * ps, xb);
       if (PIECE == SLI_TRUNC && i == si0) {
-        v = sv0;
-        z = sz0;
+        v = G == 1 ? sv0 : stv[0][lt];
+        z = G == 1 ? sz0 : stz[0][lt];
       } else if (PIECE == SLI_TRUNC && i == si1) {
-        v = sv1;
-        z = sz1;
+        v = G == 1 ? sv1 : stv[1][lt];
+        z = G == 1 ? sz1 : stz[1][lt];
       } else {
         v = cu.v + A.sig[i] * (ubs[grp][q][cc] + suf - g0 * sb);
         z = cu.z + A.sig[i] * sb;
