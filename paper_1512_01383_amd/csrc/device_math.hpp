@@ -253,25 +253,79 @@ __device__ __forceinline__ void tq_hull_range(float a, float c, float nu, float 
   }
 }
 
-// Projection for a straddling interval whose hull range (ml, mr) is known. Between two
-// consecutive band samples the kink (difference quotient of the parabola) is
-// a ((t_m + t_{m+1})/2 - c); only the two tangent edges need a division.
+// Projection for a straddling interval whose hull range (ml, mr) is known. The hull has
+// vertices v = 0 (first sample), v = 1 .. nb (band samples ml .. mr) and v = nb + 1 (last
+// sample); kink j lies between parts j and j + 1 of the conjugate, at the slope of the hull
+// between vertices j and j + 1 (between consecutive band samples the difference quotient
+// of the parabola, a ((t_m + t_{m+1})/2 - c)). The exterior of the epigraph is ordered:
+// strip of part 0, normal cone of kink 0, strip of part 1, ... So both the part under the
+// point (inside test) and the region holding it are found by binary search over the kinks
+// (at most 15, four halvings) instead of a pass over all vertices. A point lies left of the
+// cone of kink j if, relative to the kink, it is below it and left of the cone's left edge
+// (direction (t_j, -1)), or not below it and left of it.
 __device__ __forceinline__ void proj_tq_chain(float a, float c, float nu, float g0, float g1,
                                               int ml, int mr, float &y, float &w) {
   const float hs = (g1 - g0) * (1.f / (float)(SLI_NSUB - 1));
-  PLProj pl;
-  pl.init(y, w);
-  pl.push(g0, tq_sample(a, c, nu, g0, g1, hs, 0));
-  if (ml <= mr) {
-    pl.push(tq_t(g0, g1, hs, ml), tq_sample(a, c, nu, g0, g1, hs, ml));
-    for (int m = ml + 1; m <= mr; m++) {
-      const float tm = g0 + hs * (float)m;
-      const float d = tm - c;
-      pl.push_k(tm, 0.5f * a * d * d, a * (tm - 0.5f * hs - c));
+  const int nb = ml <= mr ? mr - ml + 1 : 0;
+  const int nk = nb + 1;   // kinks
+  auto vt = [&](int v) { return v == 0 ? g0 : (v == nb + 1 ? g1 : g0 + hs * (float)(ml + v - 1)); };
+  auto vr = [&](int v) {
+    if (v == 0) return tq_sample(a, c, nu, g0, g1, hs, 0);
+    if (v == nb + 1) return tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1);
+    if (v == 1) return tq_sample(a, c, nu, g0, g1, hs, ml);
+    const float d = vt(v) - c;
+    return 0.5f * a * d * d;
+  };
+  auto kb = [&](int j) {
+    if (j == 0 || j == nb) return (vr(j + 1) - vr(j)) * frcp(vt(j + 1) - vt(j));
+    return a * (vt(j + 1) - 0.5f * hs - c);
+  };
+  const float y0 = y, w0 = w;
+  // part under y0: the first kink at or right of it
+  int lo = 0, hi = nk;
+#pragma unroll
+  for (int it = 0; it < 4; it++)
+    if (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (y0 <= kb(m))
+        hi = m;
+      else
+        lo = m + 1;
+    }
+  if (w0 >= vt(lo) * y0 - vr(lo)) return;
+  // region: the first kink whose cone lies right of the point
+  lo = 0;
+  hi = nk;
+#pragma unroll
+  for (int it = 0; it < 4; it++)
+    if (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      const float b = kb(m), t = vt(m);
+      const float dy = y0 - b, dw = t * b - vr(m) - w0;
+      if (dw > 0.f ? dy < t * dw : dy < 0.f)
+        hi = m;
+      else
+        lo = m + 1;
+    }
+  int part = lo;   // strip of this part, unless the point sits in the cone of kink lo - 1
+  if (lo > 0) {
+    const int j = lo - 1;
+    const float b = kb(j), t = vt(j), t1 = vt(j + 1);
+    const float G = t * b - vr(j);
+    const float dy = y0 - b, dw = G - w0;
+    if (!(dw > 0.f ? dy > t1 * dw : dy > 0.f)) {
+      y = b;
+      w = G;
+      return;
     }
   }
-  pl.push(g1, tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1));
-  pl.finish(y, w);
+  const float t = vt(part), r = vr(part);
+  const float mu = (t * y0 - r - w0) * frcp(1.f + t * t);
+  float yf = y0 - mu * t;
+  if (part > 0) yf = fmaxf(yf, kb(part - 1));
+  if (part < nk) yf = fminf(yf, kb(part));
+  y = yf;
+  w = t * yf - r;
 }
 
 // Constant piece nu on [g0, g1]: the conjugate is max(g0 y, g1 y) - nu with one kink at
