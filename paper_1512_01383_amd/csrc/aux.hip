@@ -36,6 +36,11 @@ struct PieceD {
   double bshift, cshift, wlo;  // additive term
 };
 
+// 1/m and 1/(15 - m) for the hull's tangent search (no FP64 division in the loops)
+__constant__ double kInvSub[SLI_NSUB] = {0.0,       1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                         1.0 / 6,   1.0 / 7,   1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                         1.0 / 12,  1.0 / 13,  1.0 / 14, 1.0 / 15};
+
 __device__ double straddle_sample(const PieceD &P, int m) {
   double t = P.g0 + P.hs * m;
   double d = t - P.c;
@@ -142,7 +147,7 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
         double best = INFINITY;
         int ml = SLI_NSUB - 1;
         for (int m = 1; m < SLI_NSUB; m++) {
-          double sl = (straddle_sample(P, m) - r0) / m;
+          double sl = (straddle_sample(P, m) - r0) * kInvSub[m];
           if (sl <= best) {
             best = sl;
             ml = m;
@@ -151,7 +156,7 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
         best = -INFINITY;
         int mr = 0;
         for (int m = SLI_NSUB - 2; m >= 0; m--) {
-          double sl = (rN - straddle_sample(P, m)) / (SLI_NSUB - 1 - m);
+          double sl = (rN - straddle_sample(P, m)) * kInvSub[SLI_NSUB - 1 - m];
           if (sl >= best) {
             best = sl;
             mr = m;
@@ -176,10 +181,11 @@ __device__ void proj_p(const IterArgs &A, const DT *p, int i, long long x, doubl
                        double &py) {
   px = ldv(p, i * A.ps + x);
   py = ldv(p, (A.k + i) * A.ps + x);
-  double n = sqrt(px * px + py * py);
-  if (n > rad) {
-    px *= rad / n;
-    py *= rad / n;
+  const double n2 = px * px + py * py;
+  if (n2 > rad * rad) {
+    const double f = rad / sqrt(n2);
+    px *= f;
+    py *= f;
   }
 }
 
@@ -196,70 +202,102 @@ __device__ void block_sum(double *vals, int nv, double *out_row) {
     for (int q = 0; q < nv; q++) out_row[q] = red[q][0];
 }
 
+// A monitor block covers 64 consecutive pixels (one wavefront) times MT label chunks (one
+// wavefront per chunk): with one thread per pixel a 256 x 256 image would leave one
+// wavefront per SIMD. Per-pixel couplings across labels (the simplex threshold, the
+// suffix of the repaired weights, the prefix of div p, the max over labels, the
+// back-projection) go through LDS in a fixed order.
+constexpr int MT = MB / 64;
+
 // per-pixel terms: data parts of both primal bounds, dual, nonconvex data term
 template <int PIECE, bool ADD, typename DT>
 __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPtrs M) {
+  __shared__ double xa[MT][64], xb[MT][64];
+  __shared__ int xn[MT][64];
   const long long N = (long long)A.H * A.W;
-  const long long x = (long long)blockIdx.x * MB + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long x0 = (long long)blockIdx.x * 64 + lane;
+  const bool in = x0 < N;
+  const long long x = in ? x0 : 0;
+  const int k = A.k;
+  const int ch = (k + MT - 1) / MT;
+  const int i0 = min(k, t * ch), i1 = min(k, i0 + ch);
+  const int r = (int)(x / A.W), cc = (int)(x % A.W);
   double vals[4] = {0, 0, 0, 0};
-  const DT *v_ = (const DT *)M.v;
-  (void)v_;
-  if (x < N) {
-    const int k = A.k;
-    const int r = (int)(x / A.W), cc = (int)(x % A.W);
-    PieceD P;
-    // (a) repair: simplex projection of -h s by Michelot's finite algorithm
-    double xs[SLI_MAXK], w[SLI_MAXK];
-    for (int i = 0; i < k; i++) xs[i] = -D.h[i] * M.s[i * A.ps + x];
-    double theta = 0.0;
-    {
-      bool act[SLI_MAXK];
-      for (int i = 0; i < k; i++) act[i] = true;
-      for (int it = 0; it <= k; it++) {
-        double sum = 0.0;
-        int n = 0;
-        for (int i = 0; i < k; i++)
-          if (act[i]) {
-            sum += xs[i];
-            n++;
-          }
-        theta = (sum - 1.0) / n;
-        bool changed = false;
-        for (int i = 0; i < k; i++)
-          if (act[i] && xs[i] <= theta) {
-            act[i] = false;
-            changed = true;
-          }
-        if (!changed) break;
+  PieceD P;
+
+  // (a) repair: simplex projection of x = -h s by Michelot's finite algorithm. Its active
+  // set only shrinks and is always {i : x_i > theta} for the current threshold, so no
+  // per-label arrays are kept (x is re-read, the loads hit the cache). A block repeats a
+  // pass while any of its pixels still removes labels (a pass that removes nothing leaves
+  // the threshold unchanged).
+  auto xs = [&](int i) { return -D.h[i] * (double)M.s[i * A.ps + x]; };
+  double theta = -INFINITY;
+  for (int it = 0; it <= k; it++) {
+    double sum = 0.0;
+    int n = 0;
+    if (in)
+      for (int i = i0; i < i1; i++) {
+        const double xi = xs(i);
+        if (xi > theta) {
+          sum += xi;
+          n++;
+        }
       }
+    xa[t][lane] = sum;
+    xn[t][lane] = n;
+    __syncthreads();
+    double S = 0.0;
+    int Nn = 0;
+#pragma unroll
+    for (int g = 0; g < MT; g++) {
+      S += xa[g][lane];
+      Nn += xn[g][lane];
     }
-    for (int i = 0; i < k; i++) w[i] = xs[i] > theta ? xs[i] - theta : 0.0;
-    double lo = 0.0, dat = 0.0;
-    for (int i = k - 1; i >= 0; i--) {
+    const double th = Nn > 0 ? (S - 1.0) / Nn : theta;
+    int removed = 0;
+    if (in)
+      for (int i = i0; i < i1; i++) {
+        const double xi = xs(i);
+        removed += (xi > theta && xi <= th);
+      }
+    theta = th;
+    if (!__syncthreads_or(removed)) break;
+  }
+  // repaired weights w_i = max(x_i - theta, 0); u_i clamped into [sum_{j>i} w_j, sum_{j>=i} w_j]
+  double tw = 0.0;
+  if (in)
+    for (int i = i0; i < i1; i++) tw += fmax(xs(i) - theta, 0.0);
+  xa[t][lane] = tw;
+  __syncthreads();
+  double lo = 0.0;
+#pragma unroll
+  for (int g = MT - 1; g >= 0; g--)
+    if (g > t) lo += xa[g][lane];
+  double dat = 0.0;
+  if (in)
+    for (int i = i1 - 1; i >= i0; i--) {
+      const double xi = xs(i);
+      const double wi = xi > theta ? xi - theta : 0.0;
       double al = 0.0;
-      if (w[i] > 0.0) al = fmin(fmax((M.u[i * A.ps + x] - lo) / w[i], 0.0), 1.0);
-      M.mon_u[i * A.ps + x] = lo + w[i] * al;
-      if (w[i] > 0.0) {
+      if (wi > 0.0) al = fmin(fmax((M.u[i * A.ps + x] - lo) / wi, 0.0), 1.0);
+      M.mon_u[i * A.ps + x] = lo + wi * al;
+      if (wi > 0.0) {
         make_piece<PIECE, ADD>(A, D, M, x, i, P);
-        dat += w[i] * val_full(P, D.gam[i] + D.h[i] * al);
+        dat += wi * val_full(P, D.gam[i] + D.h[i] * al);
       }
-      lo += w[i];
+      lo += wi;
     }
-    vals[0] = dat;
-    // (b) graph lifting of the back-projected u
-    double t = D.gam[0];
-    for (int i = 0; i < k; i++) t += D.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
-    M.mon_b[x] = t;
-    int is = 0;
-    while (is < k - 1 && t > D.gam[is + 1]) is++;
-    double al = fmin(fmax((t - D.gam[is]) / D.h[is], 0.0), 1.0);
-    make_piece<PIECE, ADD>(A, D, M, x, is, P);
-    vals[1] = val_full(P, D.gam[is] + D.h[is] * al);
-    // dual bound
-    const DT *p = (const DT *)M.p;
-    double mx = -INFINITY, pre = 0.0;
-    for (int i = 0; i < k; i++) {
-      double rad = D.lam * D.h[i];
+  vals[0] = dat;
+
+  // dual bound: max over labels of sum_{j<i} vh_j - gamma_i vh_i/h_i + rho_i^*(vh_i/h_i),
+  // vh = div of p projected onto K; each chunk forms its local prefix and maximum
+  const DT *p = (const DT *)M.p;
+  double mloc = -INFINITY, pre = 0.0, ub = 0.0;
+  if (in)
+    for (int i = i0; i < i1; i++) {
+      const double rad = D.lam * D.h[i];
       double px, py, qx, qy;
       proj_p(A, p, i, x, rad, px, py);
       double vh = 0.0;
@@ -274,27 +312,49 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
         vh -= qy;
       }
       make_piece<PIECE, ADD>(A, D, M, x, i, P);
-      double y = vh / D.h[i];
-      double val = pre - D.gam[i] * y + conj_full(P, y);
-      mx = fmax(mx, val);
+      const double y = vh / D.h[i];
+      mloc = fmax(mloc, pre - D.gam[i] * y + conj_full(P, y));
       pre += vh;
+      ub += D.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
+    }
+  __syncthreads();   // every read of xa above is done
+  xa[t][lane] = mloc;
+  xb[t][lane] = pre;
+  __shared__ double xu[MT][64];
+  xu[t][lane] = ub;
+  __syncthreads();
+  if (t == 0 && in) {
+    double base = 0.0, mx = -INFINITY, tsum = D.gam[0];
+#pragma unroll
+    for (int g = 0; g < MT; g++) {
+      mx = fmax(mx, base + xa[g][lane]);
+      base += xb[g][lane];
+      tsum += xu[g][lane];
     }
     vals[2] = -mx;
+    // (b) graph lifting of the back-projected u
+    const double tt = tsum;
+    M.mon_b[x] = tt;
+    int is = 0;
+    while (is < k - 1 && tt > D.gam[is + 1]) is++;
+    const double al = fmin(fmax((tt - D.gam[is]) / D.h[is], 0.0), 1.0);
+    make_piece<PIECE, ADD>(A, D, M, x, is, P);
+    vals[1] = val_full(P, D.gam[is] + D.h[is] * al);
     // nonconvex data term at the back-projected value
     double e;
     if (PIECE == SLI_SAMPLED) {
       int m = 0;
-      while (m < A.M - 2 && t > M.taud[m + 1]) m++;
-      double a2 = (t - M.taud[m]) / (M.taud[m + 1] - M.taud[m]);
+      while (m < A.M - 2 && tt > M.taud[m + 1]) m++;
+      const double a2 = (tt - M.taud[m]) / (M.taud[m + 1] - M.taud[m]);
       const float *raw = M.cost + (long long)A.M * A.ps;
       e = (1.0 - a2) * raw[m * A.ps + x] + a2 * raw[(m + 1) * A.ps + x];
     } else {
-      double d = t - ((double)M.f_orig[x] - D.shift) / D.scale;
+      const double d = tt - ((double)M.f_orig[x] - D.shift) / D.scale;
       e = 0.5 * D.a * d * d;
       if (PIECE == SLI_TRUNC && e > D.nu) e = D.nu;
     }
     if (ADD) {
-      double a3 = (t - D.gam[is]) / D.h[is];
+      const double a3 = (tt - D.gam[is]) / D.h[is];
       e += (1.0 - a3) * M.wadd[is * A.ps + x] + a3 * M.wadd[(is + 1) * A.ps + x];
     }
     vals[3] = e;
@@ -302,10 +362,14 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
   block_sum(vals, 4, M.part1 + (long long)blockIdx.x * SLI_NMON);
 }
 
-// TV terms of both primal points and of the back-projected u
+// TV terms of both primal points and of the back-projected u (64 pixels x MT label chunks)
 __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs M) {
   const long long N = (long long)A.H * A.W;
-  const long long x = (long long)blockIdx.x * MB + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int t = (int)(threadIdx.x >> 6);
+  const long long x = (long long)blockIdx.x * 64 + lane;
+  const int ch = (A.k + MT - 1) / MT;
+  const int i0 = min(A.k, t * ch), i1 = min(A.k, i0 + ch);
   double vals[3] = {0, 0, 0};
   if (x < N) {
     const int r = (int)(x / A.W), cc = (int)(x % A.W);
@@ -313,7 +377,7 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
     const double *b = M.mon_b;
     const double *mu = M.mon_u;
     double tr = 0.0, tg = 0.0;
-    for (int i = 0; i < A.k; i++) {
+    for (int i = i0; i < i1; i++) {
       double u0 = mu[i * A.ps + x];
       double gx = hx ? mu[i * A.ps + x + 1] - u0 : 0.0;
       double gy = hy ? mu[i * A.ps + x + A.W] - u0 : 0.0;
@@ -324,10 +388,12 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
       double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
       tg += D.h[i] * sqrt(lx * lx + ly * ly);
     }
-    double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
     vals[0] = tr;
     vals[1] = tg;
-    vals[2] = sqrt(bx * bx + by * by);
+    if (t == 0) {
+      double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
+      vals[2] = sqrt(bx * bx + by * by);
+    }
   }
   block_sum(vals, 3, M.part2 + (long long)blockIdx.x * SLI_NMON);
 }
@@ -470,7 +536,7 @@ inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, MB); }
+int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, 64); }
 
 hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonArgs &D,
                           const MonPtrs &M, hipStream_t st, int *nb_out) {
