@@ -106,6 +106,31 @@ __device__ double val_full(const PieceD &P, double t) {
   return val0(P, t) + P.wlo + P.bshift * (t - P.g0);
 }
 
+// tangent points of the lower hull of a straddling interval's samples (the band samples
+// lie on a strictly convex parabola, all others at nu): ml has the least slope seen from
+// the first sample, mr the largest slope towards the last one
+__device__ void hull_range_d(const PieceD &P, int &ml, int &mr) {
+  const double r0 = straddle_sample(P, 0), rN = straddle_sample(P, SLI_NSUB - 1);
+  double best = INFINITY;
+  ml = SLI_NSUB - 1;
+  for (int m = 1; m < SLI_NSUB; m++) {
+    const double sl = (straddle_sample(P, m) - r0) * kInvSub[m];
+    if (sl <= best) {
+      best = sl;
+      ml = m;
+    }
+  }
+  best = -INFINITY;
+  mr = 0;
+  for (int m = SLI_NSUB - 2; m >= 0; m--) {
+    const double sl = (rN - straddle_sample(P, m)) * kInvSub[SLI_NSUB - 1 - m];
+    if (sl >= best) {
+      best = sl;
+      mr = m;
+    }
+  }
+}
+
 template <int PIECE, bool ADD>
 __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long x,
                            int i, PieceD &P) {
@@ -142,29 +167,12 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
         P.kind = 1;
         P.mode = 2;
         P.hs = (P.g1 - P.g0) / (SLI_NSUB - 1);
-        // tangent points of the lower hull (see the FP32 version in device_math.hpp)
-        double r0 = straddle_sample(P, 0), rN = straddle_sample(P, SLI_NSUB - 1);
-        double best = INFINITY;
-        int ml = SLI_NSUB - 1;
-        for (int m = 1; m < SLI_NSUB; m++) {
-          double sl = (straddle_sample(P, m) - r0) * kInvSub[m];
-          if (sl <= best) {
-            best = sl;
-            ml = m;
-          }
-        }
-        best = -INFINITY;
-        int mr = 0;
-        for (int m = SLI_NSUB - 2; m >= 0; m--) {
-          double sl = (rN - straddle_sample(P, m)) * kInvSub[SLI_NSUB - 1 - m];
-          if (sl >= best) {
-            best = sl;
-            mr = m;
-          }
-        }
-        P.ml = ml;
-        P.mr = mr;
-        P.nv = 2 + (ml <= mr ? mr - ml + 1 : 0);
+        // tangent points of the lower hull, from the per-pixel FP64 table built at set-up
+        const unsigned info = M.sinfod[x];
+        const unsigned f = ((info & 31u) == (unsigned)i) ? info : (info >> 13);
+        P.ml = (int)((f >> 5) & 15u);
+        P.mr = (int)((f >> 9) & 15u);
+        P.nv = 2 + (P.ml <= P.mr ? P.mr - P.ml + 1 : 0);
       }
     }
   }
@@ -477,24 +485,38 @@ __global__ void k_convexify(const float *samples, float *cost, const double *tau
 
 // Classification of every interval against the band |t - f| <= sqrt(2 nu / a), with the same
 // float decisions as the iteration, and the hull tangent range of the straddling ones.
-__global__ void k_straddle_info(const float *fn, unsigned *sinfo, IterArgs A) {
+// per pixel: the (at most two) straddling intervals with their hull tangent ranges, once in
+// FP32 for the iteration and once in FP64 for the monitor (same float classification)
+__global__ void k_straddle_info(const float *fn, const float *f_orig, unsigned *sinfo, unsigned *sinfod,
+                                IterArgs A, MonArgs D) {
   const long long N = (long long)A.H * A.W;
   const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= N) return;
   const float fc = fn[x];
   const float lo = fc - A.del, hb = fc + A.del;
-  unsigned info = 31u | (31u << 13);
+  unsigned info = 31u | (31u << 13), infod = info;
   int slot = 0;
+  PieceD P;
+  P.a = D.a;
+  P.nu = D.nu;
+  P.c = ((double)f_orig[x] - D.shift) / D.scale;
   for (int i = 0; i < A.k && slot < 2; i++) {
     const float g0 = A.gam[i], g1 = A.gam[i + 1];
     if ((lo <= g0 && g1 <= hb) || (g1 <= lo || g0 >= hb)) continue;
     int ml, mr;
     tq_hull_range(A.a, fc, A.nu, g0, g1, ml, mr);
-    const unsigned f = (unsigned)i | ((unsigned)ml << 5) | ((unsigned)mr << 9);
+    unsigned f = (unsigned)i | ((unsigned)ml << 5) | ((unsigned)mr << 9);
     info = (info & ~(0x1fffu << (13 * slot))) | (f << (13 * slot));
+    P.g0 = D.gam[i];
+    P.g1 = D.gam[i + 1];
+    P.hs = (P.g1 - P.g0) / (SLI_NSUB - 1);
+    hull_range_d(P, ml, mr);
+    f = (unsigned)i | ((unsigned)ml << 5) | ((unsigned)mr << 9);
+    infod = (infod & ~(0x1fffu << (13 * slot))) | (f << (13 * slot));
     slot++;
   }
   sinfo[x] = info;
+  sinfod[x] = infod;
 }
 
 __global__ void k_readout(const float *u, float *ulift, float *uout, IterArgs A, MonArgs D) {
@@ -584,10 +606,10 @@ hipError_t launch_convexify(const float *samples, float *cost, const double *tau
   return hipGetLastError();
 }
 
-hipError_t launch_straddle_info(const float *fn, unsigned *sinfo, const IterArgs &A,
-                                hipStream_t st) {
+hipError_t launch_straddle_info(const float *fn, const float *f_orig, unsigned *sinfo, unsigned *sinfod,
+                                const IterArgs &A, const MonArgs &D, hipStream_t st) {
   long long N = (long long)A.H * A.W;
-  hipLaunchKernelGGL(k_straddle_info, dim3(nblk(N, 256)), dim3(256), 0, st, fn, sinfo, A);
+  hipLaunchKernelGGL(k_straddle_info, dim3(nblk(N, 256)), dim3(256), 0, st, fn, f_orig, sinfo, sinfod, A, D);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   long long N, ps;
   size_t off_u, off_s, off_v, off_z, off_p, off_qd, off_fn, off_forig, off_w, off_cost, off_tau,
-      off_taud, off_sinfo;
+      off_taud, off_sinfo, off_sinfod;
   size_t off_monu, off_monb, off_part1, off_part2, off_fin, off_flag, total;
   size_t off_ysave, off_rpart, off_rfin;  // step control: duals before an iteration, residual sums
   size_t state_lo, state_hi;  // contiguous range holding u, s, v, z, p, qd
@@ -74,6 +74,7 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   L.off_fn = take(sampled ? 0 : pf);
   L.off_forig = take(sampled ? 0 : pf);
   L.off_sinfo = take(d->rho == SL_RHO_TRUNC_QUAD ? pf : 0);
+  L.off_sinfod = take(d->rho == SL_RHO_TRUNC_QUAD ? pf : 0);
   L.off_w = take((!sampled && d->samples) ? (size_t)d->L * pf : 0);
   L.off_cost = take(sampled ? (size_t)2 * d->M * pf : 0);
   L.off_tau = take(sampled ? (size_t)d->M * 4 : 0);
@@ -358,6 +359,7 @@ sl_status monitor(sl_problem_ *P, sl_report *out) {
   M.cost = (const float *)(P->ws + P->lay.off_cost);
   M.f_orig = (const float *)(P->ws + P->lay.off_forig);
   M.taud = (const double *)(P->ws + P->lay.off_taud);
+  M.sinfod = (const unsigned *)(P->ws + P->lay.off_sinfod);
   M.mon_u = (double *)(P->ws + P->lay.off_monu);
   M.mon_b = (double *)(P->ws + P->lay.off_monb);
   M.part1 = (double *)(P->ws + P->lay.off_part1);
@@ -798,8 +800,9 @@ static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes
     if ((e = launch_copy_planes(desc->f, (float *)(P->ws + lay.off_forig), 1, N, lay.ps, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "copy f"));
     if (P->piece == SLI_TRUNC &&
-        (e = launch_straddle_info((const float *)(P->ws + lay.off_fn), (unsigned *)(P->ws + lay.off_sinfo),
-                                  P->A, P->st)) != hipSuccess)
+        (e = launch_straddle_info((const float *)(P->ws + lay.off_fn), (const float *)(P->ws + lay.off_forig),
+                                  (unsigned *)(P->ws + lay.off_sinfo), (unsigned *)(P->ws + lay.off_sinfod),
+                                  P->A, P->D, P->st)) != hipSuccess)
       return cleanup(hip_fail(e, "straddle info"));
     if (P->add &&
         (e = launch_copy_planes(desc->samples, (float *)(P->ws + lay.off_w), desc->L, N, lay.ps, P->st)) != hipSuccess)

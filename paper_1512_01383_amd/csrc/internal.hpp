@@ -97,6 +97,7 @@ struct MonPtrs {
   const float *qd, *fn, *wadd, *cost;
   const float *f_orig;    // caller's f (QUAD, TRUNC_QUAD)
   const double *taud;     // normalised sample positions in double (SAMPLED)
+  const unsigned *sinfod; // straddling intervals with FP64 hull ranges (TRUNC_QUAD)
   double *mon_u, *mon_b;
   double *part1, *part2, *final_;
   int bf16;
@@ -115,7 +116,9 @@ hipError_t launch_convexify(const float *samples, float *cost, const double *tau
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
 // per pixel: labels and hull tangent ranges of the (at most two) truncated-quadratic
 // intervals that straddle a band edge, packed as 2 x (label:5, ml:4, mr:4) bits, label 31 = none
-hipError_t launch_straddle_info(const float *fn, unsigned *sinfo, const IterArgs &A, hipStream_t st);
+// (sinfod: the same in FP64 from f_orig for the monitor, whose hull is that of the exact samples)
+hipError_t launch_straddle_info(const float *fn, const float *f_orig, unsigned *sinfo, unsigned *sinfod,
+                                const IterArgs &A, const MonArgs &D, hipStream_t st);
 hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterArgs &A,
                           const MonArgs &D, hipStream_t st);
 hipError_t launch_pack_state(const void *const *planes, const int *bf16, int nplanes,
