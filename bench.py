@@ -75,9 +75,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="tq", choices=["tq", "batch"],
+    ap.add_argument("--workload", default="tq", choices=["tq", "batch", "diff"],
                     help="tq: one truncated-quadratic instance (default); batch: 64 mixed "
-                         "instances in one persistent launch per iteration")
+                         "instances in one persistent launch per iteration; diff: forward and "
+                         "backward of 200 unrolled iterations (256x256, L=8)")
     ap.add_argument("--batch-iters", type=int, default=240)
     ap.add_argument("--batch-gap", type=float, default=0.0,
                     help="batch mode: also time run-to-gap at this tolerance (0 = skip)")
@@ -96,6 +97,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "diff":
+        return bench_diff(args)
 
     wl = W.truncated_quadratic(L=args.L, H=args.size, W=args.size)
     dev = torch.device("cuda:0")
@@ -291,6 +294,78 @@ def bench_batch(args):
                   "hbm_gbs_algorithmic": bytes_it * n_it / t_batch / 1e9,
                   "hbm_frac": bytes_it * n_it / t_batch / 1e9 / HBM_PEAK_GBS},
         "time_to_gap": gap,
+    }
+    print(json.dumps(out))
+
+
+def bench_diff(args):
+    """Unrolled differentiation: K = 200 iterations with a checkpoint every 20 on the
+    256x256, L = 8 truncated-quadratic instance with per-label additive values; loss =
+    squared error of the read-out against the clean image; gradients w.r.t. f, lambda and
+    the 8 x 256 x 256 additive values. Compared with the plain solve of the same instance to
+    a 1e-3 certified gap (adaptive steps) on the same GPU."""
+    import numpy as np
+    import torch
+
+    import paper_1512_01383_amd as S
+    import workloads as W
+
+    wl = W.differentiation()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K, C = 200, 20
+    tgt = torch.as_tensor(wl.target, device=dev)
+
+    def one():
+        p = S.Problem.from_workload(wl, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.unrolled_forward(K, C)
+        _, u = p.read_u()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gf, gl, gw = p.unrolled_backward(2.0 * (u - tgt))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        p.close()
+        return t1 - t0, t2 - t1, gl
+
+    for _ in range(max(1, args.warmup)):
+        one()
+    fw, bw = [], []
+    for _ in range(max(1, args.steps)):
+        a, b, gl = one()
+        fw.append(a)
+        bw.append(b)
+    t_f, t_b = float(np.median(fw)), float(np.median(bw))
+    g2 = S.Problem.from_workload(wl, device=dev, adaptive=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_gap = g2.run_to_gap(1e-3, args.gap_max_iters)
+    t_gap = time.perf_counter() - t0
+    rep = g2.energy()
+    g2.close()
+    pli = wl.H * wl.W * wl.k * K
+    out = {
+        "metric": "lifted PDHG pixel-label-iter/s",
+        "value": pli / (t_f + t_b),
+        "unit": "pixel-label-iter/s",
+        "n_gpus": 1,
+        "steps": len(fw),
+        "warmup": max(1, args.warmup),
+        "ms_per_step": (t_f + t_b) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "unrolled differentiation, truncated quadratic 256x256, L=8, K=200 "
+                               "iterations, checkpoint every 20; step = forward + backward",
+                   "K": K, "C": C},
+        "differentiation": {"forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+                            "backward_over_forward": t_b / t_f, "grad_lambda": gl,
+                            "plain_solve_to_1e-3": {"seconds": t_gap, "iterations": n_gap,
+                                                    "rel_gap": rep["rel_gap"]}},
     }
     print(json.dumps(out))
 
