@@ -80,8 +80,9 @@ def main():
                          "instances in one persistent launch per iteration; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
     ap.add_argument("--batch-iters", type=int, default=240)
-    ap.add_argument("--batch-gap", type=float, default=0.0,
-                    help="batch mode: also time run-to-gap at this tolerance (0 = skip)")
+    ap.add_argument("--batch-gap", type=float, default=1e-3,
+                    help="batch mode: also time every member to this certified gap with "
+                         "adaptive steps, batched and one after another (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -252,7 +253,7 @@ def bench_batch(args):
 
     gap = None
     if args.batch_gap > 0:
-        b = S.BatchProblem(wls, storage=args.storage, device=dev)
+        b = S.BatchProblem(wls, storage=args.storage, device=dev, adaptive=True)
         b.set_tiling(*tiling)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -262,7 +263,8 @@ def bench_batch(args):
         b.close()
         t_s, reached_s = 0.0, 0
         for w in wls:
-            g = S.Problem.from_workload(w, storage=args.storage, device=dev)
+            g = S.Problem.from_workload(w, storage=args.storage, device=dev, adaptive=True,
+                                        check_every=48)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             g.run_to_gap(args.batch_gap, args.gap_max_iters)

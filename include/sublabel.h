@@ -90,7 +90,7 @@ typedef struct {
   int32_t normalize_labels;/* 1: iterate on the labels mapped affinely onto [0,1] (an
                               exact reparametrisation; energies are unchanged)            */
   int32_t adaptive_steps;  /* 1: sl_run_to_gap balances the steps by the residuals (see
-                              sl_set_step_balance); 0: fixed steps. Not for batches.      */
+                              sl_residuals); 0: fixed steps. In a batch, per member.      */
 } sl_problem_desc;
 
 #define SL_MAX_LABELS 28      /* k = L-1 <= 27                                           */
@@ -232,8 +232,9 @@ sl_status sl_get_step_balance(sl_problem p, double *c);
  * end of every check interval and rescales the balance c: if the primal residual
  * exceeds 1.5 s times the dual one (s: sl_set_residual_target), the primal steps grow by
  * 1/(1 - alpha); if it is below s/1.5 times the dual one, the dual steps do (alpha = 0.5,
- * times 0.95 after every change; c stays in [1/4096, 4096]). Synchronises the stream. Not
- * for batches (SL_ERR_UNSUPPORTED). */
+ * times 0.95 after every change; c stays in [1/4096, 4096]). In a batch, every member with
+ * adaptive_steps = 1 is rebalanced this way from its own residuals. Synchronises the stream.
+ * sl_residuals itself takes a single-problem handle (SL_ERR_UNSUPPORTED for a batch). */
 sl_status sl_residuals(sl_problem p, double *primal, double *dual);
 
 /* Target ratio s of the primal to the dual residual for the adaptive balance (the residual

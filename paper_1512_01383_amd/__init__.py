@@ -265,7 +265,7 @@ class Problem:
         return rp.value, rd.value
 
     def set_residual_target(self, s: float):
-        """Target ratio of primal to dual residual for the adaptive balance (default 1)."""
+        """Target ratio of primal to dual residual for the adaptive balance (default 0.003)."""
         _check(lib().sl_set_residual_target(self.h, float(s)))
 
     def set_step_balance(self, c: float):

@@ -548,16 +548,44 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
   return SL_OK;
 }
 
+sl_status save_duals(sl_problem_ *P);
+sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd);
+void adapt_balance(sl_problem_ *P, double rp, double rd);
+
 sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
   const int chunk = std::max(6, (P->check_every + 5) / 6 * 6);
   int32_t n = 0;
   while (n < max_iters) {
-    bool any = false;
-    for (char a : P->active) any |= a != 0;
+    bool any = false, adapt = false;
+    for (size_t i = 0; i < P->sub.size(); i++) {
+      any |= P->active[i] != 0;
+      adapt |= P->active[i] && P->sub[i]->d.adaptive_steps;
+    }
     if (!any) break;
     const int c = std::min(chunk, max_iters - n);
-    sl_status s = batch_enqueue(P, c);
-    if (s != SL_OK) return s;
+    sl_status s;
+    if (adapt) {
+      // as for a single problem: the interval's last iteration measures each member's
+      // residuals, which rebalance that member's steps (parameter table re-uploaded; a
+      // captured graph reads it from device memory)
+      if ((s = batch_enqueue(P, c - 1)) != SL_OK) return s;
+      for (size_t i = 0; i < P->sub.size(); i++)
+        if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = save_duals(P->sub[i])) != SL_OK) return s;
+      if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
+      for (size_t i = 0; i < P->sub.size(); i++) {
+        if (!P->active[i] || !P->sub[i]->d.adaptive_steps) continue;
+        double rp = 0.0, rd = 0.0;
+        if ((s = residuals_of_last(P->sub[i], &rp, &rd)) != SL_OK) return s;
+        adapt_balance(P->sub[i], rp, rd);
+        P->args_host[i] = P->sub[i]->A;
+      }
+      HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
+                            hipMemcpyHostToDevice, P->st),
+             "batch parameters");
+      HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
+    } else if ((s = batch_enqueue(P, c)) != SL_OK) {
+      return s;
+    }
     n += c;
     bool changed = false;
     for (size_t i = 0; i < P->sub.size(); i++) {
@@ -578,8 +606,8 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
   return SL_OK;
 }
 
-// One iteration with the residual norms of its step (primal, dual; l1, FP64).
-sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
+// v, z, q before an iteration (the residuals compare them with the values after it)
+sl_status save_duals(sl_problem_ *P) {
   const int k = P->A.k;
   const size_t pdb = (size_t)P->lay.ps * P->esz(), pfb = (size_t)P->lay.ps * 4;
   char *ys = P->ws + P->lay.off_ysave;
@@ -589,8 +617,14 @@ sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
   HIPCHK(launch_copy2((const float *)(P->ws + P->lay.off_qd), (float *)(ys + 2 * k * pdb), pfb / 4, nullptr,
                       nullptr, 0, P->st),
          "save duals");
-  sl_status s = enqueue_iters(P, 1);
-  if (s != SL_OK) return s;
+  return SL_OK;
+}
+
+// residual norms of the iteration that followed save_duals (synchronises)
+sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
+  const int k = P->A.k;
+  const size_t pdb = (size_t)P->lay.ps * P->esz();
+  char *ys = P->ws + P->lay.off_ysave;
   ResPtrs R;
   R.u = P->ubuf(P->iu);
   R.up = P->ubuf((P->iu + 2) % 3);
@@ -613,6 +647,14 @@ sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
   *rp = h[0];
   *rd = h[1];
   return SL_OK;
+}
+
+// One iteration with the residual norms of its step (primal, dual; l1, FP64).
+sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
+  sl_status s = save_duals(P);
+  if (s == SL_OK) s = enqueue_iters(P, 1);
+  if (s == SL_OK) s = residuals_of_last(P, rp, rd);
+  return s;
 }
 
 // Residual balancing: a primal residual more than 1.5 times s times the dual one enlarges
@@ -938,9 +980,6 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   if (s != SL_OK) return s;
   if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
   if (bytes < need) return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, need);
-  for (int i = 0; i < n; i++)
-    if (descs[i].adaptive_steps)
-      return fail(SL_ERR_UNSUPPORTED, "instance %d: adaptive steps in a batch are not built", i);
   for (int i = 1; i < n; i++)
     if (descs[i].rho != descs[0].rho || descs[i].storage != descs[0].storage ||
         (descs[i].samples != nullptr) != (descs[0].samples != nullptr))
@@ -1285,6 +1324,7 @@ sl_status sl_set_residual_target(sl_problem P, double s) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (!(s > 0.0) || !isfinite(s)) return fail(SL_ERR_INVALID_ARG, "the target must be finite and > 0");
   P->adapt_s = s;
+  for (sl_problem_ *q : P->sub) q->adapt_s = s;
   return SL_OK;
 }
 

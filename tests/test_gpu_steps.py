@@ -93,7 +93,22 @@ def test_adaptive_run_reaches_gap_and_brackets_oracle(orc):
     assert g2.get_step_balance() == c and g2.energy()["best_primal"] == e["best_primal"]
 
 
-def test_adaptive_rejected_for_batches():
-    wls = [W.truncated_quadratic(L=4, H=8, W=20, seed=s) for s in (1, 2)]
-    with pytest.raises(S.SublabelError):
-        S.BatchProblem(wls, adaptive=True)
+def test_batch_adaptive_members_equal_lone_adaptive_runs():
+    """Every batch member is rebalanced from its own residuals exactly as a lone adaptive
+    solve with the same tiling and check interval: same iterations, same iterates."""
+    wls = [W.truncated_quadratic(L=4, H=24, W=70, seed=61), W.truncated_quadratic(L=6, H=30, W=64, seed=62),
+           W.truncated_quadratic(L=8, H=16, W=90, seed=63)]
+    b = S.BatchProblem(wls, check_every=48, adaptive=True)
+    tiling = b.get_tiling()
+    b.run_to_gap(1e-3, 30000)
+    for i, wl in enumerate(wls):
+        g = S.Problem.from_workload(wl, check_every=48, adaptive=True)
+        g.set_tiling(*tiling)
+        n = g.run_to_gap(1e-3, 30000)
+        nb, active = b.info_of(i)
+        print(f"member {i} L={wl.L}: lone {n} iterations, batch {nb}, balance {g.get_step_balance():.4g}")
+        assert nb == n and not active
+        assert torch.equal(b.read_u_of(i)[0], g.read_u()[0])
+        assert b.energy_of(i)["rel_gap"] <= 1e-3
+        g.close()
+    b.close()
