@@ -172,6 +172,7 @@ struct sl_problem_ {
   IterArgs A{};
   MonArgs D{};
   double shift = 0, scale = 1, lam = 0;
+  double *fin_dev = nullptr;  // batch member: its monitor / residual sums go to the batch's array
   double step_c = 1.0;  // balance of dual against primal steps (sigma * c, tau / c)
   double adapt_alpha = 0.5;  // current relative change of the balance (adaptive steps)
   double adapt_s = 0.003;    // target ratio of the primal to the dual residual
@@ -200,6 +201,8 @@ struct sl_problem_ {
   int *count_dev = nullptr, *counter_dev = nullptr;
   void *ptrs_dev = nullptr;
   IterArgs *args_dev = nullptr;
+  double *bfin_dev = nullptr;      // 16 doubles per member: monitor sums, residual sums
+  std::vector<double> bfin_host;
   std::vector<char> ptrs_host;
   std::vector<IterArgs> args_host;
   int kmax = 0;
@@ -346,7 +349,10 @@ sl_status enqueue_iters(sl_problem_ *P, int iters) {
   return SL_OK;
 }
 
-sl_status monitor(sl_problem_ *P, sl_report *out) {
+double *mon_out(sl_problem_ *P) { return P->fin_dev ? P->fin_dev : (double *)(P->ws + P->lay.off_fin); }
+
+// FP64 monitor of the current iterate, enqueued (its 7 sums land at mon_out(P))
+sl_status monitor_enqueue(sl_problem_ *P) {
   MonPtrs M;
   M.u = P->ubuf(P->iu);
   M.s = P->sbuf(P->is);
@@ -364,12 +370,14 @@ sl_status monitor(sl_problem_ *P, sl_report *out) {
   M.mon_b = (double *)(P->ws + P->lay.off_monb);
   M.part1 = (double *)(P->ws + P->lay.off_part1);
   M.part2 = (double *)(P->ws + P->lay.off_part2);
-  M.final_ = (double *)(P->ws + P->lay.off_fin);
+  M.final_ = mon_out(P);
   M.bf16 = P->bf16;
   HIPCHK(launch_monitor(P->piece, P->add, P->A, P->D, M, P->st, nullptr), "monitor launch");
-  HIPCHK(hipMemcpyAsync(P->fin, M.final_, 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
-         "monitor copy");
-  HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
+  return SL_OK;
+}
+
+// the report from the monitor sums in P->fin (best-so-far bounds updated)
+sl_status monitor_finish(sl_problem_ *P, sl_report *out) {
   const double lam = P->lam;
   const double pr = P->fin[0] + lam * P->fin[4];
   const double pg = P->fin[1] + lam * P->fin[5];
@@ -394,6 +402,15 @@ sl_status monitor(sl_problem_ *P, sl_report *out) {
     out->iters = P->iters;
   }
   return SL_OK;
+}
+
+sl_status monitor(sl_problem_ *P, sl_report *out) {
+  sl_status s = monitor_enqueue(P);
+  if (s != SL_OK) return s;
+  HIPCHK(hipMemcpyAsync(P->fin, mon_out(P), 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
+         "monitor copy");
+  HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
+  return monitor_finish(P, out);
 }
 
 void state_planes(sl_problem_ *P, std::vector<const void *> &pl, std::vector<int> &bf) {
@@ -458,7 +475,7 @@ size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
   size_t items = 0;
   for (int t : maxtiles) items += (size_t)t;
   return align256(items * sizeof(BatchItem)) + 256 + align256((size_t)n * 6 * sizeof(IterPtrs<float>)) +
-         align256((size_t)n * sizeof(IterArgs));
+         align256((size_t)n * sizeof(IterArgs)) + align256((size_t)n * 16 * sizeof(double));
 }
 
 // work list of the active instances, costliest (k x tiles) first, tiles in row-major order
@@ -549,7 +566,7 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
 }
 
 sl_status save_duals(sl_problem_ *P);
-sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd);
+sl_status residuals_enqueue(sl_problem_ *P);
 void adapt_balance(sl_problem_ *P, double rp, double rd);
 
 sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
@@ -572,11 +589,15 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       for (size_t i = 0; i < P->sub.size(); i++)
         if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = save_duals(P->sub[i])) != SL_OK) return s;
       if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
+      for (size_t i = 0; i < P->sub.size(); i++)
+        if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = residuals_enqueue(P->sub[i])) != SL_OK) return s;
+      HIPCHK(hipMemcpyAsync(P->bfin_host.data(), P->bfin_dev, P->bfin_host.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, P->st),
+             "residual copy");
+      HIPCHK(hipStreamSynchronize(P->st), "residual sync");
       for (size_t i = 0; i < P->sub.size(); i++) {
         if (!P->active[i] || !P->sub[i]->d.adaptive_steps) continue;
-        double rp = 0.0, rd = 0.0;
-        if ((s = residuals_of_last(P->sub[i], &rp, &rd)) != SL_OK) return s;
-        adapt_balance(P->sub[i], rp, rd);
+        adapt_balance(P->sub[i], P->bfin_host[i * 16 + 8], P->bfin_host[i * 16 + 9]);
         P->args_host[i] = P->sub[i]->A;
       }
       HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
@@ -587,11 +608,19 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       return s;
     }
     n += c;
+    // every active member's monitor, then one copy and one wait for all of them
+    for (size_t i = 0; i < P->sub.size(); i++)
+      if (P->active[i] && (s = monitor_enqueue(P->sub[i])) != SL_OK) return s;
+    HIPCHK(hipMemcpyAsync(P->bfin_host.data(), P->bfin_dev, P->bfin_host.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, P->st),
+           "monitor copy");
+    HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
     bool changed = false;
     for (size_t i = 0; i < P->sub.size(); i++) {
       if (!P->active[i]) continue;
+      memcpy(P->sub[i]->fin, &P->bfin_host[i * 16], 7 * sizeof(double));
       sl_report r;
-      if ((s = monitor(P->sub[i], &r)) != SL_OK) {
+      if ((s = monitor_finish(P->sub[i], &r)) != SL_OK) {
         if (done) *done = n;
         return s;
       }
@@ -620,8 +649,13 @@ sl_status save_duals(sl_problem_ *P) {
   return SL_OK;
 }
 
-// residual norms of the iteration that followed save_duals (synchronises)
-sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
+double *res_out(sl_problem_ *P) {
+  return P->fin_dev ? P->fin_dev + 8 : (double *)(P->ws + P->lay.off_rfin);
+}
+
+// residual norms of the iteration that followed save_duals, enqueued (2 sums at res_out(P));
+// residuals_of_last also waits for them
+sl_status residuals_enqueue(sl_problem_ *P) {
   const int k = P->A.k;
   const size_t pdb = (size_t)P->lay.ps * P->esz();
   char *ys = P->ws + P->lay.off_ysave;
@@ -639,10 +673,15 @@ sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
   R.p = P->pbuf(P->ip);
   R.po = P->pbuf(1 - P->ip);
   R.part = (double *)(P->ws + P->lay.off_rpart);
-  double *fin = (double *)(P->ws + P->lay.off_rfin);
-  HIPCHK(launch_residuals(P->bf16, R, P->A, fin, P->st), "residuals");
+  HIPCHK(launch_residuals(P->bf16, R, P->A, res_out(P), P->st), "residuals");
+  return SL_OK;
+}
+
+sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
+  sl_status s = residuals_enqueue(P);
+  if (s != SL_OK) return s;
   double h[2];
-  HIPCHK(hipMemcpyAsync(h, fin, sizeof h, hipMemcpyDeviceToHost, P->st), "residual copy");
+  HIPCHK(hipMemcpyAsync(h, res_out(P), sizeof h, hipMemcpyDeviceToHost, P->st), "residual copy");
   HIPCHK(hipStreamSynchronize(P->st), "residual sync");
   *rp = h[0];
   *rd = h[1];
@@ -1026,6 +1065,10 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->ptrs_dev = base + off;
   off += align256((size_t)n * 6 * sizeof(IterPtrs<float>));
   B->args_dev = (IterArgs *)(base + off);
+  off += align256((size_t)n * sizeof(IterArgs));
+  B->bfin_dev = (double *)(base + off);
+  B->bfin_host.assign((size_t)n * 16, 0.0);
+  for (int i = 0; i < n; i++) B->sub[i]->fin_dev = B->bfin_dev + (size_t)i * 16;
   B->ptrs_host.resize((size_t)n * 6 * sizeof(IterPtrs<float>));
   B->args_host.resize(n);
   for (int i = 0; i < n; i++) {
