@@ -44,7 +44,7 @@ typedef struct sl_problem_ *sl_problem; /* opaque, owned by the library */
 typedef enum {
   SL_OK = 0,
   SL_ERR_INVALID_ARG = 1, /* a documented precondition does not hold                  */
-  SL_ERR_UNSUPPORTED = 2, /* valid, but outside what this build implements            */
+  SL_ERR_UNSUPPORTED = 2, /* valid, but outside what the library implements          */
   SL_ERR_DEVICE = 3,      /* a HIP runtime call failed (no device, launch failure ...) */
   SL_ERR_WORKSPACE = 4,   /* workspace pointer NULL, misaligned or too small          */
   SL_ERR_NUMERIC = 5      /* a NaN / Inf appeared in the energy monitor               */
@@ -70,7 +70,7 @@ typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;
 typedef enum { SL_STORE_FP32 = 0, SL_STORE_BF16_DUAL = 1 } sl_storage;
 
 typedef struct {
-  int32_t H, W, L;         /* H, W >= 1; 2 <= L <= SL_MAX_LABELS                         */
+  int32_t H, W, L;         /* H, W >= 1, H*W < 2^29 (else UNSUPPORTED); 2 <= L <= SL_MAX_LABELS */
   const double *gamma;     /* HOST [L], finite, strictly increasing; copied               */
   sl_rho_kind rho;
   const float *f;          /* DEVICE [H*W] data image (QUAD, TRUNC_QUAD); NULL for
@@ -84,7 +84,7 @@ typedef struct {
                               additive values w_j(x), interpolated linearly between
                               labels and added to rho. May be NULL. Read in sl_create. */
   double lambda;           /* >= 0                                                        */
-  sl_tv_kind tv;           /* SL_TV_ISO only in this build (ANISO -> SL_ERR_UNSUPPORTED)  */
+  sl_tv_kind tv;           /* SL_TV_ISO only (ANISO -> SL_ERR_UNSUPPORTED)               */
   sl_storage storage;
   int32_t check_every;     /* iterations between gap checks in sl_run_to_gap (>= 1)      */
   int32_t normalize_labels;/* 1: iterate on the labels mapped affinely onto [0,1] (an

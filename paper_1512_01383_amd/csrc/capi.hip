@@ -100,7 +100,8 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
 sl_status validate(const sl_problem_desc *d) {
   if (!d) return fail(SL_ERR_INVALID_ARG, "desc is NULL");
   if (d->H < 1 || d->W < 1) return fail(SL_ERR_INVALID_ARG, "H and W must be >= 1");
-  if ((long long)d->H * d->W >= (1LL << 30)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^30");
+  // one FP32 plane stays below 2 GiB: byte offsets are 32-bit and 2^31 marks an idle lane
+  if ((long long)d->H * d->W >= (1LL << 29)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^29");
   if (d->L < 2) return fail(SL_ERR_INVALID_ARG, "L must be >= 2");
   if (d->L > SL_MAX_LABELS) return fail(SL_ERR_UNSUPPORTED, "L must be <= %d", SL_MAX_LABELS);
   if (!d->gamma) return fail(SL_ERR_INVALID_ARG, "gamma is NULL");
@@ -761,9 +762,10 @@ bool cfg_fits(const sl_problem_ *P, int cfg) {
   return pdhg_iter_lds_bytes(k, kIterCfg[cfg][1]) + pdhg_iter_static_lds(cfg) <= (size_t)P->maxlds;
 }
 
-// Label groups: chunks of about six labels per wavefront keep the label walk short, and
-// small images get more groups until there are >= 2048 wavefronts (8 per compute unit).
-// Tiles of 4 rows. (Measured on MI355X: see the tiling sweep in the design doc.)
+// Label groups: one wavefront walks all labels of its row unless the image has too few
+// rows of 64 pixels to fill the chip; then the labels are split over 2 or 4 groups until
+// there are >= 3000 wavefronts (about 12 per compute unit). Tiles of 4 rows. Measured on
+// MI355X over truncated-quadratic images from 256^2 to 2048^2 and the stereo workload.
 int auto_cfg(const sl_problem_ *P) {
   long long waves = (P->lay.N + 63) / 64;
   int k = P->A.k;
@@ -772,8 +774,8 @@ int auto_cfg(const sl_problem_ *P) {
     for (const sl_problem_ *q : P->sub) waves += (q->lay.N + 63) / 64;
     k = P->kmax;
   }
-  int g = k < 9 ? 1 : (k < 18 ? 2 : 4);
-  while (waves * g < 2048 && g < 4 && g < k) g *= 2;
+  int g = 1;
+  while (waves * g < 3000 && g < 4 && g < k) g *= 2;
   const int want = g == 1 ? 0 : (g == 2 ? 2 : 4);
   const int order[3] = {want, 2, 0};
   for (int j = 0; j < 3; j++)

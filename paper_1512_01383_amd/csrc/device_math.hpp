@@ -49,6 +49,36 @@ __device__ __forceinline__ float ldvb(const uint16_t *base, unsigned off) {
 __device__ __forceinline__ void stvb(float *base, unsigned off, float x) { stb(base, off, x); }
 __device__ __forceinline__ void stvb(uint16_t *base, unsigned off, float x) { stb(base, off, f2bf(x)); }
 
+// Buffer loads / stores through a descriptor of one plane of `bytes` bytes. The hardware
+// range check makes a lane whose byte offset lies at or beyond `bytes` read 0 and write
+// nothing, so lanes outside the image (offset kOOB) and whole steps past the end of a
+// label chunk (bytes = 0) need no branch around the access: the memory counters then
+// advance the same way on every path, and waits on earlier loads need not drain stores.
+constexpr unsigned kOOB = 0x80000000u;   // plane sizes stay below 2 GiB
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float bld(const float *base, unsigned bytes, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(base, bytes), (int)off, 0, 0));
+}
+__device__ __forceinline__ unsigned bldu(const unsigned *base, unsigned bytes, unsigned off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(base, bytes), (int)off, 0, 0);
+}
+__device__ __forceinline__ float bldv(const float *base, unsigned bytes, unsigned off) {
+  return bld(base, bytes, off);
+}
+__device__ __forceinline__ float bldv(const uint16_t *base, unsigned bytes, unsigned off) {
+  const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(plane_rsrc(base, bytes), (int)off, 0, 0);
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+__device__ __forceinline__ void bst(float *base, unsigned bytes, unsigned off, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), plane_rsrc(base, bytes), (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstv(float *base, unsigned bytes, unsigned off, float x) { bst(base, bytes, off, x); }
+__device__ __forceinline__ void bstv(uint16_t *base, unsigned bytes, unsigned off, float x) {
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)f2bf(x), plane_rsrc(base, bytes), (int)off, 0, 0);
+}
+
 // ---------------------------------------------------------------- TV ball (Prop. 5)
 
 __device__ __forceinline__ void ball(float &px, float &py, float rad) {

@@ -18,11 +18,14 @@
 // exchanges of per-chunk partial sums through LDS: the weighted sum of sbar before the
 // label walk (q and the suffix sums) and the sum of the new v after it (the prefix sums
 // of the s update, applied as a correction when s is stored).
-// Per label, ubar is staged in LDS with a one-pixel halo, p is updated for the tile and
-// recomputed on the left column and top row of the halo (bitwise identical to what the
-// neighbouring tile computes), so div p needs no second pass over memory. u is
-// triple-buffered and p double-buffered, so halo reads never see a value written in the
-// same launch: one launch streams every state field once through HBM.
+// Per label, every wavefront works on its own row without LDS or barriers: it reads
+// ubar on the rows above and below and p on the row above, and recomputes that p with the
+// expression its owner evaluates (bitwise the same value), so div p needs no second pass
+// over memory; neighbours within the row come from the adjacent lane (DPP), the values
+// just beyond the tile's left and right edges from a few-lane gather. Those extra rows are
+// read from L2, not HBM: the neighbouring wavefronts load them at about the same time.
+// u is triple-buffered and p double-buffered, so neighbour reads never see a value
+// written in the same launch: one launch streams every state field once through HBM.
 // Truncated-quadratic intervals that straddle a band edge (at most two per pixel) are
 // projected before the label walk, so the costly envelope projection does not diverge
 // inside it. Blocks are mapped to tiles so that each XCD (own L2) gets a contiguous run
@@ -34,14 +37,31 @@ namespace {
 
 constexpr int TW = 64;
 
+__device__ __forceinline__ float rdlane(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+// x of the next lane (lane 63 takes `last`), x of the previous lane (lane 0 takes `first`)
+__device__ __forceinline__ float from_right(float x, float last) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, last),
+                                                               __builtin_bit_cast(int, x), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_left(float x, float first) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, first),
+                                                               __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
+}
+// p <- Proj_{|.| <= rad}(p + sigma_p (gx, gy)): one expression wherever a p is formed, so
+// that a p recomputed for a neighbour is bitwise the one its owner stores
+__device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx, float gy, float rad) {
+  px = px + spg * gx;
+  py = py + spg * gy;
+  ball(px, py, rad);
+}
+
 // One iteration on one tile of one problem (all labels of its pixels).
 template <int PIECE, bool ADD, typename DT, int G, int TH>
 __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs &A, int tile,
                                           float *dyn) {
   constexpr int NP = TW * TH;   // pixels of a tile = threads of a label group
-  __shared__ float ubs[G][TH + 2][TW + 2];
-  __shared__ float pxs[G][TH + 1][TW + 1];
-  __shared__ float pys[G][TH + 1][TW + 1];
   __shared__ float ex[G][NP];      // per-chunk partial sums (reused: sbar sums, then v sums)
   __shared__ float stv[G > 1 ? 2 : 1][NP], stz[G > 1 ? 2 : 1][NP];  // straddle results (G > 1)
   float *lsb = dyn;               // [k][NP] sbar
@@ -52,7 +72,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   const int tid = threadIdx.x;
   const int grp = __builtin_amdgcn_readfirstlane(tid / NP);  // one group per wavefront
   const int lt = tid - grp * NP;
-  const int tx = lt & 63, ty = lt >> 6;
+  const int tx = lt & 63, ty = lt >> 6;                     // one image row per wavefront
 
   const int ntc = (W + TW - 1) / TW;
   const int r0 = (tile / ntc) * TH;
@@ -61,6 +81,9 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   const bool in = r < H && c < W;
   const long long xo = (long long)r * W + c;
   const unsigned xb = (unsigned)xo * 4u, db = (unsigned)xo * (unsigned)sizeof(DT);
+  // plane sizes and this lane's offsets for the range-checked buffer accesses
+  const unsigned nb4 = (unsigned)(H * W) * 4u, nbd = (unsigned)(H * W) * (unsigned)sizeof(DT);
+  const unsigned xm = in ? xb : kOOB, dm = in ? db : kOOB;
   const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
   const float tau_u = A.tau_c / (1.f + (float)deg);
 
@@ -72,23 +95,20 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   // ---- phase A: over-relaxed multiplier of the chunk, its weighted sum
   float Tc = 0.f;
   for (int i = i0; i < i1; i++) {
-    float s = 0.f, sb = 0.f;
-    if (in) {
-      s = ldb(P.s + (size_t)(i) * ps, xb);
-      sb = 2.f * s - ldb(P.sp + (size_t)(i) * ps, xb);
-    }
+    const float s = bld(P.s + (size_t)(i) * ps, nb4, xm);
+    const float sb = 2.f * s - bld(P.sp + (size_t)(i) * ps, nb4, xm);
     Tc += A.h[i] * sb;
     lsa[i * NP + lt] = s;
     lsb[i * NP + lt] = sb;
   }
-  ex[grp][lt] = Tc;
-  const float qd = in ? ldb(P.qd, xb) : 0.f;
-  const float fc = (PIECE != SLI_SAMPLED && in) ? ldb(P.fn, xb) : 0.f;
-  __syncthreads();
+  if (G > 1) ex[grp][lt] = Tc;
+  const float qd = bld(P.qd, nb4, xm);
+  const float fc = PIECE != SLI_SAMPLED ? bld(P.fn, nb4, xm) : 0.f;
+  if (G > 1) __syncthreads();
   float T = 0.f, base = 0.f;
 #pragma unroll
   for (int g = 0; g < G; g++) {
-    const float e = ex[g][lt];
+    const float e = G > 1 ? ex[g][lt] : Tc;
     T += e;
     if (g > grp) base += e;
   }
@@ -163,183 +183,173 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       }
     }
   }
+  // straddle results of the other groups; every read of the sbar sums in ex is done
+  if (G > 1) __syncthreads();
 
-  // ---- label walk (all groups in step). Every global load of a label step (own fields
-  // and the halo inputs this thread stages) is issued one step ahead.
-  // halo roles: wave 0 stages the halo row above and recomputes p on it, wave 1 the halo
-  // row below and p on the left halo column, wave 2 the halo columns of ubar.
-  const bool h_top = ty == 0 && r0 > 0 && c < W;
-  const bool h_bot = ty == 1 && r0 + TH < H && c < W;
-  const int eq = tx >> 1, ecol = (tx & 1) ? c0 + TW : c0 - 1, erow = r0 - 1 + eq;
-  const bool h_edge = ty == 2 && tx < 2 * (TH + 2) && erow >= 0 && erow < H && ecol >= 0 && ecol < W;
-  const bool h_left = ty == 1 && tx < TH && c0 > 0 && r0 + tx < H;
-  const long long x_top = (long long)(r0 - 1) * W + c;
-  const long long x_bot = (long long)(r0 + TH) * W + c;
-  const long long x_edge = (long long)erow * W + ecol;
-  const long long x_left = (long long)(r0 + tx) * W + (c0 - 1);
-  const long long x_hu = ty == 0 ? x_top : ty == 1 ? x_bot : x_edge;
-  const bool h_u = h_top || h_bot || h_edge;
-  const long long x_hp = ty == 0 ? x_top : x_left;
-  const bool h_p = h_top || h_left;
-  const unsigned xb_hu = h_u ? (unsigned)x_hu * 4u : 0u;
-  const unsigned db_hp = h_p ? (unsigned)x_hp * (unsigned)sizeof(DT) : 0u;
-  struct Step {
-    float u, up, v, z, px, py, hu, hup, hpx, hpy;
-  };
-  auto load_step = [&](int i, Step &o) {
-    o.u = o.up = o.v = o.z = o.px = o.py = o.hu = o.hup = o.hpx = o.hpy = 0.f;
-    if (i >= i1) return;
-    if (in) {
-      o.u = ldb(P.u + (size_t)(i) * ps, xb);
-      o.up = ldb(P.up + (size_t)(i) * ps, xb);
-      o.v = ldvb(P.v + (size_t)(i) * ps, db);
-      o.z = ldvb(P.z + (size_t)(i) * ps, db);
-      o.px = ldvb(P.pin + (size_t)(i) * ps, db);
-      o.py = ldvb(P.pin + (size_t)((k + i)) * ps, db);
-    }
-    if (h_u) {
-      o.hu = ldb(P.u + (size_t)i * ps, xb_hu);
-      o.hup = ldb(P.up + (size_t)i * ps, xb_hu);
-    }
-    if (h_p) {
-      o.hpx = ldvb(P.pin + (size_t)i * ps, db_hp);
-      o.hpy = ldvb(P.pin + (size_t)(k + i) * ps, db_hp);
-    }
-  };
-  Step nx;
-  load_step(i0, nx);
-  float pre = 0.f;                  // sum of the chunk's new v so far
-  float wlo = (ADD && in && i0 < i1) ? ldb(P.wadd + (size_t)(i0) * ps, xb) : 0.f;
-  for (int t = 0; t < chn; t++) {
-    const int i = i0 + t;
-    const bool act = i < i1;
-    const Step cu = nx;
-    ubs[grp][ty + 1][tx + 1] = in ? 2.f * cu.u - cu.up : 0.f;
-    if (act) {
-      const float hub = h_u ? 2.f * cu.hu - cu.hup : 0.f;
-      if (ty == 0)
-        ubs[grp][0][tx + 1] = hub;
-      else if (ty == 1)
-        ubs[grp][TH + 1][tx + 1] = hub;
-      else if (ty == 2 && tx < 2 * (TH + 2))
-        ubs[grp][eq][(tx & 1) ? TW + 1 : 0] = hub;
-    }
-    __syncthreads();
-    load_step(i + 1, nx);   // next label step in flight during this one
-
-    float px = 0.f, py = 0.f;
-    if (act) {
-      const float rad = A.lam * A.h[i];
-      const float spg = A.sig_p;
-      if (in) {
-        const int q = ty + 1, cc = tx + 1;
-        const float gx = (c < W - 1) ? ubs[grp][q][cc + 1] - ubs[grp][q][cc] : 0.f;
-        const float gy = (r < H - 1) ? ubs[grp][q + 1][cc] - ubs[grp][q][cc] : 0.f;
-        px = cu.px + spg * gx;
-        py = cu.py + spg * gy;
-        ball(px, py, rad);
-        pxs[grp][q][cc] = px;
-        pys[grp][q][cc] = py;
-      }
-      if (h_top) {
-        const float gx = (c < W - 1) ? ubs[grp][0][tx + 2] - ubs[grp][0][tx + 1] : 0.f;
-        const float gy = ubs[grp][1][tx + 1] - ubs[grp][0][tx + 1];
-        float hx = cu.hpx + spg * gx, hy = cu.hpy + spg * gy;
-        ball(hx, hy, rad);
-        pxs[grp][0][tx + 1] = hx;
-        pys[grp][0][tx + 1] = hy;
-      } else if (h_left) {
-        const int rr = r0 + tx;
-        const float gx = ubs[grp][tx + 1][1] - ubs[grp][tx + 1][0];
-        const float gy = (rr < H - 1) ? ubs[grp][tx + 2][0] - ubs[grp][tx + 1][0] : 0.f;
-        float hx = cu.hpx + spg * gx, hy = cu.hpy + spg * gy;
-        ball(hx, hy, rad);
-        pxs[grp][tx + 1][0] = hx;
-        pys[grp][tx + 1][0] = hy;
-      }
-    }
-    __syncthreads();
-
-    if (act && in) {
-      const int q = ty + 1, cc = tx + 1;
-      stvb(P.pout + (size_t)(i) * ps, db, px);
-      stvb(P.pout + (size_t)((k + i)) * ps, db, py);
-      float dv = 0.f;
-      if (c < W - 1) dv += pxs[grp][q][cc];
-      if (c > 0) dv -= pxs[grp][q][cc - 1];
-      if (r < H - 1) dv += pys[grp][q][cc];
-      if (r > 0) dv -= pys[grp][q - 1][cc];
-      const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
-      const float s = lsa[i * NP + lt];
-      const float sb = lsb[i * NP + lt];
-      suf -= hi * sb;
-      float v, z;
-      float whi = 0.f;
-      if (ADD) whi = ldb(P.wadd + (size_t)((i + 1)) * ps, xb);
-      if (PIECE == SLI_TRUNC && i == si0) {
-        v = G == 1 ? sv0 : stv[0][lt];
-        z = G == 1 ? sz0 : stz[0][lt];
-      } else if (PIECE == SLI_TRUNC && i == si1) {
-        v = G == 1 ? sv1 : stv[1][lt];
-        z = G == 1 ? sz1 : stz[1][lt];
-      } else {
-        v = cu.v + A.sig[i] * (ubs[grp][q][cc] + suf - g0 * sb);
-        z = cu.z + A.sig[i] * sb;
-        float y = v * ih, w = z * ih;
-        float bs = 0.f, cs = 0.f;
-        if (ADD) {
-          bs = (whi - wlo) * ih;
-          cs = -wlo + bs * g0;
-          y -= bs;
-          w -= cs;
-        }
-        if (PIECE == SLI_QUAD) {
-          proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
-        } else if (PIECE == SLI_TRUNC) {
-          // not straddling: inside the band (quadratic) or outside it (constant nu)
-          if (fc - A.del <= g0 && g1 <= fc + A.del)
-            proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
-          else
-            proj_flat(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w);
-        } else {
-          PLProj pl;
-          pl.init(y, w);
-          const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
-          for (int m = m0; m <= m1; m++) pl.push(P.tau[m], ldb(P.cost + (size_t)(m) * ps, xb));
-          pl.finish(y, w);
-        }
-        if (ADD) {
-          y += bs;
-          w += cs;
-        }
-        v = hi * y;
-        z = hi * w;
-      }
-      if (ADD) wlo = whi;
-      stvb(P.v + (size_t)(i) * ps, db, v);
-      stvb(P.z + (size_t)(i) * ps, db, z);
-      const float sn = s - A.taus[i] * (z - hi * qn + hi * pre - g0 * v);
-      pre += v;
-      stb(P.un + (size_t)(i) * ps, xb, cu.u - tau_u * (v - dv));
-      if (G == 1)
-        stb(P.sp + (size_t)(i) * ps, xb, sn);
-      else
-        lsa[i * NP + lt] = sn;
-    }
+  // ---- label walk: every wavefront on its own (no barrier). The stencil needs ubar on
+  // the rows above and below and p on the row above: each wavefront loads those rows and
+  // recomputes p of the row above (the same expression its owner evaluates, so bitwise the
+  // same value); the left and right neighbours within the row come from the adjacent lane,
+  // and at the tile's edges from a four-lane gather of ubar at (r, c0-1), (r+1, c0-1),
+  // (r, c0+64), (r-1, c0+64) and p at (r, c0-1). The next label step's loads are in flight
+  // during the current one.
+  const unsigned W4 = (unsigned)W * 4u, WD = (unsigned)W * (unsigned)sizeof(DT);
+  const unsigned xm_up = (in && r > 0) ? xb - W4 : kOOB;        // row above
+  const unsigned xm_dn = (in && r + 1 < H) ? xb + W4 : kOOB;    // row below
+  const unsigned dm_up = (in && r > 0) ? db - WD : kOOB;
+  int er = r, ec = c0 - 1;
+  bool ev = false;
+  if (tx == 0) {
+    ev = c0 > 0 && r < H;
+  } else if (tx == 1) {
+    er = r + 1;
+    ev = c0 > 0 && r + 1 < H;
+  } else if (tx == 2) {
+    ec = c0 + TW;
+    ev = c0 + TW < W && r < H;
+  } else if (tx == 3) {
+    er = r - 1;
+    ec = c0 + TW;
+    ev = c0 + TW < W && r > 0 && r <= H;
   }
+  const unsigned em = ev ? (unsigned)((long long)er * W + ec) * 4u : kOOB;
+  const unsigned eml = (tx == 0 && c0 > 0 && r < H) ? (unsigned)((long long)r * W + c0 - 1) * (unsigned)sizeof(DT) : kOOB;
+  struct Step {
+    float u, up, uu, uup, ud, udp, px, py, pxu, pyu, v, z, eu, eup, epx, epy, wh;
+  };
+  // past the chunk the planes have size 0 (nothing is read)
+  auto load_step = [&](int i, Step &o) {
+    const unsigned b4 = i < i1 ? nb4 : 0u, bd = i < i1 ? nbd : 0u;
+    const float *pu = P.u + (size_t)i * ps, *pup = P.up + (size_t)i * ps;
+    const DT *ppx = P.pin + (size_t)i * ps, *ppy = P.pin + (size_t)(k + i) * ps;
+    o.u = bld(pu, b4, xm);
+    o.up = bld(pup, b4, xm);
+    o.uu = bld(pu, b4, xm_up);
+    o.uup = bld(pup, b4, xm_up);
+    o.ud = bld(pu, b4, xm_dn);
+    o.udp = bld(pup, b4, xm_dn);
+    o.px = bldv(ppx, bd, dm);
+    o.py = bldv(ppy, bd, dm);
+    o.pxu = bldv(ppx, bd, dm_up);
+    o.pyu = bldv(ppy, bd, dm_up);
+    o.v = bldv(P.v + (size_t)i * ps, bd, dm);
+    o.z = bldv(P.z + (size_t)i * ps, bd, dm);
+    o.eu = bld(pu, b4, em);
+    o.eup = bld(pup, b4, em);
+    o.epx = bldv(ppx, bd, eml);
+    o.epy = bldv(ppy, bd, eml);
+    o.wh = ADD ? bld(P.wadd + (size_t)(i + 1) * ps, b4, xm) : 0.f;
+  };
+  float pre = 0.f;                  // sum of the chunk's new v so far
+  float wlo = (ADD && i0 < i1) ? bld(P.wadd + (size_t)(i0) * ps, nb4, xm) : 0.f;
+
+  auto label_step = [&](int i, const Step &cu, Step &nx) {
+    load_step(i + 1, nx);
+    const float rad = A.lam * A.h[i];
+    const float spg = A.sig_p;
+    const float ub = 2.f * cu.u - cu.up;
+    const float ubu = 2.f * cu.uu - cu.uup;
+    const float ubd = 2.f * cu.ud - cu.udp;
+    const float eub = 2.f * cu.eu - cu.eup;
+    const float ubL = rdlane(eub, 0), ubLd = rdlane(eub, 1), ubR = rdlane(eub, 2), ubRu = rdlane(eub, 3);
+    // lane shifts with every lane active (a lane masked off would read as out of range)
+    const float ubr = from_right(ub, ubR), ubur = from_right(ubu, ubRu);
+    // own p
+    float px = cu.px, py = cu.py;
+    p_step(px, py, spg, (c < W - 1) ? ubr - ub : 0.f, (r < H - 1) ? ubd - ub : 0.f, rad);
+    // p of the row above (only its y part enters div p)
+    float pxu = cu.pxu, pyu = cu.pyu;
+    p_step(pxu, pyu, spg, (c < W - 1) ? ubur - ubu : 0.f, ub - ubu, rad);
+    // p at (r, c0-1) for lane 0's left neighbour (only its x part enters div p)
+    float pxL = rdlane(cu.epx, 0), pyL = rdlane(cu.epy, 0);
+    p_step(pxL, pyL, spg, rdlane(ub, 0) - ubL, (r < H - 1) ? ubLd - ubL : 0.f, rad);
+    const float pxl = from_left(px, pxL);
+
+    // lanes outside the image and steps past the chunk store nothing
+    bstv(P.pout + (size_t)(i) * ps, nbd, dm, px);
+    bstv(P.pout + (size_t)((k + i)) * ps, nbd, dm, py);
+    float dv = 0.f;
+    if (c < W - 1) dv += px;
+    if (c > 0) dv -= pxl;
+    if (r < H - 1) dv += py;
+    if (r > 0) dv -= pyu;
+    const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
+    const float s = lsa[i * NP + lt];
+    const float sb = lsb[i * NP + lt];
+    suf -= hi * sb;
+    float v, z;
+    const float whi = cu.wh;
+    if (PIECE == SLI_TRUNC && i == si0) {
+      v = G == 1 ? sv0 : stv[0][lt];
+      z = G == 1 ? sz0 : stz[0][lt];
+    } else if (PIECE == SLI_TRUNC && i == si1) {
+      v = G == 1 ? sv1 : stv[1][lt];
+      z = G == 1 ? sz1 : stz[1][lt];
+    } else {
+      v = cu.v + A.sig[i] * (ub + suf - g0 * sb);
+      z = cu.z + A.sig[i] * sb;
+      float y = v * ih, w = z * ih;
+      float bs = 0.f, cs = 0.f;
+      if (ADD) {
+        bs = (whi - wlo) * ih;
+        cs = -wlo + bs * g0;
+        y -= bs;
+        w -= cs;
+      }
+      if (PIECE == SLI_QUAD) {
+        proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
+      } else if (PIECE == SLI_TRUNC) {
+        // not straddling: inside the band (quadratic) or outside it (constant nu)
+        if (fc - A.del <= g0 && g1 <= fc + A.del)
+          proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
+        else
+          proj_flat(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w);
+      } else {
+        PLProj pl;
+        pl.init(y, w);
+        const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
+        for (int m = m0; m <= m1; m++) pl.push(P.tau[m], bld(P.cost + (size_t)(m) * ps, nb4, xm));
+        pl.finish(y, w);
+      }
+      if (ADD) {
+        y += bs;
+        w += cs;
+      }
+      v = hi * y;
+      z = hi * w;
+    }
+    if (ADD) wlo = whi;
+    bstv(P.v + (size_t)(i) * ps, nbd, dm, v);
+    bstv(P.z + (size_t)(i) * ps, nbd, dm, z);
+    const float sn = s - A.taus[i] * (z - hi * qn + hi * pre - g0 * v);
+    pre += v;
+    bst(P.un + (size_t)(i) * ps, nb4, xm, cu.u - tau_u * (v - dv));
+    if (G == 1)
+      bst(P.sp + (size_t)(i) * ps, nb4, xm, sn);
+    else
+      lsa[i * NP + lt] = sn;
+  };
+  // two step buffers in turn: a step consumes one and fills the other
+  Step b0, b1;
+  load_step(i0, b0);
+  int i = i0;
+  for (; i + 2 <= i1; i += 2) {
+    label_step(i, b0, b1);
+    label_step(i + 1, b1, b0);
+  }
+  if (i < i1) label_step(i, b0, b1);
 
   // ---- prefix of the new v over the earlier chunks: correction of the s update
   if (G > 1) {
-    ex[grp][lt] = pre;   // every read of the sbar sums precedes a barrier of the walk
+    ex[grp][lt] = pre;   // every read of the sbar sums precedes the barrier after the straddles
     __syncthreads();
     float vb = 0.f;
 #pragma unroll
     for (int g = 0; g < G; g++)
       if (g < grp) vb += ex[g][lt];
-    if (in)
-      for (int i = i0; i < i1; i++) stb(P.sp + (size_t)(i) * ps, xb, lsa[i * NP + lt] - A.taus[i] * (A.h[i] * vb));
+    for (int j = i0; j < i1; j++) bst(P.sp + (size_t)(j) * ps, nb4, xm, lsa[j * NP + lt] - A.taus[j] * (A.h[j] * vb));
   }
-  if (grp == 0 && in) stb(P.qd, xb, qn);
+  if (grp == 0) bst(P.qd, nb4, xm, qn);
 }
 
 template <int PIECE, bool ADD, typename DT, int G, int TH>
@@ -444,7 +454,7 @@ size_t pdhg_iter_lds_bytes(int k, int th) { return (size_t)2 * k * TW * th * siz
 
 size_t pdhg_iter_static_lds(int cfg) {
   const int G = kIterCfg[cfg][0], TH = kIterCfg[cfg][1];
-  return sizeof(float) * (size_t)G * ((TH + 2) * (TW + 2) + 2 * (TH + 1) * (TW + 1) + TW * TH);
+  return sizeof(float) * (size_t)(G + (G > 1 ? 4 : 2)) * TW * TH;   // ex, stv, stz
 }
 
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
