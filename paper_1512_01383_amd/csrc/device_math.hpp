@@ -82,12 +82,10 @@ __device__ __forceinline__ void bstv(uint16_t *base, unsigned bytes, unsigned of
 // ---------------------------------------------------------------- TV ball (Prop. 5)
 
 __device__ __forceinline__ void ball(float &px, float &py, float rad) {
-  float n2 = px * px + py * py;
-  if (n2 > rad * rad) {
-    float f = rad * __builtin_amdgcn_rsqf(n2);
-    px *= f;
-    py *= f;
-  }
+  const float n2 = px * px + py * py;
+  const float f = n2 > rad * rad ? rad * __builtin_amdgcn_rsqf(n2) : 1.f;
+  px *= f;
+  py *= f;
 }
 
 // ---------------------------------------------------------------- quadratic pieces
@@ -363,19 +361,13 @@ __device__ __forceinline__ void proj_tq_chain(float a, float c, float nu, float 
 __device__ __forceinline__ void proj_flat(float nu, float g0, float g1, float ig0, float ig1,
                                           float &y, float &w) {
   const float g = fmaxf(g0 * y, g1 * y) - nu;
-  if (w >= g) return;
+  const bool inside = w >= g;
   const float m0 = (g0 * y - nu - w) * ig0, y0 = y - m0 * g0;
-  if (m0 >= 0.f && y0 <= 0.f) {
-    y = y0;
-    w = g0 * y0 - nu;
-    return;
-  }
+  const bool c0 = m0 >= 0.f && y0 <= 0.f;
   const float m1 = (g1 * y - nu - w) * ig1, y1 = y - m1 * g1;
-  if (m1 >= 0.f && y1 >= 0.f) {
-    y = y1;
-    w = g1 * y1 - nu;
-    return;
-  }
-  y = 0.f;
-  w = -nu;
+  const bool c1 = m1 >= 0.f && y1 >= 0.f;
+  const float yn = c0 ? y0 : (c1 ? y1 : 0.f);
+  const float wn = c0 ? g0 * y0 - nu : (c1 ? g1 * y1 - nu : -nu);
+  y = inside ? y : yn;
+  w = inside ? w : wn;
 }

@@ -244,6 +244,9 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   float wlo = (ADD && i0 < i1) ? bld(P.wadd + (size_t)(i0) * ps, nb4, xm) : 0.f;
 
   auto label_step = [&](int i, const Step &cu, Step &nx) {
+    // one group: the block's rows stay in step, so a row fetched for its neighbours is
+    // still in L2 when they read it (on large images they would drift apart otherwise)
+    if (G == 1) __builtin_amdgcn_s_barrier();
     load_step(i + 1, nx);
     const float rad = A.lam * A.h[i];
     const float spg = A.sig_p;
