@@ -296,16 +296,24 @@ __device__ __forceinline__ void proj_tq_chain(float a, float c, float nu, float 
   const float hs = (g1 - g0) * (1.f / (float)(SLI_NSUB - 1));
   const int nb = ml <= mr ? mr - ml + 1 : 0;
   const int nk = nb + 1;   // kinks
+  // values at the two ends and at the first band sample, and the slopes of the two end
+  // kinks, once per call; the searches below then cost a few selects per halving
+  const float rs0 = tq_sample(a, c, nu, g0, g1, hs, 0);
+  const float rsN = tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1);
+  const float rs1 = tq_sample(a, c, nu, g0, g1, hs, ml);
   auto vt = [&](int v) { return v == 0 ? g0 : (v == nb + 1 ? g1 : g0 + hs * (float)(ml + v - 1)); };
   auto vr = [&](int v) {
-    if (v == 0) return tq_sample(a, c, nu, g0, g1, hs, 0);
-    if (v == nb + 1) return tq_sample(a, c, nu, g0, g1, hs, SLI_NSUB - 1);
-    if (v == 1) return tq_sample(a, c, nu, g0, g1, hs, ml);
+    if (v == 0) return rs0;
+    if (v == nb + 1) return rsN;
+    if (v == 1) return rs1;
     const float d = vt(v) - c;
     return 0.5f * a * d * d;
   };
+  const float kb0 = (vr(1) - vr(0)) * frcp(vt(1) - vt(0));
+  const float kbN = (vr(nb + 1) - vr(nb)) * frcp(vt(nb + 1) - vt(nb));
   auto kb = [&](int j) {
-    if (j == 0 || j == nb) return (vr(j + 1) - vr(j)) * frcp(vt(j + 1) - vt(j));
+    if (j == 0) return kb0;
+    if (j == nb) return kbN;
     return a * (vt(j + 1) - 0.5f * hs - c);
   };
   const float y0 = y, w0 = w;

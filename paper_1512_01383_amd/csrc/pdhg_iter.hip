@@ -128,9 +128,9 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       if ((info & 31u) != 31u) si0 = (int)(info & 31u);
       if (((info >> 13) & 31u) != 31u) si1 = (int)((info >> 13) & 31u);
     }
-#pragma unroll
-    for (int slot = 0; slot < 2; slot++) {
-      if (G > 1 && slot != grp) continue;
+    const int s_lo = G == 1 ? 0 : grp, s_hi = G == 1 ? 2 : min(grp + 1, 2);
+#pragma unroll 1
+    for (int slot = s_lo; slot < s_hi; slot++) {   // one copy of the projection code
       const unsigned f = info >> (13 * slot);
       const int i = (int)(f & 31u);
       if (G == 1 ? (i < i0 || i >= i1) : i == 31) continue;
