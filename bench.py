@@ -29,11 +29,15 @@ KERNEL_SOURCES = ("paper_1512_01383_amd/csrc/pdhg_iter.hip", "paper_1512_01383_a
 
 
 def kernel_hash() -> str:
-    """Hash of the sources of the fused iteration kernel (ties counter data to a kernel)."""
+    """Hash of the code of the fused iteration kernel (ties counter data to a kernel):
+    the sources with // comments and blank space removed, so comment edits keep it."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            for line in f:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -5,7 +5,7 @@
 //   u[3][k]     rotating primal buffers: u_prev, u, u_next
 //   s[2][k]     multiplier of the z-equality: s, s_prev (s_new overwrites s_prev)
 //   v[k], z[k]  data-term duals (float or bf16), updated in place
-//   p[2][2k]    TV duals, double-buffered (halo reads of the old p): px_i at plane i,
+//   p[2][2k]    TV duals, double-buffered (neighbour reads of the old p): px_i at plane i,
 //               py_i at plane k+i (float or bf16)
 //   q[1]        scalar dual of the pointwise max of the conjugates
 //   fn[1]       data image mapped to normalised label coordinates (QUAD, TRUNC_QUAD)

@@ -29,7 +29,7 @@
 // Truncated-quadratic intervals that straddle a band edge (at most two per pixel) are
 // projected before the label walk, so the costly envelope projection does not diverge
 // inside it. Blocks are mapped to tiles so that each XCD (own L2) gets a contiguous run
-// of tiles and halo rows / columns are mostly shared within one L2.
+// of tiles and the rows read by neighbouring tiles are mostly shared within one L2.
 #include "device_math.hpp"
 #include "internal.hpp"
 
