@@ -80,6 +80,9 @@ def _cases():
     out.append(("one_row", W.truncated_quadratic(L=6, H=1, W=200, seed=3)))
     out.append(("one_col", W.truncated_quadratic(L=6, H=77, W=1, seed=4)))
     out.append(("k27", W.truncated_quadratic(L=28, H=5, W=70, seed=9)))
+    # widths that are whole tiles: the gathers beyond the right edge fall outside the image
+    out.append(("w64", W.truncated_quadratic(L=5, H=6, W=64, seed=12)))
+    out.append(("w128", W.truncated_quadratic(L=7, H=8, W=128, seed=13)))
     return out
 
 
