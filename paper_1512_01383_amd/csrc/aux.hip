@@ -236,22 +236,24 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
   PieceD P;
 
   // (a) repair: simplex projection of x = -h s by Michelot's finite algorithm. Its active
-  // set only shrinks and is always {i : x_i > theta} for the current threshold, so no
-  // per-label arrays are kept (x is re-read, the loads hit the cache). A block repeats a
-  // pass while any of its pixels still removes labels (a pass that removes nothing leaves
-  // the threshold unchanged).
-  auto xs = [&](int i) { return -D.h[i] * (double)M.s[i * A.ps + x]; };
+  // set only shrinks and is always {i : x_i > theta} for the current threshold. A thread's
+  // chunk of x (at most MC labels) is loaded once into registers; a block repeats a pass
+  // while any of its pixels still removes labels (a pass that removes nothing leaves the
+  // threshold unchanged).
+  constexpr int MC = (SLI_MAXK + MT - 1) / MT;
+  double xv[MC];
+#pragma unroll
+  for (int q = 0; q < MC; q++)
+    xv[q] = (in && i0 + q < i1) ? -D.h[i0 + q] * (double)M.s[(i0 + q) * A.ps + x] : -INFINITY;
   double theta = -INFINITY;
   for (int it = 0; it <= k; it++) {
     double sum = 0.0;
     int n = 0;
-    if (in)
-      for (int i = i0; i < i1; i++) {
-        const double xi = xs(i);
-        if (xi > theta) {
-          sum += xi;
-          n++;
-        }
+#pragma unroll
+    for (int q = 0; q < MC; q++)
+      if (xv[q] > theta) {
+        sum += xv[q];
+        n++;
       }
     xa[t][lane] = sum;
     xn[t][lane] = n;
@@ -265,18 +267,17 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
     }
     const double th = Nn > 0 ? (S - 1.0) / Nn : theta;
     int removed = 0;
-    if (in)
-      for (int i = i0; i < i1; i++) {
-        const double xi = xs(i);
-        removed += (xi > theta && xi <= th);
-      }
+#pragma unroll
+    for (int q = 0; q < MC; q++) removed += (xv[q] > theta && xv[q] <= th);
     theta = th;
     if (!__syncthreads_or(removed)) break;
   }
+  auto xs = [&](int i) { return -D.h[i] * (double)M.s[i * A.ps + x]; };
   // repaired weights w_i = max(x_i - theta, 0); u_i clamped into [sum_{j>i} w_j, sum_{j>=i} w_j]
   double tw = 0.0;
-  if (in)
-    for (int i = i0; i < i1; i++) tw += fmax(xs(i) - theta, 0.0);
+#pragma unroll
+  for (int q = 0; q < MC; q++)
+    if (i0 + q < i1) tw += fmax(xv[q] - theta, 0.0);
   xa[t][lane] = tw;
   __syncthreads();
   double lo = 0.0;
