@@ -217,6 +217,9 @@ def test_invalid_arguments_gpu():
     with pytest.raises(S.SublabelError) as e:
         S.Problem(3, 3, W.equispaced(40), S.RHO_QUAD, 0.1, f=f)
     assert e.value.status == 2
+    with pytest.raises(S.SublabelError) as e:   # H*W = 2^29: a plane would reach 2 GiB
+        S.Problem(1 << 15, 1 << 14, [0.0, 1.0], S.RHO_QUAD, 0.1)
+    assert e.value.status == 2 and "2^29" in str(e.value)
 
 
 def _bf16_round(a):
