@@ -336,26 +336,59 @@ __global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
   float cb_acc = 0.f, lb_acc = 0.f;
   float top = 0.f, wb_low = 0.f;        // additive-value adjoints at the chunk's ends
   float w_up = (ADD && in && i0 < i1) ? Q.wadd[(size_t)i1 * ps + x] : 0.f;
+  // the inputs of one label; those of the next label down are loaded while the current
+  // one is processed (this kernel writes only the dual adjoints, at the label being done)
+  struct In {
+    float u, up, ur, upr, ud, upd, s, sp, v, z, px, py, bu, bur, bud, bs, bv, bz, bpx, bpy, wl;
+  };
+  auto load = [&](int i, In &o) {
+    const size_t b = (size_t)i * ps;
+    o.u = X.u[b + x];
+    o.up = X.up[b + x];
+    o.ur = X.u[b + xr];
+    o.upr = X.up[b + xr];
+    o.ud = X.u[b + xd];
+    o.upd = X.up[b + xd];
+    o.s = X.s[b + x];
+    o.sp = X.sp[b + x];
+    o.v = X.v[b + x];
+    o.z = X.z[b + x];
+    o.px = X.px[b + x];
+    o.py = X.py[b + x];
+    o.bu = B.u[b + x];
+    o.bur = B.u[b + xr];
+    o.bud = B.u[b + xd];
+    o.bs = B.s[b + x];
+    o.bv = B.v[b + x];
+    o.bz = B.z[b + x];
+    o.bpx = B.px[b + x];
+    o.bpy = B.py[b + x];
+    o.wl = ADD ? Q.wadd[b + x] : 0.f;
+  };
+  In nx;
+  if (in && i0 < i1) load(i1 - 1, nx);
   if (in)
     for (int i = i1 - 1; i >= i0; i--) {
+      const In cu = nx;
+      if (i > i0) load(i - 1, nx);
       const size_t o = (size_t)i * ps;
       const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
       // forward quantities at this state
-      const float ub = 2.f * X.u[o + x] - X.up[o + x];
-      const float sb = 2.f * X.s[o + x] - X.sp[o + x];
-      const float gx = hr ? (2.f * X.u[o + xr] - X.up[o + xr]) - ub : 0.f;
-      const float gy = hd ? (2.f * X.u[o + xd] - X.up[o + xd]) - ub : 0.f;
-      const float v0 = X.v[o + x] + A.sig[i] * (ub + suf_sb - g0 * sb);
-      const float z0 = X.z[o + x] + A.sig[i] * sb;
-      const float ax = X.px[o + x] + A.sig_p * gx, ay = X.py[o + x] + A.sig_p * gy;
+      const float ub = 2.f * cu.u - cu.up;
+      const float sb = 2.f * cu.s - cu.sp;
+      const float gx = hr ? (2.f * cu.ur - cu.upr) - ub : 0.f;
+      const float gy = hd ? (2.f * cu.ud - cu.upd) - ub : 0.f;
+      const float v0 = cu.v + A.sig[i] * (ub + suf_sb - g0 * sb);
+      const float z0 = cu.z + A.sig[i] * sb;
+      const float ax = cu.px + A.sig_p * gx, ay = cu.py + A.sig_p * gy;
       suf_sb += hi * sb;
       // step 1: K applied to -T (u', s') adjoints
-      const float Ku = -tau_u * B.u[o + x];
-      const float Ks = -A.taus[i] * B.s[o + x];
-      const float vbt = B.v[o + x] + Ku - g0 * Ks + suf_ks;
-      const float zbt = B.z[o + x] + Ks;
-      const float pbx = B.px[o + x] + (hr ? -tau_r * B.u[o + xr] - Ku : 0.f);
-      const float pby = B.py[o + x] + (hd ? -tau_d * B.u[o + xd] - Ku : 0.f);
+      const float Ku = -tau_u * cu.bu;
+      const float Ks = -A.taus[i] * cu.bs;
+      const float vbt = cu.bv + Ku - g0 * Ks + suf_ks;
+      const float zbt = cu.bz + Ks;
+      const float pbx = cu.bpx + (hr ? -tau_r * cu.bur - Ku : 0.f);
+      const float pby = cu.bpy + (hd ? -tau_d * cu.bud - Ku : 0.f);
       suf_ks += hi * Ks;
       // step 3: ball
       float abx, aby, rb;
@@ -365,7 +398,7 @@ __global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
       float y = v0 * ih, w = z0 * ih;
       float bs = 0.f, cs = 0.f, w_lo = 0.f;
       if (ADD) {
-        w_lo = Q.wadd[o + x];
+        w_lo = cu.wl;
         bs = (w_up - w_lo) * ih;
         cs = -w_lo + bs * g0;
         y -= bs;
