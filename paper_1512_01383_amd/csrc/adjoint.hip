@@ -480,19 +480,42 @@ __global__ __launch_bounds__(64 * T) void k_adj_primal(AdjBuf B, IterArgs A) {
   for (int g = 0; g < T; g++)
     if (g < t) pre += ex_v[g][lane];
   const float Kq = A.sig_q * B.q[x];
+  // the inputs of one label; the next label's are loaded while the current one is done
+  // (this kernel writes only the u / s adjoints of its own pixel)
+  const long long xl = c > 0 ? x - 1 : x, xu = r > 0 ? x - W : x;
+  struct In {
+    float v, z, px, pxl, py, pyu, u, up, s, sp;
+  };
+  auto load = [&](int i, In &o) {
+    const size_t b = (size_t)i * ps;
+    o.v = B.v[b + x];
+    o.z = B.z[b + x];
+    o.px = B.px[b + x];
+    o.pxl = B.px[b + xl];
+    o.py = B.py[b + x];
+    o.pyu = B.py[b + xu];
+    o.u = B.u[b + x];
+    o.up = B.up[b + x];
+    o.s = B.s[b + x];
+    o.sp = B.sp[b + x];
+  };
+  In nx;
+  if (i0 < i1) load(i0, nx);
   for (int i = i0; i < i1; i++) {
+    const In cu = nx;
+    if (i + 1 < i1) load(i + 1, nx);
     const size_t o = (size_t)i * ps;
-    const float Kv = A.sig[i] * B.v[o + x];
-    const float Kz = A.sig[i] * B.z[o + x];
+    const float Kv = A.sig[i] * cu.v;
+    const float Kz = A.sig[i] * cu.z;
     float dv = 0.f;
-    if (c < W - 1) dv += B.px[o + x];
-    if (c > 0) dv -= B.px[o + x - 1];
-    if (r < H - 1) dv += B.py[o + x];
-    if (r > 0) dv -= B.py[o + x - W];
+    if (c < W - 1) dv += cu.px;
+    if (c > 0) dv -= cu.pxl;
+    if (r < H - 1) dv += cu.py;
+    if (r > 0) dv -= cu.pyu;
     const float ubb = Kv - A.sig_p * dv;
     const float sbb = Kz - A.h[i] * Kq - A.gam[i] * Kv + A.h[i] * pre;
     pre += Kv;
-    const float ut = B.u[o + x] + B.up[o + x], st = B.s[o + x] + B.sp[o + x];
+    const float ut = cu.u + cu.up, st = cu.s + cu.sp;
     B.u[o + x] = ut + 2.f * ubb;
     B.up[o + x] = -ubb;
     B.s[o + x] = st + 2.f * sbb;

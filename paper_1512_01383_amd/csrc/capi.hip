@@ -317,6 +317,10 @@ IterPtrs<float> iter_ptrs_f(sl_problem_ *P) {
   Q.cost = (const float *)(P->ws + P->lay.off_cost);
   Q.tau = (const float *)(P->ws + P->lay.off_tau);
   Q.sinfo = (const unsigned *)(P->ws + P->lay.off_sinfo);
+  Q.spi = Q.sp;
+  Q.vi = Q.v;
+  Q.zi = Q.z;
+  Q.qdi = Q.qd;
   return Q;
 }
 
@@ -341,6 +345,10 @@ sl_status enqueue_iters(sl_problem_ *P, int iters) {
       B.cost = Q.cost;
       B.tau = Q.tau;
       B.sinfo = Q.sinfo;
+      B.spi = Q.spi;
+      B.vi = (const uint16_t *)Q.vi;
+      B.zi = (const uint16_t *)Q.zi;
+      B.qdi = Q.qdi;
       e = launch_pdhg_iter(P->piece, P->add, true, P->cfg, P->A, &B, P->st);
     } else {
       e = launch_pdhg_iter(P->piece, P->add, false, P->cfg, P->A, &Q, P->st);
@@ -1304,19 +1312,21 @@ sl_status sl_unrolled_backward(sl_problem P, const float *grad_u, float *grad_f,
     HIPCHK(hipMemcpyAsync(uslot(0), ck, 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "restore");
     HIPCHK(hipMemcpyAsync(sslot(0), ck + 2 * k * pl, 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "restore");
     HIPCHK(hipMemcpyAsync(yv(0), ck + 4 * k * pl, yslot, hipMemcpyDeviceToDevice, P->st), "restore");
-    // replay the segment, keeping every state (same launch configuration as the forward pass)
+    // replay the segment, keeping every state (same launch configuration as the forward
+    // pass): each iteration reads state j from its slots and writes state j + 1 to the next
     for (int j = 0; j + 1 < n; j++) {
-      HIPCHK(launch_copy2(sslot(j), sslot(j + 2), (size_t)k * ps, yv(j), yv(j + 1), (size_t)(2 * k + 1) * ps,
-                          P->st),
-             "replay");
       IterPtrs<float> R = iter_ptrs_f(P);
       R.u = uslot(j + 1);
       R.up = uslot(j);
       R.un = uslot(j + 2);
       R.s = sslot(j + 1);
+      R.spi = sslot(j);
       R.sp = sslot(j + 2);
+      R.vi = yv(j);
       R.v = yv(j + 1);
+      R.zi = yz(j);
       R.z = yz(j + 1);
+      R.qdi = yq(j);
       R.qd = yq(j + 1);
       R.pin = yp(j);
       R.pout = yp(j + 1);

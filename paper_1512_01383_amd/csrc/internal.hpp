@@ -55,6 +55,11 @@ struct IterPtrs {
   float *qd;
   const float *fn, *wadd, *cost, *tau;
   const unsigned *sinfo;  // straddling intervals per pixel (TRUNC_QUAD)
+  // read side of sp, v, z, qd: the same planes for an iteration in place; distinct ones
+  // when a replay keeps every state (the new values go to the slot of the next state)
+  const float *spi;
+  const DT *vi, *zi;
+  const float *qdi;
 };
 
 // Host-side launchers (pdhg_iter.hip, aux.hip).

@@ -96,13 +96,13 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   float Tc = 0.f;
   for (int i = i0; i < i1; i++) {
     const float s = bld(P.s + (size_t)(i) * ps, nb4, xm);
-    const float sb = 2.f * s - bld(P.sp + (size_t)(i) * ps, nb4, xm);
+    const float sb = 2.f * s - bld(P.spi + (size_t)(i) * ps, nb4, xm);
     Tc += A.h[i] * sb;
     lsa[i * NP + lt] = s;
     lsb[i * NP + lt] = sb;
   }
   if (G > 1) ex[grp][lt] = Tc;
-  const float qd = bld(P.qd, nb4, xm);
+  const float qd = bld(P.qdi, nb4, xm);
   const float fc = PIECE != SLI_SAMPLED ? bld(P.fn, nb4, xm) : 0.f;
   if (G > 1) __syncthreads();
   float T = 0.f, base = 0.f;
@@ -151,8 +151,8 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       const float g0 = A.gam[i], g1 = A.gam[i + 1];
       const float sb = lsb[i * NP + lt];
       const float ub = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
-      float v = ldvb(P.v + (size_t)(i) * ps, db) + A.sig[i] * (ub + run - g0 * sb);
-      float z = ldvb(P.z + (size_t)(i) * ps, db) + A.sig[i] * sb;
+      float v = ldvb(P.vi + (size_t)(i) * ps, db) + A.sig[i] * (ub + run - g0 * sb);
+      float z = ldvb(P.zi + (size_t)(i) * ps, db) + A.sig[i] * sb;
       float y = v * A.ih[i], w = z * A.ih[i];
       float bs = 0.f, cs = 0.f;
       if (ADD) {
@@ -232,8 +232,8 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     o.py = bldv(ppy, bd, dm);
     o.pxu = bldv(ppx, bd, dm_up);
     o.pyu = bldv(ppy, bd, dm_up);
-    o.v = bldv(P.v + (size_t)i * ps, bd, dm);
-    o.z = bldv(P.z + (size_t)i * ps, bd, dm);
+    o.v = bldv(P.vi + (size_t)i * ps, bd, dm);
+    o.z = bldv(P.zi + (size_t)i * ps, bd, dm);
     o.eu = bld(pu, b4, em);
     o.eup = bld(pup, b4, em);
     o.epx = bldv(ppx, bd, eml);
