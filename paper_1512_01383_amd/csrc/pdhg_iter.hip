@@ -92,6 +92,11 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   const int i0 = grp * chn;
   const int i1 = min(k, i0 + chn);
 
+  // several groups: the straddle information is loaded first and this group's straddle
+  // inputs are gathered before the exchange of the chunk sums, so their latency overlaps
+  // the wait at its barrier (one group has no barrier there and loads them later)
+  const unsigned info_g = (G > 1 && PIECE == SLI_TRUNC && in) ? ldb(P.sinfo, xb) : 0xFFFFFFFFu;
+
   // ---- phase A: over-relaxed multiplier of the chunk, its weighted sum
   float Tc = 0.f;
   for (int i = i0; i < i1; i++) {
@@ -100,6 +105,19 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     Tc += A.h[i] * sb;
     lsa[i * NP + lt] = s;
     lsb[i * NP + lt] = sb;
+  }
+  float gu = 0.f, gv = 0.f, gz = 0.f, gwl = 0.f, gwh = 0.f;
+  if (G > 1 && PIECE == SLI_TRUNC && in && grp < 2) {
+    const int i = (int)((info_g >> (13 * grp)) & 31u);
+    if (i != 31) {
+      gu = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
+      gv = ldvb(P.vi + (size_t)(i) * ps, db);
+      gz = ldvb(P.zi + (size_t)(i) * ps, db);
+      if (ADD) {
+        gwl = ldb(P.wadd + (size_t)(i) * ps, xb);
+        gwh = ldb(P.wadd + (size_t)(i + 1) * ps, xb);
+      }
+    }
   }
   if (G > 1) ex[grp][lt] = Tc;
   const float qd = bld(P.qdi, nb4, xm);
@@ -123,7 +141,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   int si0 = -1, si1 = -1;
   float sv0 = 0.f, sz0 = 0.f, sv1 = 0.f, sz1 = 0.f;   // G = 1: the results stay in registers
   if (PIECE == SLI_TRUNC && in) {
-    const unsigned info = ldb(P.sinfo, xb);
+    const unsigned info = G > 1 ? info_g : ldb(P.sinfo, xb);
     if (G > 1) {
       if ((info & 31u) != 31u) si0 = (int)(info & 31u);
       if (((info >> 13) & 31u) != 31u) si1 = (int)((info >> 13) & 31u);
@@ -150,13 +168,14 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       }
       const float g0 = A.gam[i], g1 = A.gam[i + 1];
       const float sb = lsb[i * NP + lt];
-      const float ub = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
-      float v = ldvb(P.vi + (size_t)(i) * ps, db) + A.sig[i] * (ub + run - g0 * sb);
-      float z = ldvb(P.zi + (size_t)(i) * ps, db) + A.sig[i] * sb;
+      const float ub = G > 1 ? gu : 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
+      float v = (G > 1 ? gv : ldvb(P.vi + (size_t)(i) * ps, db)) + A.sig[i] * (ub + run - g0 * sb);
+      float z = (G > 1 ? gz : ldvb(P.zi + (size_t)(i) * ps, db)) + A.sig[i] * sb;
       float y = v * A.ih[i], w = z * A.ih[i];
       float bs = 0.f, cs = 0.f;
       if (ADD) {
-        const float wl = ldb(P.wadd + (size_t)(i) * ps, xb), wh = ldb(P.wadd + (size_t)(i + 1) * ps, xb);
+        const float wl = G > 1 ? gwl : ldb(P.wadd + (size_t)(i) * ps, xb);
+        const float wh = G > 1 ? gwh : ldb(P.wadd + (size_t)(i + 1) * ps, xb);
         bs = (wh - wl) * A.ih[i];
         cs = -wl + bs * g0;
         y -= bs;
