@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="tq", choices=["tq", "batch", "diff"],
+    ap.add_argument("--workload", default="tq", choices=["tq", "stereo", "batch", "diff"],
                     help="tq: one truncated-quadratic instance (default); batch: 64 mixed "
                          "instances in one persistent launch per iteration; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
@@ -105,7 +105,10 @@ def main():
     if args.workload == "diff":
         return bench_diff(args)
 
-    wl = W.truncated_quadratic(L=args.L, H=args.size, W=args.size)
+    if args.workload == "stereo":
+        wl = W.stereo()            # sampled costs, 384x288, 64 disparities, L = 8
+    else:
+        wl = W.truncated_quadratic(L=args.L, H=args.size, W=args.size)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     g = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY, device=dev)
@@ -200,13 +203,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else "f32 (bf16 dual storage)",
         "data": "synthetic",
-        "config": {"workload": f"truncated-quadratic denoising {wl.H}x{wl.W}, L={wl.L}, "
-                               f"lambda={wl.lam}, nu=0.025; step = {CHECK_EVERY} fused "
-                               f"iterations + FP64 gap monitor",
+        "config": {"workload": (f"sampled-cost stereo {wl.W}x{wl.H}, {wl.M} disparity samples, "
+                                f"L={wl.L}, lambda={wl.lam}" if args.workload == "stereo" else
+                                f"truncated-quadratic denoising {wl.H}x{wl.W}, L={wl.L}, "
+                                f"lambda={wl.lam}, nu=0.025") +
+                               f"; step = {CHECK_EVERY} fused iterations + FP64 gap monitor",
                    "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}"),
+                     "traffic": (None if args.workload == "stereo" else
+                                 measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}")),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_hash": kernel_hash(), "tiling": list(g.get_tiling())},
