@@ -185,10 +185,22 @@ def main():
         t0 = time.perf_counter()
         o.run(n_it)
         dt_cpu = time.perf_counter() - t0
+        # the same on one thread, over a shorter sample
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        o.run(2)
+        per1 = (time.perf_counter() - t0) / 2
+        n1 = max(2, int(args.cpu_seconds / 3 / max(per1, 1e-6)))
+        t0 = time.perf_counter()
+        o.run(n1)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(ncores)
         cpu = {"value": N * k * n_it / dt_cpu, "unit": "pixel-label-iter/s", "cores": ncores,
                "kind": "oracle",
                "sample": f"{n_it} FP64 iterations of the same {wl.H}x{wl.W} L={wl.L} problem "
-                         f"({dt_cpu:.1f} s, monitor excluded)"}
+                         f"({dt_cpu:.1f} s, monitor excluded)",
+               "value_1_thread": N * k * n1 / dt1,
+               "sample_1_thread": f"{n1} iterations ({dt1:.1f} s)"}
 
     out = {
         "metric": "lifted PDHG pixel-label-iter/s",
