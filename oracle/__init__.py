@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "oracle.c")
 
 QUAD, TRUNC_QUAD, SAMPLED = 0, 1, 2
+TV_ISO, TV_ANISO = 0, 1
 PIECE_QUAD, PIECE_PL = 0, 1
 
 
@@ -38,7 +39,8 @@ class _Desc(C.Structure):
                 ("f", C.POINTER(C.c_float)), ("a", C.c_double), ("nu", C.c_double),
                 ("M", C.c_int32), ("tau", C.POINTER(C.c_double)),
                 ("samples", C.POINTER(C.c_float)), ("lam", C.c_double),
-                ("normalize", C.c_int32), ("n_sub", C.c_int32), ("step_balance", C.c_double)]
+                ("normalize", C.c_int32), ("n_sub", C.c_int32), ("step_balance", C.c_double),
+                ("tv", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -91,11 +93,13 @@ def lib():
         L.or_lower_hull.restype = C.c_int
         L.or_proj_simplex.argtypes = [C.c_int, _dp, _dp]
         L.or_proj_ball.argtypes = [_dp, _dp, C.c_double]
+        L.or_proj_box.argtypes = [_dp, _dp, C.c_double]
         L.or_residual_norms.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_unrolled_forward.argtypes = [C.c_void_p, C.c_int]
         L.or_unrolled_backward.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_step_vjp.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp]
         L.or_proj_ball_vjp.argtypes = [C.c_double] * 5 + [_dp] * 3
+        L.or_proj_box_vjp.argtypes = [C.c_double] * 5 + [_dp] * 3
         L.or_proj_epi_quad_vjp.argtypes = [C.c_double] * 9 + [_dp] * 4
         L.or_proj_epi_pl_vjp.argtypes = [C.c_int, _dp, _dp] + [C.c_double] * 4 + [_dp] * 3
         _lib = L
@@ -174,6 +178,19 @@ def proj_ball(px, py, radius):
     return a.value, b.value
 
 
+def proj_box(px, py, radius):
+    a, b = C.c_double(px), C.c_double(py)
+    lib().or_proj_box(C.byref(a), C.byref(b), radius)
+    return a.value, b.value
+
+
+def proj_box_vjp(ax, ay, radius, pxb, pyb):
+    """Adjoint of the box projection: returns (axb, ayb, radius_b)."""
+    a, b, r = C.c_double(), C.c_double(), C.c_double(0.0)
+    lib().or_proj_box_vjp(ax, ay, radius, pxb, pyb, C.byref(a), C.byref(b), C.byref(r))
+    return a.value, b.value, r.value
+
+
 def proj_ball_vjp(ax, ay, radius, pxb, pyb):
     """Adjoint of the ball projection: returns (axb, ayb, radius_b)."""
     a, b, r = C.c_double(), C.c_double(), C.c_double(0.0)
@@ -232,6 +249,7 @@ class Problem:
         d.normalize = 1 if normalize else 0
         d.n_sub = n_sub
         d.step_balance = float(step_balance)
+        d.tv = int(wl.tv)
         h = lib().or_create(C.byref(d))
         if not h:
             raise ValueError(lib().or_last_error().decode())

@@ -60,6 +60,7 @@ struct or_problem {
   double shift, scale; /* original label = shift + scale * normalised label */
   double *gam, *h;     /* normalised labels [L], interval lengths [k]        */
   double lam;          /* lambda * scale                                     */
+  int tv;              /* OR_TV_ISO or OR_TV_ANISO                           */
   int rho;
   double a, nu;        /* a * scale^2, nu                                    */
   int n_sub;
@@ -318,6 +319,13 @@ void or_proj_ball(double *px, double *py, double radius) {
   }
 }
 
+/* projection onto the l-inf box of the given half-width (the set K of Prop. 5 for the
+ * anisotropic TV, whose dual norm is the max norm) */
+void or_proj_box(double *px, double *py, double radius) {
+  *px = clampd(*px, -radius, radius);
+  *py = clampd(*py, -radius, radius);
+}
+
 /* ------------------------------------------------------------------------------- */
 /* data-term pieces                                                                  */
 
@@ -560,6 +568,8 @@ or_problem *or_create(const or_desc *d) {
   for (int j = 0; j < d->L; j++) P->gam[j] = (d->gamma[j] - P->shift) / P->scale;
   for (int i = 0; i < k; i++) P->h[i] = P->gam[i + 1] - P->gam[i];
   P->lam = d->lambda * P->scale;
+  if (d->tv != OR_TV_ISO && d->tv != OR_TV_ANISO) FAIL("unknown TV kind");
+  P->tv = d->tv;
   if (d->rho == OR_QUAD || d->rho == OR_TRUNC_QUAD) {
     if (!d->f || !finite_f(d->f, N)) FAIL("f must be given and finite");
     if (!(d->a > 0.0) || !isfinite(d->a)) FAIL("a must be > 0");
@@ -660,6 +670,19 @@ void or_destroy(or_problem *P) {
 /* ------------------------------------------------------------------------------- */
 /* the primal-dual iteration                                                          */
 
+/* projection onto the per-label set K of radius lambda h_i, and the norm of the
+ * regulariser whose dual ball it is */
+static void proj_K(const or_problem *P, double *px, double *py, double radius) {
+  if (P->tv == OR_TV_ANISO)
+    or_proj_box(px, py, radius);
+  else
+    or_proj_ball(px, py, radius);
+}
+
+static double tv_norm(const or_problem *P, double gx, double gy) {
+  return P->tv == OR_TV_ANISO ? fabs(gx) + fabs(gy) : sqrt(gx * gx + gy * gy);
+}
+
 static void pdhg_iteration(or_problem *P) {
   const int k = P->k;
   const int64_t N = P->N, kN = (int64_t)k * N;
@@ -669,7 +692,7 @@ static void pdhg_iteration(or_problem *P) {
     P->sb[i] = 2.0 * P->s[i] - P->sp[i];
   }
   or_apply_K(P, P->ub, P->sb, P->Kv, P->Kq, P->Kpx, P->Kpy, P->Kz);
-  /* dual ascent and projections onto C (per-interval scaled epigraphs) and K (balls) */
+  /* dual ascent and projections onto C (per-interval scaled epigraphs) and K (balls or boxes) */
 #pragma omp parallel for schedule(static)
   for (int64_t x = 0; x < N; x++) {
     piece pc;
@@ -684,7 +707,7 @@ static void pdhg_iteration(or_problem *P) {
       P->z[e] = P->h[i] * w;
       double px = P->px[e] + P->sig_p * P->Kpx[e];
       double py = P->py[e] + P->sig_p * P->Kpy[e];
-      or_proj_ball(&px, &py, P->lam * P->h[i]);
+      proj_K(P, &px, &py, P->lam * P->h[i]);
       P->px[e] = px;
       P->py[e] = py;
     }
@@ -752,7 +775,7 @@ void or_monitor(or_problem *P, or_report *out) {
   for (int i = 0; i < k; i++) {
     or_grad(P->H, P->W, ut + i * N, gx, gy);
     double acc = 0.0;
-    for (int64_t x = 0; x < N; x++) acc += sqrt(gx[x] * gx[x] + gy[x] * gy[x]);
+    for (int64_t x = 0; x < N; x++) acc += tv_norm(P, gx[x], gy[x]);
     P_tv += P->lam * P->h[i] * acc;
   }
   double primal = P_tv;
@@ -776,7 +799,7 @@ void or_monitor(or_problem *P, or_report *out) {
   for (int i = 0; i < k; i++) {
     or_grad(P->H, P->W, ut + i * N, gx, gy);
     double acc = 0.0;
-    for (int64_t x = 0; x < N; x++) acc += sqrt(gx[x] * gx[x] + gy[x] * gy[x]);
+    for (int64_t x = 0; x < N; x++) acc += tv_norm(P, gx[x], gy[x]);
     primal_g += P->lam * P->h[i] * acc;
   }
   for (int64_t x = 0; x < N; x++) primal_g += dat[x];
@@ -786,7 +809,7 @@ void or_monitor(or_problem *P, or_report *out) {
   for (int i = 0; i < k; i++) {
     for (int64_t x = 0; x < N; x++) {
       double a = P->px[i * N + x], b = P->py[i * N + x];
-      or_proj_ball(&a, &b, P->lam * P->h[i]);
+      proj_K(P, &a, &b, P->lam * P->h[i]);
       pxh[i * N + x] = a;
       pyh[i * N + x] = b;
     }
@@ -817,7 +840,7 @@ void or_monitor(or_problem *P, or_report *out) {
   }
   or_grad(P->H, P->W, ubp, gx, gy);
   double e = 0.0;
-  for (int64_t x = 0; x < N; x++) e += enc[x] + P->lam * sqrt(gx[x] * gx[x] + gy[x] * gy[x]);
+  for (int64_t x = 0; x < N; x++) e += enc[x] + P->lam * tv_norm(P, gx[x], gy[x]);
 
   if (!P->have_best || primal < P->best_P) P->best_P = primal;
   if (!P->have_best || dualv > P->best_D) P->best_D = dualv;
@@ -887,7 +910,7 @@ void or_normalized(const or_problem *P, double *gam, double *lam, double *shift,
 /* values w. Every map of the iteration is differentiated where it is smooth; on the   */
 /* boundary between two parts of a projection the part the forward pass chose decides */
 /* (the graph of a conjugate is C^1 at ray/arc junctions, so only kinks of PL pieces  */
-/* and the ball boundary are genuine nonsmooth points).                               */
+/* and the boundary of K (ball or box) are genuine nonsmooth points).                 */
 
 /* adjoint of the projection onto the l2 ball: p = a if |a| <= r, else r a / |a| */
 void or_proj_ball_vjp(double ax, double ay, double radius, double pxb, double pyb,
@@ -902,6 +925,22 @@ void or_proj_ball_vjp(double ax, double ay, double radius, double pxb, double py
   } else {
     *axb = pxb;
     *ayb = pyb;
+  }
+}
+
+/* adjoint of the projection onto the box: p_j = clamp(a_j, -r, r) per component; a clamped
+ * component passes nothing to a and its sign to r */
+void or_proj_box_vjp(double ax, double ay, double radius, double pxb, double pyb,
+                     double *axb, double *ayb, double *rb) {
+  *axb = pxb;
+  *ayb = pyb;
+  if (fabs(ax) > radius) {
+    *axb = 0.0;
+    *rb += ax > 0.0 ? pxb : -pxb;
+  }
+  if (fabs(ay) > radius) {
+    *ayb = 0.0;
+    *rb += ay > 0.0 ? pyb : -pyb;
   }
 }
 
@@ -1072,7 +1111,7 @@ int or_step_vjp(or_problem *P, const double *st, double *adj, double *gc, double
   }
   for (int64_t x = 0; x < N; x++) Aq[x] += qb[x];
 
-  /* q' = q + sigma_q (K_q xbar - 1); p' = Proj_ball(p + sigma_p grad ubar);
+  /* q' = q + sigma_q (K_q xbar - 1); p' = Proj_K(p + sigma_p grad ubar);
    * (v', z') = h Proj_epi((v + sigma K_v xbar, z + sigma K_z xbar) / h) */
   double lam_acc = 0.0;
 #pragma omp parallel for schedule(static) reduction(+ : lam_acc)
@@ -1085,7 +1124,10 @@ int or_step_vjp(or_problem *P, const double *st, double *adj, double *gc, double
       int64_t e = i * N + x;
       double ax = px[e] + P->sig_p * Kpx[e], ay = py[e] + P->sig_p * Kpy[e];
       double axb, ayb, radb = 0.0;
-      or_proj_ball_vjp(ax, ay, P->lam * P->h[i], Apx[e], Apy[e], &axb, &ayb, &radb);
+      if (P->tv == OR_TV_ANISO)
+        or_proj_box_vjp(ax, ay, P->lam * P->h[i], Apx[e], Apy[e], &axb, &ayb, &radb);
+      else
+        or_proj_ball_vjp(ax, ay, P->lam * P->h[i], Apx[e], Apy[e], &axb, &ayb, &radb);
       lam_acc += radb * P->h[i];
       pxb[e] = axb;
       pyb[e] = ayb;

@@ -22,6 +22,10 @@ extern "C" {
 
 enum { OR_QUAD = 0, OR_TRUNC_QUAD = 1, OR_SAMPLED = 2 };
 enum { OR_PIECE_QUAD = 0, OR_PIECE_PL = 1 };
+/* regulariser: isotropic TV (l2 norm of the gradient, Prop. 5: K is a product of l2
+ * balls) or anisotropic TV (l1 norm, Sec. 5, comparison with Zach and Kohli: Props. 4
+ * and 5 hold for any convex one-homogeneous norm, and K becomes a product of l-inf boxes) */
+enum { OR_TV_ISO = 0, OR_TV_ANISO = 1 };
 
 typedef struct {
   int32_t H, W, L;          /* image size, number of labels (L >= 2)                 */
@@ -37,6 +41,7 @@ typedef struct {
   int32_t normalize;        /* 1: iterate on labels mapped affinely onto [0,1]         */
   int32_t n_sub;            /* samples per straddling truncated-quadratic interval     */
   double step_balance;      /* dual steps times c, primal steps divided by c (0: c = 1) */
+  int32_t tv;               /* OR_TV_ISO or OR_TV_ANISO                                */
 } or_desc;
 
 typedef struct {
@@ -85,6 +90,8 @@ int or_step_vjp(or_problem *P, const double *state, double *adj, double *gc, dou
                 double *gw);
 void or_proj_ball_vjp(double ax, double ay, double radius, double pxb, double pyb,
                       double *axb, double *ayb, double *rb);
+void or_proj_box_vjp(double ax, double ay, double radius, double pxb, double pyb,
+                     double *axb, double *ayb, double *rb);
 void or_proj_epi_quad_vjp(double a, double c, double d, double g0, double g1, double y0,
                           double w0, double yb, double wb, double *y0b, double *w0b,
                           double *cb, double *db);
@@ -109,6 +116,7 @@ void or_proj_epi_pl(int n, const double *t, const double *r, double *y, double *
 int or_lower_hull(int n, const double *t, const double *r, int *idx);
 void or_proj_simplex(int n, const double *x, double *out);
 void or_proj_ball(double *px, double *py, double radius);
+void or_proj_box(double *px, double *py, double radius);
 
 #ifdef __cplusplus
 }

@@ -37,13 +37,19 @@ def iso_tv(u: np.ndarray) -> float:
     return float(np.sqrt(gx * gx + gy * gy).sum())
 
 
+def aniso_tv(u: np.ndarray) -> float:
+    gx, gy = fd_grad(u)
+    return float((np.abs(gx) + np.abs(gy)).sum())
+
+
 # --------------------------------------------------------------------------- ROF (Prop. 3)
 
 def fgp_box_rof(f: np.ndarray, lam: float, lo: float = 0.0, hi: float = 1.0,
-                tol: float = 1e-11, max_iter: int = 400000):
-    """Fast gradient projection on the dual of box-constrained isotropic ROF
-    (Beck & Teboulle 2009):  min_{lo<=u<=hi} 1/2 |u - f|^2 + lam sum |grad u|.
-    Returns (u, primal, dual)."""
+                tol: float = 1e-11, max_iter: int = 400000, aniso: bool = False):
+    """Fast gradient projection on the dual of box-constrained ROF (Beck & Teboulle
+    2009):  min_{lo<=u<=hi} 1/2 |u - f|^2 + lam sum |grad u|, with the isotropic (l2) or
+    the anisotropic (l1) norm of the gradient; the dual variable is then projected onto
+    unit l2 discs or onto the unit l-inf box. Returns (u, primal, dual)."""
     f = f.astype(np.float64)
     px = np.zeros_like(f)
     py = np.zeros_like(f)
@@ -56,7 +62,7 @@ def fgp_box_rof(f: np.ndarray, lam: float, lo: float = 0.0, hi: float = 1.0,
 
     def bounds(ax, ay):
         u = u_of(ax, ay)
-        primal = 0.5 * ((u - f) ** 2).sum() + lam * iso_tv(u)
+        primal = 0.5 * ((u - f) ** 2).sum() + lam * (aniso_tv(u) if aniso else iso_tv(u))
         dual = 0.5 * ((u - f) ** 2).sum() - lam * (fd_div(ax, ay) * u).sum()
         return u, primal, dual
 
@@ -64,8 +70,11 @@ def fgp_box_rof(f: np.ndarray, lam: float, lo: float = 0.0, hi: float = 1.0,
         u = u_of(rx, ry)
         gx, gy = fd_grad(u)
         qx, qy = rx + step * gx, ry + step * gy
-        nrm = np.maximum(1.0, np.sqrt(qx * qx + qy * qy))
-        nx, ny = qx / nrm, qy / nrm
+        if aniso:
+            nx, ny = np.clip(qx, -1.0, 1.0), np.clip(qy, -1.0, 1.0)
+        else:
+            nrm = np.maximum(1.0, np.sqrt(qx * qx + qy * qy))
+            nx, ny = qx / nrm, qy / nrm
         t2 = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
         rx = nx + (t - 1.0) / t2 * (nx - px)
         ry = ny + (t - 1.0) / t2 * (ny - py)
@@ -181,6 +190,23 @@ def brute_force_lifted(cost_fn, grid: np.ndarray, gamma: np.ndarray, H: int, W: 
                          0.0, 1.0)                                       # [C, k, H, W]
         gx, gy = fd_grad(lifted)
         tv = (h[None, :, None, None] * np.sqrt(gx ** 2 + gy ** 2)).sum(axis=(1, 2, 3))
+        best = min(best, float((data + lam * tv).min()))
+    return best
+
+
+def brute_force_aniso(cost_fn, grid: np.ndarray, H: int, W: int, lam: float) -> float:
+    """Minimum over all assignments u(x) in ``grid`` of the unlifted energy
+    sum_x cost_fn(x, u(x)) + lam sum_x (|d_x u| + |d_y u|) (anisotropic TV)."""
+    N = H * W
+    G = len(grid)
+    costs = np.array([[cost_fn(x, g) for g in grid] for x in range(N)])  # [N, G]
+    best = np.inf
+    combos = np.array(list(itertools.product(range(G), repeat=N)))      # [C, N]
+    for chunk in np.array_split(combos, max(1, len(combos) // 200000)):
+        vals = grid[chunk].reshape(-1, H, W)
+        data = costs[np.arange(N)[None, :], chunk].sum(axis=1)
+        gx, gy = fd_grad(vals)
+        tv = (np.abs(gx) + np.abs(gy)).sum(axis=(1, 2))
         best = min(best, float((data + lam * tv).min()))
     return best
 

@@ -47,6 +47,7 @@ class Workload:
     samples: Optional[np.ndarray] = None  # [M][H][W] float32
     iters: int = 0                      # fixed iteration count of the workload (0: run to gap)
     target: Optional[np.ndarray] = None  # clean image (differentiation workload)
+    tv: int = 0                         # 0: isotropic TV (l2), 1: anisotropic TV (l1)
 
     @property
     def L(self) -> int:
