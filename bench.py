@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--tv", default="iso", choices=["iso", "aniso"],
+                    help="regulariser: isotropic (l2) or anisotropic (l1) total variation")
     ap.add_argument("--kernel-iters", type=int, default=500)
     ap.add_argument("--gap-max-iters", type=int, default=60000)
     ap.add_argument("--no-gap", action="store_true")
@@ -109,6 +111,7 @@ def main():
         wl = W.stereo()            # sampled costs, 384x288, 64 disparities, L = 8
     else:
         wl = W.truncated_quadratic(L=args.L, H=args.size, W=args.size)
+    wl.tv = 1 if args.tv == "aniso" else 0
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     g = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY, device=dev)
@@ -219,12 +222,14 @@ def main():
                                 f"L={wl.L}, lambda={wl.lam}" if args.workload == "stereo" else
                                 f"truncated-quadratic denoising {wl.H}x{wl.W}, L={wl.L}, "
                                 f"lambda={wl.lam}, nu=0.025") +
+                               (", anisotropic TV" if wl.tv else "") +
                                f"; step = {CHECK_EVERY} fused iterations + FP64 gap monitor",
-                   "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage},
+                   "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage, "tv": args.tv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (None if args.workload == "stereo" else
-                                 measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}")),
+                                 measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}"
+                                                  + ("_aniso" if wl.tv else ""))),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_hash": kernel_hash(), "tiling": list(g.get_tiling())},

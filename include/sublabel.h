@@ -61,7 +61,11 @@ typedef enum {
  *                    interval the convex envelope of its samples is used (Sec. 5.4). */
 typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2 } sl_rho_kind;
 
-/* TV kind: isotropic (Prop. 5: K is a product of l2 balls). */
+/* TV kind. ISO: sum_x |grad u(x)|_2, K a product of l2 discs of radius lambda h_i
+ * (Prop. 5). ANISO: sum_x |grad u(x)|_1; Props. 4 and 5 hold for any convex
+ * one-homogeneous norm (Sec. 5, comparison with Zach and Kohli), so K becomes a product
+ * of l-inf boxes of half-width lambda h_i. The certified bounds and the nonconvex energy
+ * use the same norm. */
 typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;
 
 /* Storage precision of the iteration state. FP32: everything in float. BF16_DUAL: the
@@ -84,7 +88,7 @@ typedef struct {
                               additive values w_j(x), interpolated linearly between
                               labels and added to rho. May be NULL. Read in sl_create. */
   double lambda;           /* >= 0                                                        */
-  sl_tv_kind tv;           /* SL_TV_ISO only (ANISO -> SL_ERR_UNSUPPORTED)               */
+  sl_tv_kind tv;           /* SL_TV_ISO or SL_TV_ANISO (else INVALID_ARG)                */
   sl_storage storage;
   int32_t check_every;     /* iterations between gap checks in sl_run_to_gap (>= 1)      */
   int32_t normalize_labels;/* 1: iterate on the labels mapped affinely onto [0,1] (an

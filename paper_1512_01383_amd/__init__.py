@@ -132,7 +132,7 @@ def _dev_f32(a, device):
 
 
 def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
-               check_every, device, adaptive=False):
+               check_every, device, adaptive=False, tv=TV_ISO):
     """Fill a Desc; device copies of the inputs are kept on ``obj._keep``."""
     obj.H, obj.W = int(H), int(W)
     obj.gamma = np.ascontiguousarray(gamma, dtype=np.float64)
@@ -153,7 +153,7 @@ def _make_desc(obj, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, norm
         d.samples = obj._keep["samples"].data_ptr()
     obj.has_w = tau is not None and int(rho) != RHO_SAMPLED
     d.lam = float(lam)
-    d.tv = TV_ISO
+    d.tv = int(tv)
     d.storage = {"fp32": STORE_FP32, "bf16": STORE_BF16_DUAL}[storage]
     d.check_every = int(check_every)
     d.normalize_labels = 1 if normalize else 0
@@ -172,13 +172,13 @@ class Problem:
     def __init__(self, H: int, W: int, gamma, rho: int, lam: float, f=None, a: float = 1.0,
                  nu: float = 0.0, tau=None, samples=None, storage: str = "fp32",
                  normalize: bool = True, check_every: int = 50, device=None,
-                 adaptive: bool = False):
+                 adaptive: bool = False, tv: int = TV_ISO):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()
         self._keep = {}
         d = _make_desc(self, H, W, gamma, rho, lam, f, a, nu, tau, samples, storage, normalize,
-                       check_every, self.device, adaptive)
+                       check_every, self.device, adaptive, tv)
         self.desc = d
         nbytes = C.c_size_t()
         _check(L_.sl_workspace_size(C.byref(d), C.byref(nbytes)))
@@ -193,6 +193,7 @@ class Problem:
 
     @classmethod
     def from_workload(cls, wl, **kw):
+        kw.setdefault("tv", getattr(wl, "tv", TV_ISO))
         return cls(wl.H, wl.W, wl.gamma, wl.rho, wl.lam, f=wl.f, a=wl.a, nu=wl.nu, tau=wl.tau,
                    samples=wl.samples, **kw)
 
@@ -320,7 +321,7 @@ class BatchProblem(Problem):
             it = _Inst()
             descs[j] = _make_desc(it, wl.H, wl.W, wl.gamma, wl.rho, wl.lam, wl.f, wl.a, wl.nu,
                                   wl.tau, wl.samples, storage, normalize, check_every,
-                                  self.device, adaptive)
+                                  self.device, adaptive, getattr(wl, "tv", TV_ISO))
             self._insts.append(it)
         self.n = len(instances)
         nbytes = C.c_size_t()

@@ -7,8 +7,9 @@
 // Its adjoint, given the adjoint of x', runs the steps backwards:
 //   1. primal descent: the adjoint of y' -> K^T y' is K, applied to -T xbar' ;
 //   2. q' = q + sigma_q (K_q xbar - 1): identity plus the scaled K_q part;
-//   3. p' = Proj_ball(p + sigma_p grad ubar): Jacobian transpose of the ball projection
-//      (Prop. 5), the radius lambda h_i collects the lambda adjoint;
+//   3. p' = Proj_K(p + sigma_p grad ubar): Jacobian transpose of the projection onto the
+//      disc (Prop. 5) or, for the anisotropic TV, the box; the radius lambda h_i collects
+//      the lambda adjoint;
 //   4. (v', z') = h Proj_epi((v, z + sigma K xbar) / h): Jacobian transpose of the epigraph
 //      projection (Sec. 4, Fig. 2) on the part of the graph the point landed on; the
 //      piece parameters collect the adjoints of the data centre c and of w;
@@ -41,6 +42,16 @@ __device__ __forceinline__ void ball_vjp(float ax, float ay, float rad, float pb
     aby = pby;
     rb = 0.f;
   }
+}
+
+// box projection p_j = clamp(a_j, -rad, rad): a clamped component passes nothing back to
+// a and its sign to rad
+__device__ __forceinline__ void box_vjp(float ax, float ay, float rad, float pbx, float pby,
+                                        float &abx, float &aby, float &rb) {
+  const bool cx = fabsf(ax) > rad, cy = fabsf(ay) > rad;
+  abx = cx ? 0.f : pbx;
+  aby = cy ? 0.f : pby;
+  rb = (cx ? (ax > 0.f ? pbx : -pbx) : 0.f) + (cy ? (ay > 0.f ? pby : -pby) : 0.f);
 }
 
 // Quadratic piece a/2 (t-c)^2 on [g0, g1]; decisions as in proj_quad. Outputs the input
@@ -390,9 +401,12 @@ __global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
       const float pbx = cu.bpx + (hr ? -tau_r * cu.bur - Ku : 0.f);
       const float pby = cu.bpy + (hd ? -tau_d * cu.bud - Ku : 0.f);
       suf_ks += hi * Ks;
-      // step 3: ball
+      // step 3: projection onto K (disc or box)
       float abx, aby, rb;
-      ball_vjp(ax, ay, A.lam * hi, pbx, pby, abx, aby, rb);
+      if (A.aniso)
+        box_vjp(ax, ay, A.lam * hi, pbx, pby, abx, aby, rb);
+      else
+        ball_vjp(ax, ay, A.lam * hi, pbx, pby, abx, aby, rb);
       lb_acc += hi * rb;
       // step 4: epigraph, in the coordinates shifted by the additive linear term
       float y = v0 * ih, w = z0 * ih;

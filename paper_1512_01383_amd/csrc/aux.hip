@@ -4,7 +4,8 @@
 //   * an upper bound of the relaxed optimum from two feasible primal points of the
 //     split problem (the primal objective is finite iff w = -h s lies on the probability
 //     simplex and u_i lies in [sum_{j>i} w_j, sum_{j>=i} w_j]; it then equals
-//     sum_i w_i rho_i^{**}(gamma_i + h_i alpha_i) + lambda sum_i h_i |grad u_i|):
+//     sum_i w_i rho_i^{**}(gamma_i + h_i alpha_i) + lambda sum_i h_i |grad u_i|, with the
+//     l2 norm, or the l1 norm for the anisotropic TV):
 //       (a) w = simplex projection of -h s, u clamped into its ranges;
 //       (b) the graph lifting of the back-projected u (w = indicator of its interval);
 //   * a lower bound from the dual: with p projected onto K and v = div p, the best q is
@@ -184,11 +185,21 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
   }
 }
 
+// norm of the regulariser: l2 (isotropic TV) or l1 (anisotropic TV)
+__device__ __forceinline__ double tv_norm(const IterArgs &A, double gx, double gy) {
+  return A.aniso ? fabs(gx) + fabs(gy) : sqrt(gx * gx + gy * gy);
+}
+
 template <typename DT>
 __device__ void proj_p(const IterArgs &A, const DT *p, int i, long long x, double rad, double &px,
                        double &py) {
   px = ldv(p, i * A.ps + x);
   py = ldv(p, (A.k + i) * A.ps + x);
+  if (A.aniso) {   // l-inf box
+    px = fmin(fmax(px, -rad), rad);
+    py = fmin(fmax(py, -rad), rad);
+    return;
+  }
   const double n2 = px * px + py * py;
   if (n2 > rad * rad) {
     const double f = rad / sqrt(n2);
@@ -390,18 +401,18 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
       double u0 = mu[i * A.ps + x];
       double gx = hx ? mu[i * A.ps + x + 1] - u0 : 0.0;
       double gy = hy ? mu[i * A.ps + x + A.W] - u0 : 0.0;
-      tr += D.h[i] * sqrt(gx * gx + gy * gy);
+      tr += D.h[i] * tv_norm(A, gx, gy);
       double g0 = D.gam[i], ih = 1.0 / D.h[i];
       double l0 = fmin(fmax((b[x] - g0) * ih, 0.0), 1.0);
       double lx = hx ? fmin(fmax((b[x + 1] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
       double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
-      tg += D.h[i] * sqrt(lx * lx + ly * ly);
+      tg += D.h[i] * tv_norm(A, lx, ly);
     }
     vals[0] = tr;
     vals[1] = tg;
     if (t == 0) {
       double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
-      vals[2] = sqrt(bx * bx + by * by);
+      vals[2] = tv_norm(A, bx, by);
     }
   }
   block_sum(vals, 3, M.part2 + (long long)blockIdx.x * SLI_NMON);

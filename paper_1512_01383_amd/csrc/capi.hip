@@ -118,8 +118,7 @@ sl_status validate(const sl_problem_desc *d) {
     return fail(SL_ERR_INVALID_ARG, "lambda must be finite and >= 0");
   if (d->rho != SL_RHO_QUAD && d->rho != SL_RHO_TRUNC_QUAD && d->rho != SL_RHO_SAMPLED)
     return fail(SL_ERR_INVALID_ARG, "unknown data-term kind %d", (int)d->rho);
-  if (d->tv == SL_TV_ANISO) return fail(SL_ERR_UNSUPPORTED, "anisotropic TV is not built");
-  if (d->tv != SL_TV_ISO) return fail(SL_ERR_INVALID_ARG, "unknown TV kind");
+  if (d->tv != SL_TV_ISO && d->tv != SL_TV_ANISO) return fail(SL_ERR_INVALID_ARG, "unknown TV kind");
   if (d->storage != SL_STORE_FP32 && d->storage != SL_STORE_BF16_DUAL)
     return fail(SL_ERR_INVALID_ARG, "unknown storage kind");
   if (d->check_every < 0) return fail(SL_ERR_INVALID_ARG, "check_every must be >= 0");
@@ -266,6 +265,7 @@ void fill_args(sl_problem_ *P) {
   D.a = d->rho != SL_RHO_SAMPLED ? d->a * P->scale * P->scale : 0.0;
   D.nu = d->nu;
   A.lam = (float)P->lam;
+  A.aniso = d->tv == SL_TV_ANISO ? 1 : 0;
   // diagonal preconditioning: inverse absolute row / column sums of the operator, the dual
   // steps scaled by the balance c and the primal ones by 1/c (c = 1: the plain choice)
   const double cb = P->step_c;
@@ -523,10 +523,13 @@ BatchLaunch batch_launch(sl_problem_ *P, int phase) {
   L.args = P->args_dev;
   L.phase = phase;
   L.kmax = P->kmax;
+  L.tvk = SLI_TV_DISC;
+  for (size_t i = 0; i < P->sub.size(); i++)
+    if (P->sub[i]->A.aniso) L.tvk = SLI_TV_PER_PROBLEM;
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, P->bf16, P->cfg, P->kmax));
+  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, P->bf16, P->cfg, P->kmax, L.tvk));
   long long total = 0;
   for (size_t i = 0; i < P->sub.size(); i++) total += batch_tiles(P->sub[i], kIterCfg[P->cfg][1]);
   L.grid = (int)std::max(1LL, std::min((long long)occ * ncu, total));

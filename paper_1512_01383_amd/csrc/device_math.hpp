@@ -88,6 +88,21 @@ __device__ __forceinline__ void ball(float &px, float &py, float rad) {
   py *= f;
 }
 
+// The anisotropic TV (l1 norm of the gradient, Sec. 5 on Zach and Kohli: Props. 4 and 5
+// hold for any convex one-homogeneous norm) has the l-inf box as its dual set: clamp each
+// component.
+__device__ __forceinline__ void box(float &px, float &py, float rad) {
+  px = fminf(fmaxf(px, -rad), rad);
+  py = fminf(fmaxf(py, -rad), rad);
+}
+
+__device__ __forceinline__ void proj_K(float &px, float &py, float rad, bool aniso) {
+  if (aniso)
+    box(px, py, rad);
+  else
+    ball(px, py, rad);
+}
+
 // ---------------------------------------------------------------- quadratic pieces
 //
 // Piece rho_i(t) = a/2 (t - c)^2 on [g0, g1]. Its conjugate is the line of slope g0 for

@@ -25,6 +25,9 @@
 #define SLI_NMON 8    // monitor sums
 
 enum { SLI_QUAD = 0, SLI_TRUNC = 1, SLI_SAMPLED = 2 };
+// projection onto K in a fused-iteration kernel variant: l2 discs (isotropic TV), l-inf boxes
+// (anisotropic TV), or per problem from IterArgs::aniso (batches that mix both)
+enum { SLI_TV_DISC = 0, SLI_TV_BOX = 1, SLI_TV_PER_PROBLEM = 2 };
 
 // Scalars and per-label tables of one problem (passed by value as kernel argument).
 struct IterArgs {
@@ -41,6 +44,7 @@ struct IterArgs {
   float ig0[SLI_MAXK];    // 1 / (1 + gamma_i^2)
   float ig1[SLI_MAXK];    // 1 / (1 + gamma_{i+1}^2)
   int sidx[SLI_MAXK + 1]; // sample index of every label (SAMPLED)
+  int aniso;              // 1: anisotropic TV (K is a product of l-inf boxes), 0: l2 discs
 };
 
 template <typename DT>
@@ -81,10 +85,11 @@ struct BatchLaunch {
   const void *ptrs;
   const IterArgs *args;
   int phase, grid, kmax;
+  int tvk;                // SLI_TV_DISC if every member uses the isotropic TV, else PER_PROBLEM
 };
 hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
                              hipStream_t st);
-int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax);  // blocks per CU
+int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax, int tvk);  // blocks per CU
 size_t pdhg_iter_lds_bytes(int k, int tile_rows);   // dynamic LDS
 size_t pdhg_iter_static_lds(int cfg);
 

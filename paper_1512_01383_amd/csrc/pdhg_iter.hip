@@ -49,16 +49,20 @@ __device__ __forceinline__ float from_left(float x, float first) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, first),
                                                                __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
 }
-// p <- Proj_{|.| <= rad}(p + sigma_p (gx, gy)): one expression wherever a p is formed, so
-// that a p recomputed for a neighbour is bitwise the one its owner stores
-__device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx, float gy, float rad) {
+// p <- Proj_K(p + sigma_p (gx, gy)), K the disc or box of radius rad: one expression
+// wherever a p is formed, so that a p recomputed for a neighbour is bitwise the one its
+// owner stores
+__device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx, float gy, float rad,
+                                       bool aniso) {
   px = px + spg * gx;
   py = py + spg * gy;
-  ball(px, py, rad);
+  proj_K(px, py, rad, aniso);
 }
 
-// One iteration on one tile of one problem (all labels of its pixels).
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+// One iteration on one tile of one problem (all labels of its pixels). TVK selects the
+// projection onto K (SLI_TV_*): fixed at compile time for a lone problem, read from the
+// problem's parameters in a batch that mixes both kinds.
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs &A, int tile,
                                           float *dyn) {
   constexpr int NP = TW * TH;   // pixels of a tile = threads of a label group
@@ -269,6 +273,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     load_step(i + 1, nx);
     const float rad = A.lam * A.h[i];
     const float spg = A.sig_p;
+    const bool aniso = TVK == SLI_TV_PER_PROBLEM ? A.aniso != 0 : TVK == SLI_TV_BOX;
     const float ub = 2.f * cu.u - cu.up;
     const float ubu = 2.f * cu.uu - cu.uup;
     const float ubd = 2.f * cu.ud - cu.udp;
@@ -278,13 +283,13 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     const float ubr = from_right(ub, ubR), ubur = from_right(ubu, ubRu);
     // own p
     float px = cu.px, py = cu.py;
-    p_step(px, py, spg, (c < W - 1) ? ubr - ub : 0.f, (r < H - 1) ? ubd - ub : 0.f, rad);
+    p_step(px, py, spg, (c < W - 1) ? ubr - ub : 0.f, (r < H - 1) ? ubd - ub : 0.f, rad, aniso);
     // p of the row above (only its y part enters div p)
     float pxu = cu.pxu, pyu = cu.pyu;
-    p_step(pxu, pyu, spg, (c < W - 1) ? ubur - ubu : 0.f, ub - ubu, rad);
+    p_step(pxu, pyu, spg, (c < W - 1) ? ubur - ubu : 0.f, ub - ubu, rad, aniso);
     // p at (r, c0-1) for lane 0's left neighbour (only its x part enters div p)
     float pxL = rdlane(cu.epx, 0), pyL = rdlane(cu.epy, 0);
-    p_step(pxL, pyL, spg, rdlane(ub, 0) - ubL, (r < H - 1) ? ubLd - ubL : 0.f, rad);
+    p_step(pxL, pyL, spg, rdlane(ub, 0) - ubL, (r < H - 1) ? ubLd - ubL : 0.f, rad, aniso);
     const float pxl = from_left(px, pxL);
 
     // lanes outside the image and steps past the chunk store nothing
@@ -374,7 +379,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   if (grp == 0) bst(P.qd, nb4, xm, qn);
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, IterArgs A) {
   extern __shared__ float dyn[];
   // XCD-aware tile order: blocks b, b+8, b+16, ... run on one XCD; give it a contiguous run
@@ -382,12 +387,12 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
   const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
   const int per = nb >> 3, rem = nb & 7;
   const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-  iter_tile<PIECE, ADD, DT, G, TH>(P, A, tile, dyn);
+  iter_tile<PIECE, ADD, DT, G, TH, TVK>(P, A, tile, dyn);
 }
 
 // Batched iteration: persistent blocks pull (instance, tile) work items from a counter.
 // Per-instance pointers (one set per rotation phase) and parameters come from device tables.
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     const BatchItem *__restrict__ items, const int *__restrict__ count, int *counter,
     const IterPtrs<DT> *__restrict__ ptrs, const IterArgs *__restrict__ args, int phase) {
@@ -402,35 +407,35 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     if (it >= n) return;
     const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
     const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
-    iter_tile<PIECE, ADD, DT, G, TH>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
+    iter_tile<PIECE, ADD, DT, G, TH, TVK>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
   }
 }
 
 __global__ void k_reset_counter(int *counter) { *counter = 0; }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
   const int ntc = (A.W + TW - 1) / TW, ntr = (A.H + TH - 1) / TH;
   const size_t lds = pdhg_iter_lds_bytes(A.k, TH);
   const IterPtrs<DT> &P = *static_cast<const IterPtrs<DT> *>(ptrs);
-  hipLaunchKernelGGL((pdhg_iter_kernel<PIECE, ADD, DT, G, TH>), dim3(ntc * ntr), dim3(64 * TH * G),
+  hipLaunchKernelGGL((pdhg_iter_kernel<PIECE, ADD, DT, G, TH, TVK>), dim3(ntc * ntr), dim3(64 * TH * G),
                      lds, st, P, A);
   return hipGetLastError();
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 hipError_t launch_bt(const BatchLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, L.counter);
-  hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH>), dim3(L.grid), dim3(64 * TH * G),
+  hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK>), dim3(L.grid), dim3(64 * TH * G),
                      pdhg_iter_lds_bytes(L.kmax, TH), st, L.items, L.count, L.counter,
                      (const IterPtrs<DT> *)L.ptrs, L.args, L.phase);
   return hipGetLastError();
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 int occ_t(int kmax) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pdhg_batch_kernel<PIECE, ADD, DT, G, TH>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK>,
                                                    64 * TH * G, pdhg_iter_lds_bytes(kmax, TH)) != hipSuccess)
     return 0;
   return nb;
@@ -438,33 +443,74 @@ int occ_t(int kmax) {
 
 #define SLI_DISPATCH_CFG(FN, ...)                                   \
   switch (cfg) {                                                     \
-    case 0: return FN<PIECE, ADD, DT, 1, 4>(__VA_ARGS__);            \
-    case 1: return FN<PIECE, ADD, DT, 1, 8>(__VA_ARGS__);            \
-    case 2: return FN<PIECE, ADD, DT, 2, 4>(__VA_ARGS__);            \
-    case 3: return FN<PIECE, ADD, DT, 2, 8>(__VA_ARGS__);            \
-    default: return FN<PIECE, ADD, DT, 4, 4>(__VA_ARGS__);           \
+    case 0: return FN<PIECE, ADD, DT, 1, 4, TVK>(__VA_ARGS__);            \
+    case 1: return FN<PIECE, ADD, DT, 1, 8, TVK>(__VA_ARGS__);            \
+    case 2: return FN<PIECE, ADD, DT, 2, 4, TVK>(__VA_ARGS__);            \
+    case 3: return FN<PIECE, ADD, DT, 2, 8, TVK>(__VA_ARGS__);            \
+    default: return FN<PIECE, ADD, DT, 4, 4, TVK>(__VA_ARGS__);           \
   }
 
-template <int PIECE, bool ADD, typename DT>
+template <int PIECE, bool ADD, typename DT, int TVK>
 hipError_t launch_bg(int cfg, const BatchLaunch &L, hipStream_t st) { SLI_DISPATCH_CFG(launch_bt, L, st) }
-template <int PIECE, bool ADD, typename DT>
+template <int PIECE, bool ADD, typename DT, int TVK>
 int occ_g(int cfg, int kmax) { SLI_DISPATCH_CFG(occ_t, kmax) }
 
-template <int PIECE, bool ADD, typename DT>
+template <int PIECE, bool ADD, typename DT, int TVK>
 hipError_t launch_g(int cfg, const IterArgs &A, const void *ptrs, hipStream_t st) {
   switch (cfg) {
-    case 0: return launch_t<PIECE, ADD, DT, 1, 4>(A, ptrs, st);
-    case 1: return launch_t<PIECE, ADD, DT, 1, 8>(A, ptrs, st);
-    case 2: return launch_t<PIECE, ADD, DT, 2, 4>(A, ptrs, st);
-    case 3: return launch_t<PIECE, ADD, DT, 2, 8>(A, ptrs, st);
-    default: return launch_t<PIECE, ADD, DT, 4, 4>(A, ptrs, st);
+    case 0: return launch_t<PIECE, ADD, DT, 1, 4, TVK>(A, ptrs, st);
+    case 1: return launch_t<PIECE, ADD, DT, 1, 8, TVK>(A, ptrs, st);
+    case 2: return launch_t<PIECE, ADD, DT, 2, 4, TVK>(A, ptrs, st);
+    case 3: return launch_t<PIECE, ADD, DT, 2, 8, TVK>(A, ptrs, st);
+    default: return launch_t<PIECE, ADD, DT, 4, 4, TVK>(A, ptrs, st);
   }
 }
 
-template <int PIECE, bool ADD>
+template <int PIECE, bool ADD, int TVK>
 hipError_t launch_d(bool bf16, int cfg, const IterArgs &A, const void *ptrs, hipStream_t st) {
-  if (bf16) return launch_g<PIECE, ADD, uint16_t>(cfg, A, ptrs, st);
-  return launch_g<PIECE, ADD, float>(cfg, A, ptrs, st);
+  if (bf16) return launch_g<PIECE, ADD, uint16_t, TVK>(cfg, A, ptrs, st);
+  return launch_g<PIECE, ADD, float, TVK>(cfg, A, ptrs, st);
+}
+
+template <int TVK>
+hipError_t launch_p(int piece, bool add, bool bf16, int cfg, const IterArgs &A, const void *ptrs,
+                    hipStream_t st) {
+  switch (piece) {
+    case SLI_QUAD:
+      return add ? launch_d<SLI_QUAD, true, TVK>(bf16, cfg, A, ptrs, st)
+                 : launch_d<SLI_QUAD, false, TVK>(bf16, cfg, A, ptrs, st);
+    case SLI_TRUNC:
+      return add ? launch_d<SLI_TRUNC, true, TVK>(bf16, cfg, A, ptrs, st)
+                 : launch_d<SLI_TRUNC, false, TVK>(bf16, cfg, A, ptrs, st);
+    default:
+      return launch_d<SLI_SAMPLED, false, TVK>(bf16, cfg, A, ptrs, st);
+  }
+}
+
+template <int TVK>
+hipError_t launch_pb(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L, hipStream_t st) {
+  if (piece == SLI_QUAD) {
+    if (add) return bf16 ? launch_bg<SLI_QUAD, true, uint16_t, TVK>(cfg, L, st) : launch_bg<SLI_QUAD, true, float, TVK>(cfg, L, st);
+    return bf16 ? launch_bg<SLI_QUAD, false, uint16_t, TVK>(cfg, L, st) : launch_bg<SLI_QUAD, false, float, TVK>(cfg, L, st);
+  }
+  if (piece == SLI_TRUNC) {
+    if (add) return bf16 ? launch_bg<SLI_TRUNC, true, uint16_t, TVK>(cfg, L, st) : launch_bg<SLI_TRUNC, true, float, TVK>(cfg, L, st);
+    return bf16 ? launch_bg<SLI_TRUNC, false, uint16_t, TVK>(cfg, L, st) : launch_bg<SLI_TRUNC, false, float, TVK>(cfg, L, st);
+  }
+  return bf16 ? launch_bg<SLI_SAMPLED, false, uint16_t, TVK>(cfg, L, st) : launch_bg<SLI_SAMPLED, false, float, TVK>(cfg, L, st);
+}
+
+template <int TVK>
+int occ_p(int piece, bool add, bool bf16, int cfg, int kmax) {
+  if (piece == SLI_QUAD) {
+    if (add) return bf16 ? occ_g<SLI_QUAD, true, uint16_t, TVK>(cfg, kmax) : occ_g<SLI_QUAD, true, float, TVK>(cfg, kmax);
+    return bf16 ? occ_g<SLI_QUAD, false, uint16_t, TVK>(cfg, kmax) : occ_g<SLI_QUAD, false, float, TVK>(cfg, kmax);
+  }
+  if (piece == SLI_TRUNC) {
+    if (add) return bf16 ? occ_g<SLI_TRUNC, true, uint16_t, TVK>(cfg, kmax) : occ_g<SLI_TRUNC, true, float, TVK>(cfg, kmax);
+    return bf16 ? occ_g<SLI_TRUNC, false, uint16_t, TVK>(cfg, kmax) : occ_g<SLI_TRUNC, false, float, TVK>(cfg, kmax);
+  }
+  return bf16 ? occ_g<SLI_SAMPLED, false, uint16_t, TVK>(cfg, kmax) : occ_g<SLI_SAMPLED, false, float, TVK>(cfg, kmax);
 }
 
 }  // namespace
@@ -481,39 +527,17 @@ size_t pdhg_iter_static_lds(int cfg) {
 
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
                             const void *ptrs, hipStream_t st) {
-  switch (piece) {
-    case SLI_QUAD:
-      return add ? launch_d<SLI_QUAD, true>(bf16, cfg, A, ptrs, st)
-                 : launch_d<SLI_QUAD, false>(bf16, cfg, A, ptrs, st);
-    case SLI_TRUNC:
-      return add ? launch_d<SLI_TRUNC, true>(bf16, cfg, A, ptrs, st)
-                 : launch_d<SLI_TRUNC, false>(bf16, cfg, A, ptrs, st);
-    default:
-      return launch_d<SLI_SAMPLED, false>(bf16, cfg, A, ptrs, st);
-  }
+  return A.aniso ? launch_p<SLI_TV_BOX>(piece, add, bf16, cfg, A, ptrs, st)
+                 : launch_p<SLI_TV_DISC>(piece, add, bf16, cfg, A, ptrs, st);
 }
 
 hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
                              hipStream_t st) {
-  if (piece == SLI_QUAD) {
-    if (add) return bf16 ? launch_bg<SLI_QUAD, true, uint16_t>(cfg, L, st) : launch_bg<SLI_QUAD, true, float>(cfg, L, st);
-    return bf16 ? launch_bg<SLI_QUAD, false, uint16_t>(cfg, L, st) : launch_bg<SLI_QUAD, false, float>(cfg, L, st);
-  }
-  if (piece == SLI_TRUNC) {
-    if (add) return bf16 ? launch_bg<SLI_TRUNC, true, uint16_t>(cfg, L, st) : launch_bg<SLI_TRUNC, true, float>(cfg, L, st);
-    return bf16 ? launch_bg<SLI_TRUNC, false, uint16_t>(cfg, L, st) : launch_bg<SLI_TRUNC, false, float>(cfg, L, st);
-  }
-  return bf16 ? launch_bg<SLI_SAMPLED, false, uint16_t>(cfg, L, st) : launch_bg<SLI_SAMPLED, false, float>(cfg, L, st);
+  return L.tvk == SLI_TV_DISC ? launch_pb<SLI_TV_DISC>(piece, add, bf16, cfg, L, st)
+                              : launch_pb<SLI_TV_PER_PROBLEM>(piece, add, bf16, cfg, L, st);
 }
 
-int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax) {
-  if (piece == SLI_QUAD) {
-    if (add) return bf16 ? occ_g<SLI_QUAD, true, uint16_t>(cfg, kmax) : occ_g<SLI_QUAD, true, float>(cfg, kmax);
-    return bf16 ? occ_g<SLI_QUAD, false, uint16_t>(cfg, kmax) : occ_g<SLI_QUAD, false, float>(cfg, kmax);
-  }
-  if (piece == SLI_TRUNC) {
-    if (add) return bf16 ? occ_g<SLI_TRUNC, true, uint16_t>(cfg, kmax) : occ_g<SLI_TRUNC, true, float>(cfg, kmax);
-    return bf16 ? occ_g<SLI_TRUNC, false, uint16_t>(cfg, kmax) : occ_g<SLI_TRUNC, false, float>(cfg, kmax);
-  }
-  return bf16 ? occ_g<SLI_SAMPLED, false, uint16_t>(cfg, kmax) : occ_g<SLI_SAMPLED, false, float>(cfg, kmax);
+int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax, int tvk) {
+  return tvk == SLI_TV_DISC ? occ_p<SLI_TV_DISC>(piece, add, bf16, cfg, kmax)
+                            : occ_p<SLI_TV_PER_PROBLEM>(piece, add, bf16, cfg, kmax);
 }

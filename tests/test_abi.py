@@ -105,7 +105,9 @@ def test_argument_checks(lib, S):
     assert status(d) == 1
     d = _desc(S)
     d.tv = S.TV_ANISO
-    assert status(d) == 2
+    assert status(d) == 0
+    d.tv = 2
+    assert status(d) == 1 and "TV kind" in lib.sl_last_error().decode()
     # H*W = 2^29: one FP32 plane would reach 2 GiB
     assert status(_desc(S, H=1 << 15, W=1 << 14)) == 2
     assert "2^29" in lib.sl_last_error().decode()
