@@ -202,3 +202,17 @@ def test_invalid_arguments_rejected(orc):
     for wl in bad:
         with pytest.raises(ValueError):
             orc.Problem(wl)
+
+
+def test_proposed_relaxation_below_baseline_lifting(orc):
+    """At the same labels the proposed pieces (convex envelopes of rho on each interval)
+    lie below the baseline's chords between the labels (a convex function on an interval
+    lies below its chord, and the envelope meets rho at the interval ends), so the
+    proposed relaxed optimum is at most the baseline's (Sec. 5, Prop. 2)."""
+    for L in (3, 5):
+        tq = W.truncated_quadratic(L=L, H=10, W=12, seed=44)
+        rp, _ = _run_to(orc.Problem(tq), 2e-4, 80000)
+        rb, _ = _run_to(orc.Problem(W.baseline_lifting(tq)), 1e-9, 80000)
+        assert rp["rel_gap"] <= 2e-4 and rb["rel_gap"] <= 1e-9
+        # certified: the proposed upper bound is below the baseline's lower bound
+        assert rp["best_primal"] < rb["best_dual"]

@@ -227,6 +227,18 @@ def roofline(seed: int = 6, H: int = 2048, W: int = 2048, L: int = 16,
     return w
 
 
+def baseline_lifting(wl: Workload) -> Workload:
+    """The comparison method of Sec. 5 as a special case (Prop. 2): the data term of a
+    quadratic or truncated-quadratic workload given only at its labels (samples at tau ==
+    gamma), so every interval's convex piece is the chord between its end labels."""
+    f = wl.f.astype(np.float64)
+    rho = 0.5 * wl.a * (wl.gamma[:, None, None] - f[None]) ** 2
+    if wl.rho == TRUNC_QUAD:
+        rho = np.minimum(rho, wl.nu)
+    return Workload(wl.name + "_baseline", wl.H, wl.W, wl.gamma.copy(), SAMPLED, wl.lam,
+                    tau=wl.gamma.copy(), samples=rho.astype(np.float32), tv=wl.tv)
+
+
 def random_state(seed: int, k: int, H: int, W: int, scale: float = 1.0) -> dict:
     """Random iteration state (float32) for single-step parity tests. Plane order and
     shapes follow the documented state layout: u, u_prev, s, s_prev, v, z: [k][H][W];
