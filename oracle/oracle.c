@@ -337,6 +337,16 @@ static void get_piece(const or_problem *P, int64_t x, int i, piece *pc) {
     pc->a = P->a;
     pc->c = P->c[x];
     pc->d = 0.0;
+  } else if (P->rho == OR_PERIODIC_QUAD) {
+    /* the branch f + m nu whose centre is nearest the interval's midpoint; m is decided in
+     * float (same as the GPU path), the centre is then formed in double */
+    float g0f = (float)pc->g0, g1f = (float)pc->g1;
+    float iperf = (float)(P->scale / P->nu);
+    float m = rintf((0.5f * (g0f + g1f) - P->cf[x]) * iperf);
+    pc->kind = OR_PIECE_QUAD;
+    pc->a = P->a;
+    pc->c = P->c[x] + (double)m * (P->nu / P->scale);
+    pc->d = 0.0;
   } else if (P->rho == OR_TRUNC_QUAD) {
     /* classification of the interval against the band |t - f| <= sqrt(2 nu / a) where the
      * quadratic is below its truncation; decided in float (same as the GPU path) */
@@ -442,6 +452,12 @@ static double rho_true(const or_problem *P, int64_t x, double t) {
     while (m < P->M - 2 && t > P->taun[m + 1]) m++;
     double al = (t - P->taun[m]) / (P->taun[m + 1] - P->taun[m]);
     v = (1.0 - al) * P->cost[(int64_t)m * P->N + x] + al * P->cost[(int64_t)(m + 1) * P->N + x];
+  } else if (P->rho == OR_PERIODIC_QUAD) {
+    /* squared distance on the circle of circumference nu (normalised units) */
+    double per = P->nu / P->scale;
+    double r = fmod(fabs(t - P->c[x]), per);
+    double d = r < per - r ? r : per - r;
+    v = 0.5 * P->a * d * d;
   } else {
     v = 0.5 * P->a * (t - P->c[x]) * (t - P->c[x]);
     if (P->rho == OR_TRUNC_QUAD && v > P->nu) v = P->nu;
@@ -552,7 +568,7 @@ or_problem *or_create(const or_desc *d) {
     if (!isfinite(d->gamma[j]) || (j > 0 && !(d->gamma[j] > d->gamma[j - 1])))
       FAIL("gamma must be finite and strictly increasing");
   if (!(d->lambda >= 0.0) || !isfinite(d->lambda)) FAIL("lambda must be finite and >= 0");
-  if (d->rho < OR_QUAD || d->rho > OR_SAMPLED) FAIL("unknown data term kind");
+  if (d->rho < OR_QUAD || d->rho > OR_PERIODIC_QUAD) FAIL("unknown data term kind");
   P->H = d->H;
   P->W = d->W;
   P->L = d->L;
@@ -570,10 +586,11 @@ or_problem *or_create(const or_desc *d) {
   P->lam = d->lambda * P->scale;
   if (d->tv != OR_TV_ISO && d->tv != OR_TV_ANISO) FAIL("unknown TV kind");
   P->tv = d->tv;
-  if (d->rho == OR_QUAD || d->rho == OR_TRUNC_QUAD) {
+  if (d->rho != OR_SAMPLED) {
     if (!d->f || !finite_f(d->f, N)) FAIL("f must be given and finite");
     if (!(d->a > 0.0) || !isfinite(d->a)) FAIL("a must be > 0");
-    if (d->rho == OR_TRUNC_QUAD && (!(d->nu > 0.0) || !isfinite(d->nu))) FAIL("nu must be > 0");
+    if ((d->rho == OR_TRUNC_QUAD || d->rho == OR_PERIODIC_QUAD) && (!(d->nu > 0.0) || !isfinite(d->nu)))
+      FAIL("nu must be > 0");
     P->a = d->a * P->scale * P->scale;
     P->nu = d->nu;
     P->n_sub = d->n_sub > 0 ? d->n_sub : 16;

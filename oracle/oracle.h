@@ -20,7 +20,10 @@
 extern "C" {
 #endif
 
-enum { OR_QUAD = 0, OR_TRUNC_QUAD = 1, OR_SAMPLED = 2 };
+/* OR_PERIODIC_QUAD: rho = a/2 d(t, f)^2 with d the distance on a circle of circumference
+ * nu (phase unwrapping, Sec. 5); on each interval the quadratic branch a/2 (t - f - m nu)^2
+ * whose centre lies nearest the interval's midpoint (m decided in float) */
+enum { OR_QUAD = 0, OR_TRUNC_QUAD = 1, OR_SAMPLED = 2, OR_PERIODIC_QUAD = 3 };
 enum { OR_PIECE_QUAD = 0, OR_PIECE_PL = 1 };
 /* regulariser: isotropic TV (l2 norm of the gradient, Prop. 5: K is a product of l2
  * balls) or anisotropic TV (l1 norm, Sec. 5, comparison with Zach and Kohli: Props. 4
@@ -30,9 +33,10 @@ enum { OR_TV_ISO = 0, OR_TV_ANISO = 1 };
 typedef struct {
   int32_t H, W, L;          /* image size, number of labels (L >= 2)                 */
   const double *gamma;      /* [L] strictly increasing labels                          */
-  int32_t rho;              /* OR_QUAD, OR_TRUNC_QUAD or OR_SAMPLED                    */
+  int32_t rho;              /* OR_QUAD, OR_TRUNC_QUAD, OR_SAMPLED or OR_PERIODIC_QUAD  */
   const float *f;           /* [H*W] data image (QUAD / TRUNC_QUAD)                    */
-  double a, nu;             /* rho = a/2 (t-f)^2, truncated at nu (TRUNC_QUAD)          */
+  double a, nu;             /* rho = a/2 (t-f)^2, truncated at nu (TRUNC_QUAD); nu is the
+                               period of PERIODIC_QUAD                                 */
   int32_t M;                /* number of sample positions                              */
   const double *tau;        /* [M] sample positions; every label must be one of them   */
   const float *samples;     /* [M][H*W]: SAMPLED costs, or (QUAD/TRUNC, M == L)

@@ -8,7 +8,8 @@ oracle and the HIP path can consume it without sharing any code of the method.
 The paper's own inputs (the ROF / truncated-quadratic test images, Middlebury stereo
 pairs, SAR phase data, the focal stack) are not available, so every workload below is
 a synthetic stand-in with the shape and value distribution of the corresponding
-experiment (Sec. 5.1 ROF model, Sec. 5.2 robust truncated quadratic, Sec. 5.4 stereo).
+experiment (Sec. 5.1 ROF model, Sec. 5.2 robust truncated quadratic, Sec. 5.4 stereo,
+Sec. 5.5 phase unwrapping).
 All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
 """
 from __future__ import annotations
@@ -21,6 +22,7 @@ import numpy as np
 QUAD = 0
 TRUNC_QUAD = 1
 SAMPLED = 2
+PERIODIC_QUAD = 3       # a/2 d(t, f)^2, d the distance on a circle of circumference nu
 
 
 @dataclasses.dataclass
@@ -224,6 +226,22 @@ def roofline(seed: int = 6, H: int = 2048, W: int = 2048, L: int = 16,
     caches (bandwidth measurement)."""
     w = truncated_quadratic(L=L, seed=seed, H=H, W=W, lam=lam)
     w.name = f"tq{H}x{W}_L{L}"
+    return w
+
+
+def phase_unwrapping(seed: int = 7, H: int = 256, W: int = 256, L: int = 8,
+                     lam: float = 0.005, noise: float = 0.3) -> Workload:
+    """Phase unwrapping (Sec. 5.5 stand-in for the SAR data): a smooth phase surface in
+    [0.3 pi, 3.7 pi] (blobs image rescaled), observed wrapped to [0, 2 pi) after adding
+    N(0, noise^2); rho = d(t, f)^2 on the circle of circumference 2 pi (a = 2, nu = 2 pi),
+    labels equispaced on Gamma = [0, 4 pi], lambda = 0.005 as in the paper."""
+    rng = _rng(seed)
+    g = blobs_image(rng, H, W)
+    phase = np.pi * (0.3 + 3.4 * g)
+    f = np.mod(phase + rng.normal(0.0, noise, size=(H, W)), 2.0 * np.pi)
+    w = Workload(f"phase{H}x{W}_L{L}", H, W, equispaced(L, 0.0, 4.0 * np.pi), PERIODIC_QUAD, lam,
+                 f=f.astype(np.float32), a=2.0, nu=2.0 * np.pi)
+    w.target = phase.astype(np.float32)
     return w
 
 
