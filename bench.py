@@ -81,7 +81,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="tq", choices=["tq", "stereo", "batch", "diff", "labels"],
+    ap.add_argument("--workload", default="tq",
+                    choices=["tq", "stereo", "phase", "batch", "diff", "labels"],
                     help="tq: one truncated-quadratic instance (default); batch: 64 mixed "
                          "instances in one persistent launch per iteration; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
@@ -111,6 +112,8 @@ def main():
 
     if args.workload == "stereo":
         wl = W.stereo()            # sampled costs, 384x288, 64 disparities, L = 8
+    elif args.workload == "phase":
+        wl = W.phase_unwrapping(H=args.size, W=args.size)   # periodic quadratic, L = 8
     else:
         wl = W.truncated_quadratic(L=args.L, H=args.size, W=args.size)
     wl.tv = 1 if args.tv == "aniso" else 0
@@ -222,6 +225,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"sampled-cost stereo {wl.W}x{wl.H}, {wl.M} disparity samples, "
                                 f"L={wl.L}, lambda={wl.lam}" if args.workload == "stereo" else
+                                f"phase unwrapping {wl.H}x{wl.W}, periodic quadratic pieces on "
+                                f"[0, 4 pi], L={wl.L}, lambda={wl.lam}" if args.workload == "phase" else
                                 f"truncated-quadratic denoising {wl.H}x{wl.W}, L={wl.L}, "
                                 f"lambda={wl.lam}, nu=0.025") +
                                (", anisotropic TV" if wl.tv else "") +
@@ -229,7 +234,7 @@ def main():
                    "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage, "tv": args.tv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (None if args.workload == "stereo" else
+                     "traffic": (None if args.workload != "tq" else
                                  measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}"
                                                   + ("_aniso" if wl.tv else ""))),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,

@@ -58,8 +58,15 @@ typedef enum {
  *                    straddle a band edge use the convex envelope of 16 equispaced
  *                    samples of rho on the interval.
  *  SL_RHO_SAMPLED    rho given at sample positions tau_m (M planes of costs); on every
- *                    interval the convex envelope of its samples is used (Sec. 5.4). */
-typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2 } sl_rho_kind;
+ *                    interval the convex envelope of its samples is used (Sec. 5.4).
+ *  SL_RHO_PERIODIC_QUAD rho(x,t) = a/2 d(t, f(x))^2, d the distance on a circle of
+ *                    circumference nu (phase unwrapping, Sec. 5.5, where the energy is
+ *                    approximated by quadratic pieces): on each interval the branch
+ *                    a/2 (t - f(x) - m nu)^2 whose centre is nearest the interval's
+ *                    midpoint (m decided in float from the normalised f and labels);
+ *                    the reported nonconvex energy uses the true circular distance. */
+typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2,
+               SL_RHO_PERIODIC_QUAD = 3 } sl_rho_kind;
 
 /* TV kind. ISO: sum_x |grad u(x)|_2, K a product of l2 discs of radius lambda h_i
  * (Prop. 5). ANISO: sum_x |grad u(x)|_1; Props. 4 and 5 hold for any convex
@@ -77,9 +84,10 @@ typedef struct {
   int32_t H, W, L;         /* H, W >= 1, H*W < 2^29 (else UNSUPPORTED); 2 <= L <= SL_MAX_LABELS */
   const double *gamma;     /* HOST [L], finite, strictly increasing; copied               */
   sl_rho_kind rho;
-  const float *f;          /* DEVICE [H*W] data image (QUAD, TRUNC_QUAD); NULL for
+  const float *f;          /* DEVICE [H*W] data image (all but SAMPLED); NULL for
                               SAMPLED; read during sl_create only                          */
-  double a, nu;            /* a > 0 (QUAD, TRUNC_QUAD); nu > 0 (TRUNC_QUAD)                */
+  double a, nu;            /* a > 0 (all but SAMPLED); nu > 0: the truncation (TRUNC_QUAD)
+                              or the period (PERIODIC_QUAD)                               */
   int32_t M;               /* number of sample positions (0 if samples == NULL)           */
   const double *tau;       /* HOST [M] strictly increasing; every gamma_j must equal one
                               tau_m; copied                                                */

@@ -21,7 +21,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsublabel.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "sublabel.h")
 
-RHO_QUAD, RHO_TRUNC_QUAD, RHO_SAMPLED = 0, 1, 2
+RHO_QUAD, RHO_TRUNC_QUAD, RHO_SAMPLED, RHO_PERIODIC_QUAD = 0, 1, 2, 3
 TV_ISO, TV_ANISO = 0, 1
 STORE_FP32, STORE_BF16_DUAL = 0, 1
 

@@ -420,8 +420,9 @@ __global__ __launch_bounds__(64 * T) void k_adj_dual(AdjState X, AdjBuf B, AdjAc
       }
       const float yb = hi * vbt, wb = hi * zbt;
       float y0b, w0b, cb = 0.f;
-      if (PIECE == SLI_QUAD) {
-        quad_vjp(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w, yb, wb, y0b, w0b, cb);
+      if (PIECE == SLI_QUAD) {   // the centre's adjoint is the data centre's (m is locally constant)
+        quad_vjp(A.a, A.ia, piece_centre(fc, g0, g1, A.per, A.iper), g0, g1, A.ig0[i], A.ig1[i], y, w,
+                 yb, wb, y0b, w0b, cb);
       } else if (i == st0 || i == st1) {
         const int ml = i == st0 ? ml0 : ml1, mr = i == st0 ? mr0 : mr1;
         tq_chain_vjp(A.a, fc, A.nu, g0, g1, ml, mr, y, w, yb, wb, y0b, w0b, cb);

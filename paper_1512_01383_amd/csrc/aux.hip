@@ -154,6 +154,8 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
     P.c = ((double)M.f_orig[x] - D.shift) / D.scale;
     if (PIECE == SLI_QUAD) {
       P.kind = 0;
+      if (D.per > 0.0)   // periodic branch: m decided in float as in the iteration
+        P.c += D.per * (double)rintf((0.5f * (A.gam[i] + A.gam[i + 1]) - fc) * A.iper);
     } else {
       // classification decided in float, as in the iteration
       const float lo = fc - A.del, hb = fc + A.del;
@@ -369,7 +371,11 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
       const float *raw = M.cost + (long long)A.M * A.ps;
       e = (1.0 - a2) * raw[m * A.ps + x] + a2 * raw[(m + 1) * A.ps + x];
     } else {
-      const double d = tt - ((double)M.f_orig[x] - D.shift) / D.scale;
+      double d = tt - ((double)M.f_orig[x] - D.shift) / D.scale;
+      if (PIECE == SLI_QUAD && D.per > 0.0) {   // distance on the circle
+        const double r = fmod(fabs(d), D.per);
+        d = fmin(r, D.per - r);
+      }
       e = 0.5 * D.a * d * d;
       if (PIECE == SLI_TRUNC && e > D.nu) e = D.nu;
     }

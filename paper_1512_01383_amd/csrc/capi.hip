@@ -116,7 +116,8 @@ sl_status validate(const sl_problem_desc *d) {
   }
   if (!(d->lambda >= 0.0) || !isfinite(d->lambda))
     return fail(SL_ERR_INVALID_ARG, "lambda must be finite and >= 0");
-  if (d->rho != SL_RHO_QUAD && d->rho != SL_RHO_TRUNC_QUAD && d->rho != SL_RHO_SAMPLED)
+  if (d->rho != SL_RHO_QUAD && d->rho != SL_RHO_TRUNC_QUAD && d->rho != SL_RHO_SAMPLED &&
+      d->rho != SL_RHO_PERIODIC_QUAD)
     return fail(SL_ERR_INVALID_ARG, "unknown data-term kind %d", (int)d->rho);
   if (d->tv != SL_TV_ISO && d->tv != SL_TV_ANISO) return fail(SL_ERR_INVALID_ARG, "unknown TV kind");
   if (d->storage != SL_STORE_FP32 && d->storage != SL_STORE_BF16_DUAL)
@@ -129,7 +130,8 @@ sl_status validate(const sl_problem_desc *d) {
   if (d->rho != SL_RHO_SAMPLED) {
     if (!d->f) return fail(SL_ERR_INVALID_ARG, "f is NULL");
     if (!(d->a > 0.0) || !isfinite(d->a)) return fail(SL_ERR_INVALID_ARG, "a must be > 0");
-    if (d->rho == SL_RHO_TRUNC_QUAD && (!(d->nu > 0.0) || !isfinite(d->nu)))
+    if ((d->rho == SL_RHO_TRUNC_QUAD || d->rho == SL_RHO_PERIODIC_QUAD) &&
+        (!(d->nu > 0.0) || !isfinite(d->nu)))
       return fail(SL_ERR_INVALID_ARG, "nu must be > 0");
     if (d->samples) {
       if (d->M != d->L || !d->tau)
@@ -238,6 +240,12 @@ struct sl_problem_ {
 
 namespace {
 
+// kernel variant of a data-term kind (periodic pieces are quadratic pieces with a per-interval
+// centre, selected by IterArgs::per)
+int piece_of(sl_rho_kind rho) {
+  return rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : rho == SL_RHO_SAMPLED ? SLI_SAMPLED : SLI_QUAD;
+}
+
 // Iteration and monitor parameters from the problem description (labels and sample
 // positions from the copies kept in the handle; the caller's pointers are not kept).
 void fill_args(sl_problem_ *P) {
@@ -266,6 +274,8 @@ void fill_args(sl_problem_ *P) {
   D.nu = d->nu;
   A.lam = (float)P->lam;
   A.aniso = d->tv == SL_TV_ANISO ? 1 : 0;
+  A.per = A.iper = 0.f;
+  P->D.per = 0.0;
   // diagonal preconditioning: inverse absolute row / column sums of the operator, the dual
   // steps scaled by the balance c and the primal ones by 1/c (c = 1: the plain choice)
   const double cb = P->step_c;
@@ -287,6 +297,11 @@ void fill_args(sl_problem_ *P) {
     A.ia = (float)(1.0 / an);
     A.nu = (float)d->nu;
     A.del = d->rho == SL_RHO_TRUNC_QUAD ? (float)sqrt(2.0 * d->nu / an) : 0.f;
+    if (d->rho == SL_RHO_PERIODIC_QUAD) {   // the period in normalised label units
+      A.per = (float)(d->nu / P->scale);
+      A.iper = (float)(P->scale / d->nu);
+      P->D.per = d->nu / P->scale;
+    }
   } else {
     P->tau_host.resize(d->M);
     P->taud_host.resize(d->M);
@@ -857,7 +872,7 @@ static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes
   P->st = (hipStream_t)stream;
   P->nb_mon = nb_mon;
   P->bf16 = desc->storage == SL_STORE_BF16_DUAL;
-  P->piece = desc->rho == SL_RHO_QUAD ? SLI_QUAD : desc->rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : SLI_SAMPLED;
+  P->piece = piece_of(desc->rho);
   P->add = desc->rho != SL_RHO_SAMPLED && desc->samples != nullptr;
   P->check_every = desc->check_every > 0 ? desc->check_every : 50;
   P->gamma_in.assign(desc->gamma, desc->gamma + desc->L);
@@ -1046,7 +1061,7 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->d = descs[0];
   B->st = (hipStream_t)stream;
   B->bf16 = descs[0].storage == SL_STORE_BF16_DUAL;
-  B->piece = descs[0].rho == SL_RHO_QUAD ? SLI_QUAD : descs[0].rho == SL_RHO_TRUNC_QUAD ? SLI_TRUNC : SLI_SAMPLED;
+  B->piece = piece_of(descs[0].rho);
   B->add = descs[0].rho != SL_RHO_SAMPLED && descs[0].samples != nullptr;
   B->check_every = descs[0].check_every > 0 ? descs[0].check_every : 48;
   char *base = (char *)ws;

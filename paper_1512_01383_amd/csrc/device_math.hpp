@@ -104,6 +104,13 @@ __device__ __forceinline__ void proj_K(float &px, float &py, float rad, bool ani
 }
 
 // ---------------------------------------------------------------- quadratic pieces
+
+// Centre of the quadratic piece on [g0, g1]: the data centre fc, or for periodic pieces the
+// branch fc + m per nearest the interval's midpoint (m decided in float).
+__device__ __forceinline__ float piece_centre(float fc, float g0, float g1, float per, float iper) {
+  if (per > 0.f) return fc + per * rintf((0.5f * (g0 + g1) - fc) * iper);
+  return fc;
+}
 //
 // Piece rho_i(t) = a/2 (t - c)^2 on [g0, g1]. Its conjugate is the line of slope g0 for
 // y <= a(g0 - c), the parabola c y + y^2/(2a) in between and the line of slope g1 beyond.

@@ -45,6 +45,7 @@ struct IterArgs {
   float ig1[SLI_MAXK];    // 1 / (1 + gamma_{i+1}^2)
   int sidx[SLI_MAXK + 1]; // sample index of every label (SAMPLED)
   int aniso;              // 1: anisotropic TV (K is a product of l-inf boxes), 0: l2 discs
+  float per, iper;        // period of periodic quadratic pieces (normalised) and its inverse; 0: none
 };
 
 template <typename DT>
@@ -99,6 +100,7 @@ struct MonArgs {
   double gam[SLI_MAXK + 1];
   double h[SLI_MAXK];
   double a, nu, shift, scale, lam;
+  double per;             // period of periodic quadratic pieces (normalised); 0: none
 };
 
 struct MonPtrs {

@@ -324,7 +324,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
         w -= cs;
       }
       if (PIECE == SLI_QUAD) {
-        proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
+        proj_quad(A.a, A.ia, piece_centre(fc, g0, g1, A.per, A.iper), g0, g1, A.ig0[i], A.ig1[i], y, w);
       } else if (PIECE == SLI_TRUNC) {
         // not straddling: inside the band (quadratic) or outside it (constant nu)
         if (fc - A.del <= g0 && g1 <= fc + A.del)

@@ -103,6 +103,11 @@ def test_argument_checks(lib, S):
     d = _desc(S, rho=S.RHO_TRUNC_QUAD)
     d.nu = 0.0
     assert status(d) == 1
+    d = _desc(S, rho=S.RHO_PERIODIC_QUAD)
+    assert status(d) == 0
+    d.nu = 0.0
+    assert status(d) == 1 and "nu" in lib.sl_last_error().decode()
+    assert status(_desc(S, rho=4)) == 1
     d = _desc(S)
     d.tv = S.TV_ANISO
     assert status(d) == 0
