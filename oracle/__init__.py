@@ -94,6 +94,8 @@ def lib():
         L.or_proj_simplex.argtypes = [C.c_int, _dp, _dp]
         L.or_proj_ball.argtypes = [_dp, _dp, C.c_double]
         L.or_proj_box.argtypes = [_dp, _dp, C.c_double]
+        L.or_stereo_costs.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_float),
+                                      C.POINTER(C.c_float), C.c_double, _dp]
         L.or_residual_norms.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.or_unrolled_forward.argtypes = [C.c_void_p, C.c_int]
         L.or_unrolled_backward.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
@@ -176,6 +178,18 @@ def proj_ball(px, py, radius):
     a, b = C.c_double(px), C.c_double(py)
     lib().or_proj_ball(C.byref(a), C.byref(b), radius)
     return a.value, b.value
+
+
+def stereo_costs(left, right, D: int, trunc: float):
+    """Matching costs [D][H][W] of a rectified pair (see or_stereo_costs)."""
+    left = np.ascontiguousarray(left, dtype=np.float32)
+    right = np.ascontiguousarray(right, dtype=np.float32)
+    H, W = left.shape
+    out = np.empty((D, H, W), np.float64)
+    fp = C.POINTER(C.c_float)
+    lib().or_stereo_costs(H, W, D, left.ctypes.data_as(fp), right.ctypes.data_as(fp),
+                          float(trunc), _p(out))
+    return out
 
 
 def proj_box(px, py, radius):

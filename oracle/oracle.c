@@ -97,6 +97,42 @@ void or_grad(int H, int W, const double *u, double *gx, double *gy) {
     }
 }
 
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+void or_stereo_costs(int H, int W, int D, const float *left, const float *right, double trunc,
+                     double *out) {
+  const int64_t N = (int64_t)H * W;
+  double *lx = (double *)malloc(sizeof(double) * N), *ly = (double *)malloc(sizeof(double) * N);
+  double *rx = (double *)malloc(sizeof(double) * N), *ry = (double *)malloc(sizeof(double) * N);
+  double *li = (double *)malloc(sizeof(double) * N), *ri = (double *)malloc(sizeof(double) * N);
+  for (int64_t x = 0; x < N; x++) {
+    li[x] = left[x];
+    ri[x] = right[x];
+  }
+  or_grad(H, W, li, lx, ly);
+  or_grad(H, W, ri, rx, ry);
+#pragma omp parallel for schedule(static)
+  for (int d = 0; d < D; d++)
+    for (int r = 0; r < H; r++)
+      for (int c = 0; c < W; c++) {
+        double acc = 0.0;
+        for (int i = -1; i <= 2; i++)
+          for (int j = -1; j <= 2; j++) {
+            int pr = clampi(r + i, 0, H - 1), pc = clampi(c + j, 0, W - 1);
+            int qc = clampi(pc - d, 0, W - 1);
+            int64_t p = (int64_t)pr * W + pc, q = (int64_t)pr * W + qc;
+            acc += fabs(lx[p] - rx[q]) + fabs(ly[p] - ry[q]);
+          }
+        out[(int64_t)d * N + (int64_t)r * W + c] = acc < trunc ? acc : trunc;
+      }
+  free(lx);
+  free(ly);
+  free(rx);
+  free(ry);
+  free(li);
+  free(ri);
+}
+
 void or_div(int H, int W, const double *px, const double *py, double *d) {
   for (int r = 0; r < H; r++)
     for (int c = 0; c < W; c++) {

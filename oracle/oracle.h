@@ -122,6 +122,14 @@ void or_proj_simplex(int n, const double *x, double *out);
 void or_proj_ball(double *px, double *py, double radius);
 void or_proj_box(double *px, double *py, double radius);
 
+/* matching costs of the stereo experiment (Sec. 5.4): for every pixel (r, c) and disparity
+ * d = 0..D-1, the sum over the 4x4 patch (r + i, c + j), i, j in {-1, 0, 1, 2} (coordinates
+ * clamped into the image) of |dx L(p) - dx R(p - d)| + |dy L(p) - dy R(p - d)|, truncated
+ * at trunc. dx, dy are forward differences (zero on the last column / row); p - d moves d
+ * columns to the left, clamped at column 0. left, right: [H*W]; out: [D][H*W]. */
+void or_stereo_costs(int H, int W, int D, const float *left, const float *right, double trunc,
+                     double *out);
+
 #ifdef __cplusplus
 }
 #endif

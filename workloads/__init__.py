@@ -50,6 +50,7 @@ class Workload:
     iters: int = 0                      # fixed iteration count of the workload (0: run to gap)
     target: Optional[np.ndarray] = None  # clean image (differentiation workload)
     tv: int = 0                         # 0: isotropic TV (l2), 1: anisotropic TV (l1)
+    pair: Optional[tuple] = None        # (left, right) [H][W] float32 images (stereo)
 
     @property
     def L(self) -> int:
@@ -187,6 +188,7 @@ def stereo(seed: int = 3, H: int = 288, W: int = 384, n_disp: int = 64, L: int =
     w = Workload(f"stereo{H}x{W}_L{L}", H, W, gamma, SAMPLED, lam, tau=tau, samples=cost,
                  iters=iters)
     w.target = disp.astype(np.float32)
+    w.pair = (left.astype(np.float32), right.astype(np.float32))
     return w
 
 
