@@ -266,6 +266,21 @@ sl_status sl_set_residual_target(sl_problem p, double s);
 sl_status sl_set_tiling(sl_problem p, int32_t label_groups, int32_t tile_rows);
 sl_status sl_get_tiling(sl_problem p, int32_t *label_groups, int32_t *tile_rows);
 
+/* Matching costs of the stereo experiment (Sec. 5.4), the sampled data term of a stereo
+ * problem (samples for SL_RHO_SAMPLED with tau_m = m, m = 0..D-1): for every pixel (r, c)
+ * and disparity d,
+ *   costs[d][r][c] = min(trunc, sum over i, j in {-1, 0, 1, 2} of
+ *                    |dxL(p) - dxR(q)| + |dyL(p) - dyR(q)|),
+ *   p = (clamp(r + i), clamp(c + j)) (clamped into the image), q = (p_r, max(p_c - d, 0)),
+ * a truncated sum of absolute gradient differences over a 4x4 patch; dx, dy are forward
+ * differences, zero on the last column / row.
+ * left, right: DEVICE [H][W] float (row-major), read only; costs: DEVICE [D][H][W] float,
+ * written; caller-owned. H, W >= 1 with H*W < 2^29, 1 <= D <= 1024, trunc >= 0 (may be
+ * +inf), else SL_ERR_INVALID_ARG (SL_ERR_UNSUPPORTED for the size limits). Enqueued on
+ * hip_stream (NULL: the null stream); asynchronous, no allocation. */
+sl_status sl_stereo_costs(const float *left, const float *right, int32_t H, int32_t W, int32_t D,
+                          double trunc, float *costs, void *hip_stream);
+
 /* Release the handle (NULL-safe). Does not free the caller's workspace; waits for the
  * handle's stream first. */
 void sl_destroy(sl_problem p);

@@ -85,6 +85,7 @@ def lib():
         L.sl_save_state.argtypes = [vp, vp, sz]
         L.sl_load_state.argtypes = [vp, vp, sz]
         L.sl_set_tiling.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sl_stereo_costs.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, vp]
         L.sl_get_tiling.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.sl_batch_workspace_size.argtypes = [C.POINTER(Desc), C.c_int32, C.POINTER(sz)]
         L.sl_batch_create.argtypes = [C.POINTER(Desc), C.c_int32, vp, sz, vp, C.POINTER(vp)]
@@ -360,6 +361,24 @@ class BatchProblem(Problem):
 
 
 STATE_ORDER = ("u", "u_prev", "s", "s_prev", "v", "z", "px", "py", "qd")
+
+
+def stereo_costs(left, right, D: int, trunc: float, out=None, device=None):
+    """Matching-cost volume [D][H][W] (float32, on the GPU) of a rectified pair: the
+    truncated sum of absolute gradient differences over 4x4 patches (sl_stereo_costs), on
+    torch's current stream."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda:0")
+    lt = _dev_f32(left, dev).contiguous()
+    rt = _dev_f32(right, dev).contiguous()
+    H, W = lt.shape
+    if out is None:
+        out = torch.empty((int(D), H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    _check(lib().sl_stereo_costs(C.c_void_p(lt.data_ptr()), C.c_void_p(rt.data_ptr()), H, W, int(D),
+                                 float(trunc), C.c_void_p(out.data_ptr()),
+                                 C.c_void_p(stream.cuda_stream)))
+    return out   # lt / rt may be released: the allocator orders their reuse on this stream
 
 
 def unpack_state(t, k: int, H: int, W: int) -> dict:

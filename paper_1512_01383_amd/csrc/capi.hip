@@ -12,6 +12,7 @@
 
 #include "sublabel.h"
 #include "internal.hpp"
+#include "stereo.hpp"
 
 namespace {
 
@@ -1438,6 +1439,18 @@ sl_status sl_get_tiling(sl_problem P, int32_t *label_groups, int32_t *tile_rows)
   if (!P || !label_groups || !tile_rows) return fail(SL_ERR_INVALID_ARG, "NULL argument");
   *label_groups = kIterCfg[P->cfg][0];
   *tile_rows = kIterCfg[P->cfg][1];
+  return SL_OK;
+}
+
+sl_status sl_stereo_costs(const float *left, const float *right, int32_t H, int32_t W, int32_t D,
+                          double trunc, float *costs, void *hip_stream) {
+  if (!left || !right || !costs) return fail(SL_ERR_INVALID_ARG, "NULL image or cost pointer");
+  if (H < 1 || W < 1 || D < 1) return fail(SL_ERR_INVALID_ARG, "H, W and D must be >= 1");
+  if ((long long)H * W >= (1LL << 29)) return fail(SL_ERR_UNSUPPORTED, "H*W must be < 2^29");
+  if (D > 1024) return fail(SL_ERR_UNSUPPORTED, "D must be <= 1024");
+  if (!(trunc >= 0.0)) return fail(SL_ERR_INVALID_ARG, "trunc must be >= 0");
+  HIPCHK(launch_stereo_costs(left, right, H, W, D, (float)trunc, costs, (hipStream_t)hip_stream),
+         "stereo cost launch");
   return SL_OK;
 }
 

@@ -37,7 +37,7 @@ def S():
 
 def test_library_exports_every_declared_entry_point(lib):
     names = _declared()
-    assert len(names) == 28, names   # the entry points of include/sublabel.h
+    assert len(names) == 29, names   # the entry points of include/sublabel.h
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -130,3 +130,19 @@ def test_batch_workspace_size(lib, S):
     singles = sum(_size(lib, _desc(S, *hwl))[1] for hwl in [(8, 9, 5), (30, 70, 9)])
     assert n.value >= singles
     assert lib.sl_batch_workspace_size(ds, 0, C.byref(n)) == 1
+
+
+def test_stereo_cost_argument_checks(lib):
+    """Every rejected call fails before anything is launched (the pointers are dummies)."""
+    f = lib.sl_stereo_costs
+    f.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                  C.c_void_p, C.c_void_p]
+    p = C.c_void_p(256)
+    assert f(None, p, 8, 8, 4, 1.0, p, None) == 1
+    assert f(p, p, 8, 8, 4, 1.0, None, None) == 1
+    assert f(p, p, 0, 8, 4, 1.0, p, None) == 1
+    assert f(p, p, 8, 8, 0, 1.0, p, None) == 1
+    assert f(p, p, 8, 8, 1025, 1.0, p, None) == 2
+    assert f(p, p, 1 << 15, 1 << 14, 4, 1.0, p, None) == 2
+    assert f(p, p, 8, 8, 4, -1.0, p, None) == 1
+    assert f(p, p, 8, 8, 4, float("nan"), p, None) == 1
