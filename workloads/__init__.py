@@ -249,10 +249,14 @@ def phase_unwrapping(seed: int = 7, H: int = 256, W: int = 256, L: int = 8,
 
 def baseline_lifting(wl: Workload) -> Workload:
     """The comparison method of Sec. 5 as a special case (Prop. 2): the data term of a
-    quadratic or truncated-quadratic workload given only at its labels (samples at tau ==
-    gamma), so every interval's convex piece is the chord between its end labels."""
+    quadratic, truncated-quadratic or periodic workload given only at its labels (samples
+    at tau == gamma), so every interval's convex piece is the chord between its end
+    labels."""
     f = wl.f.astype(np.float64)
-    rho = 0.5 * wl.a * (wl.gamma[:, None, None] - f[None]) ** 2
+    dist = wl.gamma[:, None, None] - f[None]
+    if wl.rho == PERIODIC_QUAD:   # distance on the circle of circumference nu
+        dist = np.abs(np.mod(dist + 0.5 * wl.nu, wl.nu) - 0.5 * wl.nu)
+    rho = 0.5 * wl.a * dist ** 2
     if wl.rho == TRUNC_QUAD:
         rho = np.minimum(rho, wl.nu)
     return Workload(wl.name + "_baseline", wl.H, wl.W, wl.gamma.copy(), SAMPLED, wl.lam,
