@@ -102,3 +102,35 @@ def test_gradients_match_oracle_reverse_pass(orc):
     _check_close(gf, gfo, "grad f")
     assert abs(gl - glo) <= 1e-4 * abs(glo), (gl, glo)
     assert gw is None
+
+
+def test_bf16_single_iteration(orc):
+    """BF16 storage of the duals with periodic pieces: one iteration from a state already
+    representable in BF16 (duals to BF16 rounding, the rest to FP32 accuracy)."""
+    from tests.test_gpu_parity import _bf16_round
+    name, wl = CASES[0]
+    g = S.Problem.from_workload(wl, storage="bf16")
+    o = orc.Problem(wl)
+    st = W.random_state(43, wl.k, wl.H, wl.W)
+    for n in ("v", "z", "px", "py"):
+        st[n] = _bf16_round(st[n])
+    _load_same_state(g, o, st)
+    g.run(1)
+    o.run(1)
+    got, ref = _gpu_state(g), o.get_state()
+    for n in S.STATE_ORDER:
+        tol = 4e-3 if n in ("v", "z", "px", "py") else 2e-5
+        err = np.abs(got[n].astype(np.float64) - ref[n])
+        assert np.all(err <= tol * (1.0 + np.abs(ref[n]))), (n, err.max())
+
+
+def test_adaptive_run_unwraps():
+    """The phase workload at a reduced size solved to a 1e-3 gap with adaptive steps: the
+    read-out lies on the generating phase's branch almost everywhere."""
+    wl = W.phase_unwrapping(H=64, W=64, L=8)
+    g = S.Problem.from_workload(wl, adaptive=True)
+    g.run_to_gap(1e-3, 30000)
+    assert g.energy()["rel_gap"] <= 1e-3
+    _, u = g.read_u()
+    err = u.cpu().numpy().astype(np.float64) - wl.target
+    assert np.mean(np.abs(err) < np.pi) > 0.95
