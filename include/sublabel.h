@@ -70,7 +70,7 @@ typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2,
 
 /* TV kind. ISO: sum_x |grad u(x)|_2, K a product of l2 discs of radius lambda h_i
  * (Prop. 5). ANISO: sum_x |grad u(x)|_1; Props. 4 and 5 hold for any convex
- * one-homogeneous norm (Sec. 5, comparison with Zach and Kohli), so K becomes a product
+ * one-homogeneous norm (Sec. 5.3, comparison with Zach and Kohli), so K becomes a product
  * of l-inf boxes of half-width lambda h_i. The certified bounds and the nonconvex energy
  * use the same norm. */
 typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;

@@ -26,7 +26,7 @@ extern "C" {
 enum { OR_QUAD = 0, OR_TRUNC_QUAD = 1, OR_SAMPLED = 2, OR_PERIODIC_QUAD = 3 };
 enum { OR_PIECE_QUAD = 0, OR_PIECE_PL = 1 };
 /* regulariser: isotropic TV (l2 norm of the gradient, Prop. 5: K is a product of l2
- * balls) or anisotropic TV (l1 norm, Sec. 5, comparison with Zach and Kohli: Props. 4
+ * balls) or anisotropic TV (l1 norm, Sec. 5.3, comparison with Zach and Kohli: Props. 4
  * and 5 hold for any convex one-homogeneous norm, and K becomes a product of l-inf boxes) */
 enum { OR_TV_ISO = 0, OR_TV_ANISO = 1 };
 

@@ -88,7 +88,7 @@ __device__ __forceinline__ void ball(float &px, float &py, float rad) {
   py *= f;
 }
 
-// The anisotropic TV (l1 norm of the gradient, Sec. 5 on Zach and Kohli: Props. 4 and 5
+// The anisotropic TV (l1 norm of the gradient, Sec. 5.3 on Zach and Kohli: Props. 4 and 5
 // hold for any convex one-homogeneous norm) has the l-inf box as its dual set: clamp each
 // component.
 __device__ __forceinline__ void box(float &px, float &py, float rad) {

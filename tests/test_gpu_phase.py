@@ -134,3 +134,28 @@ def test_adaptive_run_unwraps():
     _, u = g.read_u()
     err = u.cpu().numpy().astype(np.float64) - wl.target
     assert np.mean(np.abs(err) < np.pi) > 0.95
+
+
+@pytest.mark.parametrize("tiling", [(1, 4), (4, 4)], ids=["g1t4", "g4t4"])
+def test_periodic_with_anisotropic_tv(orc, tiling):
+    """Both options together: periodic pieces and the l-inf box projection."""
+    wl = W.phase_unwrapping(seed=57, H=10, W=100, L=6, lam=0.3)
+    wl.tv = 1
+    g = S.Problem.from_workload(wl)
+    o = orc.Problem(wl)
+    g.set_tiling(*tiling)
+    st = W.random_state(44, wl.k, wl.H, wl.W)
+    _load_same_state(g, o, st)
+    g.run(1)
+    o.run(1)
+    got, ref = _gpu_state(g), o.get_state()
+    for n in S.STATE_ORDER:
+        err = np.abs(got[n].astype(np.float64) - ref[n])
+        assert np.all(err <= 2e-5 * (1.0 + np.abs(ref[n]))), (n, err.max())
+    # the monitor on an identical state (both sides load the same FP32 values)
+    st2 = W.random_state(45, wl.k, wl.H, wl.W, scale=0.3)
+    _load_same_state(g, o, st2)
+    eg, eo = g.energy(), o.monitor()
+    for a_, b_ in ((eg["primal_ub"], eo["primal"]), (eg["dual_lb"], eo["dual"]),
+                   (eg["e_nonconvex"], eo["e_nc"])):
+        assert _rel(a_, b_) < 1e-9, (a_, b_)

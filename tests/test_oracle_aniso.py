@@ -1,4 +1,4 @@
-"""Pins of the oracle's anisotropic total variation (Sec. 5, comparison with Zach and
+"""Pins of the oracle's anisotropic total variation (Sec. 5.3, comparison with Zach and
 Kohli: Props. 4 and 5 hold for any convex one-homogeneous norm of the gradient; for the
 l1 norm the per-label dual set K is the l-inf box of half-width lambda h_i).
 
