@@ -275,7 +275,7 @@ sl_status sl_get_tiling(sl_problem p, int32_t *label_groups, int32_t *tile_rows)
  * a truncated sum of absolute gradient differences over a 4x4 patch; dx, dy are forward
  * differences, zero on the last column / row.
  * left, right: DEVICE [H][W] float (row-major), read only; costs: DEVICE [D][H][W] float,
- * written; caller-owned. H, W >= 1 with H*W < 2^29, 1 <= D <= 1024, trunc >= 0 (may be
+ * written, must not overlap the images; caller-owned. H, W >= 1 with H*W < 2^29, 1 <= D <= 1024, trunc >= 0 (may be
  * +inf), else SL_ERR_INVALID_ARG (SL_ERR_UNSUPPORTED for the size limits). Enqueued on
  * hip_stream (NULL: the null stream); asynchronous, no allocation. */
 sl_status sl_stereo_costs(const float *left, const float *right, int32_t H, int32_t W, int32_t D,
