@@ -146,3 +146,11 @@ def test_stereo_cost_argument_checks(lib):
     assert f(p, p, 1 << 15, 1 << 14, 4, 1.0, p, None) == 2
     assert f(p, p, 8, 8, 4, -1.0, p, None) == 1
     assert f(p, p, 8, 8, 4, float("nan"), p, None) == 1
+
+
+def test_binding_fails_loudly_without_the_library(S, monkeypatch):
+    """No CPU fallback: with the library absent every entry point of the binding raises."""
+    monkeypatch.setattr(S, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libsublabel.so"))
+    monkeypatch.setattr(S, "_lib", None)
+    with pytest.raises(ImportError, match="missing"):
+        S.lib()
