@@ -59,3 +59,15 @@ def test_solve_on_built_volume(orc):
     eg, eo = g.energy(), o.monitor()
     for a, b in ((eg["primal_ub"], eo["primal"]), (eg["dual_lb"], eo["dual"])):
         assert abs(a - b) <= 1e-5 * abs(b), (a, b)
+
+
+def test_largest_disparity_count_and_zero_truncation(orc):
+    """D at its documented maximum (1024, far beyond the image width) and trunc = 0."""
+    left, right = _pair(11, 9, 70)
+    got = S.stereo_costs(left, right, 1024, 2.0).cpu().numpy().astype(np.float64)
+    ref = orc.stereo_costs(left, right, 1024, 2.0)
+    assert np.all(np.abs(got - ref) <= 1e-5 * (1.0 + np.abs(ref)))
+    # beyond the width every disparity reads column 0 of the right image: identical planes
+    assert np.array_equal(got[70], got[1023])
+    zero = S.stereo_costs(left, right, 5, 0.0).cpu().numpy()
+    assert np.all(zero == 0.0)
