@@ -26,7 +26,7 @@ constexpr int MB = 256;
 
 struct PieceD {
   int kind;  // 0 quad, 1 pl
-  double a, c, g0, g1, nu, hs;
+  double a, ia, c, g0, g1, nu, hs;
   int nv;      // PL vertex count
   int ml, mr;  // straddle hull range
   int mode;    // 0: explicit vertices from cost planes, 1: flat, 2: straddle samples
@@ -72,7 +72,7 @@ __device__ void vertex(const PieceD &P, int j, double &t, double &r) {
 // rho_i^*(y) without the additive term
 __device__ double conj0(const PieceD &P, double y) {
   if (P.kind == 0) {
-    double t = fmin(fmax(P.c + y / P.a, P.g0), P.g1);
+    double t = fmin(fmax(P.c + y * P.ia, P.g0), P.g1);
     return t * y - 0.5 * P.a * (t - P.c) * (t - P.c);
   }
   double g = -INFINITY;
@@ -138,6 +138,7 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
   P.g0 = D.gam[i];
   P.g1 = D.gam[i + 1];
   P.a = D.a;
+  P.ia = D.ia;
   P.nu = D.nu;
   P.ps = A.ps;
   P.x = x;
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
         vh -= qy;
       }
       make_piece<PIECE, ADD>(A, D, M, x, i, P);
-      const double y = vh / D.h[i];
+      const double y = vh * D.ih[i];
       mloc = fmax(mloc, pre - D.gam[i] * y + conj_full(P, y));
       pre += vh;
       ub += D.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
       double gx = hx ? mu[i * A.ps + x + 1] - u0 : 0.0;
       double gy = hy ? mu[i * A.ps + x + A.W] - u0 : 0.0;
       tr += D.h[i] * tv_norm(A, gx, gy);
-      double g0 = D.gam[i], ih = 1.0 / D.h[i];
+      double g0 = D.gam[i], ih = D.ih[i];
       double l0 = fmin(fmax((b[x] - g0) * ih, 0.0), 1.0);
       double lx = hx ? fmin(fmax((b[x + 1] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
       double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
@@ -516,6 +517,7 @@ __global__ void k_straddle_info(const float *fn, const float *f_orig, unsigned *
   int slot = 0;
   PieceD P;
   P.a = D.a;
+  P.ia = D.ia;
   P.nu = D.nu;
   P.c = ((double)f_orig[x] - D.shift) / D.scale;
   for (int i = 0; i < A.k && slot < 2; i++) {

@@ -267,11 +267,15 @@ void fill_args(sl_problem_ *P) {
   P->lam = d->lambda * P->scale;
   MonArgs &D = P->D;
   for (int j = 0; j < L; j++) D.gam[j] = g[j];
-  for (int i = 0; i < k; i++) D.h[i] = h[i];
+  for (int i = 0; i < k; i++) {
+    D.h[i] = h[i];
+    D.ih[i] = 1.0 / h[i];
+  }
   D.shift = P->shift;
   D.scale = P->scale;
   D.lam = P->lam;
   D.a = d->rho != SL_RHO_SAMPLED ? d->a * P->scale * P->scale : 0.0;
+  D.ia = D.a > 0.0 ? 1.0 / D.a : 0.0;
   D.nu = d->nu;
   A.lam = (float)P->lam;
   A.aniso = d->tv == SL_TV_ANISO ? 1 : 0;

@@ -101,6 +101,8 @@ struct MonArgs {
   double h[SLI_MAXK];
   double a, nu, shift, scale, lam;
   double per;             // period of periodic quadratic pieces (normalised); 0: none
+  double ih[SLI_MAXK];    // 1 / h_i
+  double ia;              // 1 / a (0 for sampled costs)
 };
 
 struct MonPtrs {
