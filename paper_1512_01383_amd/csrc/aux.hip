@@ -193,11 +193,8 @@ __device__ __forceinline__ double tv_norm(const IterArgs &A, double gx, double g
   return A.aniso ? fabs(gx) + fabs(gy) : sqrt(gx * gx + gy * gy);
 }
 
-template <typename DT>
-__device__ void proj_p(const IterArgs &A, const DT *p, int i, long long x, double rad, double &px,
-                       double &py) {
-  px = ldv(p, i * A.ps + x);
-  py = ldv(p, (A.k + i) * A.ps + x);
+// projection onto K of radius rad (l2 disc, or l-inf box for the anisotropic TV), in FP64
+__device__ void proj_K_d(const IterArgs &A, double rad, double &px, double &py) {
   if (A.aniso) {   // l-inf box
     px = fmin(fmax(px, -rad), rad);
     py = fmin(fmax(py, -rad), rad);
@@ -210,6 +207,7 @@ __device__ void proj_p(const IterArgs &A, const DT *p, int i, long long x, doubl
     py *= f;
   }
 }
+
 
 __device__ void block_sum(double *vals, int nv, double *out_row) {
   __shared__ double red[SLI_NMON][MB];
@@ -286,7 +284,6 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
     theta = th;
     if (!__syncthreads_or(removed)) break;
   }
-  auto xs = [&](int i) { return -D.h[i] * (double)M.s[i * A.ps + x]; };
   // repaired weights w_i = max(x_i - theta, 0); u_i clamped into [sum_{j>i} w_j, sum_{j>=i} w_j]
   double tw = 0.0;
 #pragma unroll
@@ -299,12 +296,19 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
   for (int g = MT - 1; g >= 0; g--)
     if (g > t) lo += xa[g][lane];
   double dat = 0.0;
-  if (in)
-    for (int i = i1 - 1; i >= i0; i--) {
-      const double xi = xs(i);
+  if (in) {
+    // the chunk's u, all in flight at once; x_i = -h_i s_i is still in xv
+    float uq[MC];
+#pragma unroll
+    for (int q = 0; q < MC; q++) uq[q] = i0 + q < i1 ? M.u[(i0 + q) * A.ps + x] : 0.f;
+#pragma unroll
+    for (int q = MC - 1; q >= 0; q--) {
+      const int i = i0 + q;
+      if (i >= i1) continue;
+      const double xi = xv[q];
       const double wi = xi > theta ? xi - theta : 0.0;
       double al = 0.0;
-      if (wi > 0.0) al = fmin(fmax((M.u[i * A.ps + x] - lo) / wi, 0.0), 1.0);
+      if (wi > 0.0) al = fmin(fmax((uq[q] - lo) / wi, 0.0), 1.0);
       M.mon_u[i * A.ps + x] = lo + wi * al;
       if (wi > 0.0) {
         make_piece<PIECE, ADD>(A, D, M, x, i, P);
@@ -312,34 +316,59 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
       }
       lo += wi;
     }
+  }
   vals[0] = dat;
 
   // dual bound: max over labels of sum_{j<i} vh_j - gamma_i vh_i/h_i + rho_i^*(vh_i/h_i),
   // vh = div of p projected onto K; each chunk forms its local prefix and maximum
   const DT *p = (const DT *)M.p;
   double mloc = -INFINITY, pre = 0.0, ub = 0.0;
-  if (in)
+  // p at the pixel, its left and its upper neighbour (the pixel itself stands in for a
+  // missing neighbour; such values are not used) and u; the next label's are loaded
+  // while the current one is evaluated
+  struct PIn {
+    float px, py, lx, ly, ux, uy, u;
+  };
+  const long long x_l = cc > 0 ? x - 1 : x, x_u = r > 0 ? x - A.W : x;
+  auto pload = [&](int i, PIn &o) {
+    const long long b = (long long)i * A.ps, bk = (long long)(A.k + i) * A.ps;
+    o.px = ldv(p, b + x);
+    o.py = ldv(p, bk + x);
+    o.lx = ldv(p, b + x_l);
+    o.ly = ldv(p, bk + x_l);
+    o.ux = ldv(p, b + x_u);
+    o.uy = ldv(p, bk + x_u);
+    o.u = M.u[b + x];
+  };
+  if (in && i0 < i1) {
+    PIn cur, nxt;
+    pload(i0, cur);
     for (int i = i0; i < i1; i++) {
+      if (i + 1 < i1) pload(i + 1, nxt);
       const double rad = D.lam * D.h[i];
-      double px, py, qx, qy;
-      proj_p(A, p, i, x, rad, px, py);
+      double px = cur.px, py = cur.py;
+      proj_K_d(A, rad, px, py);
       double vh = 0.0;
       if (cc < A.W - 1) vh += px;
       if (r < A.H - 1) vh += py;
       if (cc > 0) {
-        proj_p(A, p, i, x - 1, rad, qx, qy);
+        double qx = cur.lx, qy = cur.ly;
+        proj_K_d(A, rad, qx, qy);
         vh -= qx;
       }
       if (r > 0) {
-        proj_p(A, p, i, x - A.W, rad, qx, qy);
+        double qx = cur.ux, qy = cur.uy;
+        proj_K_d(A, rad, qx, qy);
         vh -= qy;
       }
       make_piece<PIECE, ADD>(A, D, M, x, i, P);
       const double y = vh * D.ih[i];
       mloc = fmax(mloc, pre - D.gam[i] * y + conj_full(P, y));
       pre += vh;
-      ub += D.h[i] * fmin(fmax((double)M.u[i * A.ps + x], 0.0), 1.0);
+      ub += D.h[i] * fmin(fmax((double)cur.u, 0.0), 1.0);
+      cur = nxt;
     }
+  }
   __syncthreads();   // every read of xa above is done
   xa[t][lane] = mloc;
   xb[t][lane] = pre;
