@@ -433,15 +433,30 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
     const double *b = M.mon_b;
     const double *mu = M.mon_u;
     double tr = 0.0, tg = 0.0;
-    for (int i = i0; i < i1; i++) {
-      double u0 = mu[i * A.ps + x];
-      double gx = hx ? mu[i * A.ps + x + 1] - u0 : 0.0;
-      double gy = hy ? mu[i * A.ps + x + A.W] - u0 : 0.0;
+    // the chunk's repaired u at the pixel and its right and lower neighbours, all loads in
+    // flight at once, then the sums in label order
+    constexpr int MC = (SLI_MAXK + MT - 1) / MT;
+    double u0[MC], ur[MC], ud[MC];
+#pragma unroll
+    for (int q = 0; q < MC; q++) {
+      const long long o = (long long)(i0 + q) * A.ps + x;
+      const bool use = i0 + q < i1;
+      u0[q] = use ? mu[o] : 0.0;
+      ur[q] = use && hx ? mu[o + 1] : 0.0;
+      ud[q] = use && hy ? mu[o + A.W] : 0.0;
+    }
+    const double b0 = b[x], b1 = hx ? b[x + 1] : 0.0, b2 = hy ? b[x + A.W] : 0.0;
+#pragma unroll
+    for (int q = 0; q < MC; q++) {
+      const int i = i0 + q;
+      if (i >= i1) continue;
+      double gx = hx ? ur[q] - u0[q] : 0.0;
+      double gy = hy ? ud[q] - u0[q] : 0.0;
       tr += D.h[i] * tv_norm(A, gx, gy);
       double g0 = D.gam[i], ih = D.ih[i];
-      double l0 = fmin(fmax((b[x] - g0) * ih, 0.0), 1.0);
-      double lx = hx ? fmin(fmax((b[x + 1] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
-      double ly = hy ? fmin(fmax((b[x + A.W] - g0) * ih, 0.0), 1.0) - l0 : 0.0;
+      double l0 = fmin(fmax((b0 - g0) * ih, 0.0), 1.0);
+      double lx = hx ? fmin(fmax((b1 - g0) * ih, 0.0), 1.0) - l0 : 0.0;
+      double ly = hy ? fmin(fmax((b2 - g0) * ih, 0.0), 1.0) - l0 : 0.0;
       tg += D.h[i] * tv_norm(A, lx, ly);
     }
     vals[0] = tr;
