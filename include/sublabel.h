@@ -20,7 +20,9 @@
  *  - Device buffers are plain device pointers (hipMalloc'd or a framework's tensor
  *    storage) on the device that is current when sl_create is called. The library itself
  *    never allocates device memory: all device storage it uses lives in the caller's
- *    workspace.
+ *    workspace. A handle holds one small pinned host buffer (hipHostMalloc, a few doubles;
+ *    16 per batch member), allocated at its first synchronising report and freed by
+ *    sl_destroy, as the target of the copies of the monitor and residual sums.
  *  - Work is enqueued on the hipStream_t given to sl_create (NULL = legacy stream);
  *    calls are asynchronous unless stated otherwise.
  *  - A handle is not thread-safe; distinct handles are independent.

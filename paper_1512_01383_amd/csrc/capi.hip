@@ -197,6 +197,10 @@ struct sl_problem_ {
   std::vector<float> tau_host;
   std::vector<double> taud_host;
   double fin[SLI_NMON];
+  // pinned host staging for the small device-to-host copies of the monitor and residual
+  // sums (a copy into pageable memory goes through a bounce buffer and costs ~40 us)
+  double *pin = nullptr;
+  size_t pin_n = 0;
 
   // batch handles: sub-problems advance together in one persistent launch per iteration
   bool is_batch = false;
@@ -228,6 +232,7 @@ struct sl_problem_ {
 
   ~sl_problem_() {
     for (sl_problem_ *q : sub) delete q;
+    if (pin) (void)hipHostFree(pin);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
@@ -437,12 +442,28 @@ sl_status monitor_finish(sl_problem_ *P, sl_report *out) {
   return SL_OK;
 }
 
+// the handle's pinned staging buffer, grown to at least n doubles (allocated on first use)
+sl_status pinned(sl_problem_ *P, size_t n, double **out) {
+  if (P->pin_n < n) {
+    if (P->pin) (void)hipHostFree(P->pin);
+    P->pin = nullptr;
+    P->pin_n = 0;
+    HIPCHK(hipHostMalloc((void **)&P->pin, n * sizeof(double), hipHostMallocDefault), "pinned staging buffer");
+    P->pin_n = n;
+  }
+  *out = P->pin;
+  return SL_OK;
+}
+
 sl_status monitor(sl_problem_ *P, sl_report *out) {
   sl_status s = monitor_enqueue(P);
   if (s != SL_OK) return s;
-  HIPCHK(hipMemcpyAsync(P->fin, mon_out(P), 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
+  double *stage = nullptr;
+  if ((s = pinned(P, SLI_NMON, &stage)) != SL_OK) return s;
+  HIPCHK(hipMemcpyAsync(stage, mon_out(P), 7 * sizeof(double), hipMemcpyDeviceToHost, P->st),
          "monitor copy");
   HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
+  memcpy(P->fin, stage, 7 * sizeof(double));
   return monitor_finish(P, out);
 }
 
@@ -627,10 +648,13 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
       for (size_t i = 0; i < P->sub.size(); i++)
         if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = residuals_enqueue(P->sub[i])) != SL_OK) return s;
-      HIPCHK(hipMemcpyAsync(P->bfin_host.data(), P->bfin_dev, P->bfin_host.size() * sizeof(double),
+      double *stage = nullptr;
+      if ((s = pinned(P, P->bfin_host.size(), &stage)) != SL_OK) return s;
+      HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double),
                             hipMemcpyDeviceToHost, P->st),
              "residual copy");
       HIPCHK(hipStreamSynchronize(P->st), "residual sync");
+      memcpy(P->bfin_host.data(), stage, P->bfin_host.size() * sizeof(double));
       for (size_t i = 0; i < P->sub.size(); i++) {
         if (!P->active[i] || !P->sub[i]->d.adaptive_steps) continue;
         adapt_balance(P->sub[i], P->bfin_host[i * 16 + 8], P->bfin_host[i * 16 + 9]);
@@ -647,10 +671,13 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
     // every active member's monitor, then one copy and one wait for all of them
     for (size_t i = 0; i < P->sub.size(); i++)
       if (P->active[i] && (s = monitor_enqueue(P->sub[i])) != SL_OK) return s;
-    HIPCHK(hipMemcpyAsync(P->bfin_host.data(), P->bfin_dev, P->bfin_host.size() * sizeof(double),
+    double *stage = nullptr;
+    if ((s = pinned(P, P->bfin_host.size(), &stage)) != SL_OK) return s;
+    HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double),
                           hipMemcpyDeviceToHost, P->st),
            "monitor copy");
     HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
+    memcpy(P->bfin_host.data(), stage, P->bfin_host.size() * sizeof(double));
     bool changed = false;
     for (size_t i = 0; i < P->sub.size(); i++) {
       if (!P->active[i]) continue;
@@ -716,8 +743,9 @@ sl_status residuals_enqueue(sl_problem_ *P) {
 sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
   sl_status s = residuals_enqueue(P);
   if (s != SL_OK) return s;
-  double h[2];
-  HIPCHK(hipMemcpyAsync(h, res_out(P), sizeof h, hipMemcpyDeviceToHost, P->st), "residual copy");
+  double *h = nullptr;
+  if ((s = pinned(P, 2, &h)) != SL_OK) return s;
+  HIPCHK(hipMemcpyAsync(h, res_out(P), 2 * sizeof(double), hipMemcpyDeviceToHost, P->st), "residual copy");
   HIPCHK(hipStreamSynchronize(P->st), "residual sync");
   *rp = h[0];
   *rd = h[1];
