@@ -133,8 +133,10 @@ __device__ void hull_range_d(const PieceD &P, int &ml, int &mr) {
 }
 
 template <int PIECE, bool ADD>
+// fc: the pixel's normalised data centre in float (the iteration's classification input),
+// c: the same in double from the caller's f; both are per pixel and formed once by the caller
 __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long x,
-                           int i, PieceD &P) {
+                           int i, float fc, double c, PieceD &P) {
   P.g0 = D.gam[i];
   P.g1 = D.gam[i + 1];
   P.a = D.a;
@@ -151,8 +153,7 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
     P.m0 = A.sidx[i];
     P.nv = A.sidx[i + 1] - A.sidx[i] + 1;
   } else {
-    const float fc = M.fn[x];
-    P.c = ((double)M.f_orig[x] - D.shift) / D.scale;
+    P.c = c;
     if (PIECE == SLI_QUAD) {
       P.kind = 0;
       if (D.per > 0.0)   // periodic branch: m decided in float as in the iteration
@@ -246,6 +247,9 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
   const int r = (int)(x / A.W), cc = (int)(x % A.W);
   double vals[4] = {0, 0, 0, 0};
   PieceD P;
+  // the pixel's data centre, float (classification) and double (certificate), formed once
+  const float pfc = PIECE != SLI_SAMPLED ? M.fn[x] : 0.f;
+  const double pc = PIECE != SLI_SAMPLED ? ((double)M.f_orig[x] - D.shift) / D.scale : 0.0;
 
   // (a) repair: simplex projection of x = -h s by Michelot's finite algorithm. Its active
   // set only shrinks and is always {i : x_i > theta} for the current threshold. A thread's
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
       if (wi > 0.0) al = fmin(fmax((uq[q] - lo) / wi, 0.0), 1.0);
       M.mon_u[i * A.ps + x] = lo + wi * al;
       if (wi > 0.0) {
-        make_piece<PIECE, ADD>(A, D, M, x, i, P);
+        make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
         dat += wi * val_full(P, D.gam[i] + D.h[i] * al);
       }
       lo += wi;
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
         proj_K_d(A, rad, qx, qy);
         vh -= qy;
       }
-      make_piece<PIECE, ADD>(A, D, M, x, i, P);
+      make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
       const double y = vh * D.ih[i];
       mloc = fmax(mloc, pre - D.gam[i] * y + conj_full(P, y));
       pre += vh;
@@ -390,7 +394,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
     int is = 0;
     while (is < k - 1 && tt > D.gam[is + 1]) is++;
     const double al = fmin(fmax((tt - D.gam[is]) / D.h[is], 0.0), 1.0);
-    make_piece<PIECE, ADD>(A, D, M, x, is, P);
+    make_piece<PIECE, ADD>(A, D, M, x, is, pfc, pc, P);
     vals[1] = val_full(P, D.gam[is] + D.h[is] * al);
     // nonconvex data term at the back-projected value
     double e;
