@@ -3,6 +3,8 @@ benchmark times (the automatic tiling), against the FP64 oracle. GPU only.
 
 * truncated-quadratic denoising 256x256, L = 5, 10, 20: 200 iterations; certified bounds
   and nonconvex energy within 1e-5 relative, the read-out u within 1e-4 everywhere;
+* the same image with the anisotropic TV (L = 20) and the phase-unwrapping workload
+  (256x256, L = 8 on [0, 4 pi]): the same bounds, u within 1e-4 of the label range;
 * sampled-cost stereo 384x288, 64 samples, L = 8: the workload's 1000 iterations;
   bounds within 1e-5 relative;
 * the 64-instance batch: eight members after 30 batched iterations, bounds within 1e-5
@@ -54,6 +56,32 @@ def test_truncated_quadratic_full_size(orc, L):
     err = np.abs(ug.cpu().numpy() - uo).max()
     print(f"  max |u_gpu - u_oracle| = {err:.2e}")
     assert err <= 1e-4
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("kind", ["aniso_tq20", "phase"])
+def test_widened_workloads_full_size(orc, kind):
+    """The anisotropic TV on the 256x256, L = 20 benchmark image and the 256x256, L = 8
+    phase-unwrapping workload: 200 iterations in the benchmark's launch configuration."""
+    if kind == "phase":
+        wl = W.phase_unwrapping()
+    else:
+        wl = W.truncated_quadratic(L=20)
+        wl.tv = 1
+    g = S.Problem.from_workload(wl)
+    o = orc.Problem(wl)
+    print(f"{kind}: tiling {g.get_tiling()}", flush=True)
+    g.run(200)
+    o.run(200)
+    eg, eo = g.energy(), o.monitor()
+    for kg, ko in (("primal_ub", "primal"), ("dual_lb", "dual"), ("e_nonconvex", "e_nc")):
+        print(f"  {kg}: gpu {eg[kg]:.10g} oracle {eo[ko]:.10g} rel {_rel(eg[kg], eo[ko]):.2e}")
+        assert _rel(eg[kg], eo[ko]) <= 1e-5
+    _, ug = g.read_u()
+    _, uo = o.read_u()
+    err = np.abs(ug.cpu().numpy() - uo).max()
+    print(f"  max |u_gpu - u_oracle| = {err:.2e}")
+    assert err <= 1e-4 * max(1.0, float(wl.gamma[-1] - wl.gamma[0]))
 
 
 @pytest.mark.timeout(300)
