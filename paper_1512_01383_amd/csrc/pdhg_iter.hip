@@ -356,15 +356,27 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     else
       lsa[i * NP + lt] = sn;
   };
-  // two step buffers in turn: a step consumes one and fills the other
+  // two step buffers in turn: a step consumes one and fills the other. With one label
+  // group (large images, batches) an odd last step runs inside the loop: peeled after the
+  // loop it keeps both buffers live past it, and the loop head then copies the prefetched
+  // registers and waits for every outstanding access, the trailing stores' acknowledgements
+  // included (measured: batched iterations -20 %, 2048^2 -1 %). With several groups (short
+  // chunks on small images) the peeled form measured faster.
   Step b0, b1;
   load_step(i0, b0);
-  int i = i0;
-  for (; i + 2 <= i1; i += 2) {
-    label_step(i, b0, b1);
-    label_step(i + 1, b1, b0);
+  if (G == 1) {
+    for (int i = i0; i < i1; i += 2) {
+      label_step(i, b0, b1);
+      if (i + 1 < i1) label_step(i + 1, b1, b0);
+    }
+  } else {
+    int i = i0;
+    for (; i + 2 <= i1; i += 2) {
+      label_step(i, b0, b1);
+      label_step(i + 1, b1, b0);
+    }
+    if (i < i1) label_step(i, b0, b1);
   }
-  if (i < i1) label_step(i, b0, b1);
 
   // ---- prefix of the new v over the earlier chunks: correction of the s update
   if (G > 1) {
