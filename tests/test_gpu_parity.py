@@ -75,6 +75,8 @@ def _cases():
     out.append(("quad_add_L4", wq))
     out.append(("sampled_L8", _sampled_workload(10, 97, 3)))
     out.append(("sampled_L4_M13", _sampled_workload(6, 65, 4, L=4, M=13)))
+    # both documented maxima at once: 28 labels on 256 samples
+    out.append(("sampled_max", _sampled_workload(5, 70, 21, L=28, M=256)))
     out.append(("one_pixel", W.Workload("px", 1, 1, W.equispaced(4), W.TRUNC_QUAD, 0.2,
                                         f=np.array([[0.3]], np.float32), a=2.0, nu=0.025)))
     out.append(("one_row", W.truncated_quadratic(L=6, H=1, W=200, seed=3)))
