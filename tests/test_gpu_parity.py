@@ -114,7 +114,10 @@ def test_single_iteration_from_random_state(orc, name, wl, tiling):
         assert np.all(err <= bound), f"{name}/{n}: err {err[worst]:.3e} at {worst}, ref {ref[n][worst]}"
 
 
-@pytest.mark.parametrize("name,wl", CASES[:8], ids=[c[0] for c in CASES[:8]])
+MONITOR_CASES = CASES[:8] + [c for c in CASES if c[0] in ("sampled_L8", "sampled_L4_M13", "sampled_max", "k27")]
+
+
+@pytest.mark.parametrize("name,wl", MONITOR_CASES, ids=[c[0] for c in MONITOR_CASES])
 def test_monitor_on_identical_state(orc, name, wl):
     """The FP64 monitor of both sides on the same (FP32) state."""
     g, o = _pair(wl, orc)
