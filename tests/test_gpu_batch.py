@@ -24,14 +24,15 @@ TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)]
 
 
 def _mixed_tq():
-    # sizes that leave ragged 64 x 4 and 64 x 8 tiles, label counts 2 .. 20
-    shapes = [(9, 131, 5), (40, 90, 10), (1, 70, 2), (33, 64, 20), (17, 200, 8), (1, 1, 4)]
+    # sizes that leave ragged 64 x 4 and 64 x 8 tiles, label counts 2 .. 28 (the maximum)
+    shapes = [(9, 131, 5), (40, 90, 10), (1, 70, 2), (33, 64, 20), (17, 200, 8), (1, 1, 4), (5, 70, 28)]
     return [W.truncated_quadratic(L=L, H=H, W=Wd, seed=40 + j) for j, (H, Wd, L) in enumerate(shapes)]
 
 
 def _mixed_sampled():
     out = []
-    for j, (H, Wd, L, M) in enumerate([(10, 97, 8, 64), (6, 65, 4, 13), (21, 30, 6, 40)]):
+    # the last member sits at both maxima (28 labels, 256 samples)
+    for j, (H, Wd, L, M) in enumerate([(10, 97, 8, 64), (6, 65, 4, 13), (21, 30, 6, 40), (5, 70, 28, 256)]):
         rng = np.random.default_rng(70 + j)
         tau = np.arange(M, dtype=np.float64)
         idx = np.round(np.linspace(0, M - 1, L)).astype(int)
@@ -133,7 +134,7 @@ def test_batch_member_matches_oracle(orc):
     wls = _mixed_tq()
     b = S.BatchProblem(wls)
     b.run(60)
-    for i in (1, 3, 4):
+    for i in (1, 3, 4, 6):
         o = orc.Problem(wls[i])
         o.run(60)
         rg, ro = b.energy_of(i), o.monitor()
