@@ -44,7 +44,8 @@ def _cases():
     return [("quad_w", _quad_w(20, 66, rng), 25, 7),
             ("tq_w_L6", _tq_w(6, 40, 70, 3, rng), 40, 7),
             ("tq_w_L8", _tq_w(8, 33, 130, 4, rng), 60, 20),
-            ("tq_L5_no_w", W.truncated_quadratic(L=5, H=9, W=131, seed=12), 30, 8)]
+            ("tq_L5_no_w", W.truncated_quadratic(L=5, H=9, W=131, seed=12), 30, 8),
+            ("tq_w_L28", _tq_w(28, 6, 70, 6, rng), 30, 7)]      # the label maximum
 
 
 CASES = _cases()
