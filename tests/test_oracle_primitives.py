@@ -44,6 +44,26 @@ def test_golden_ball(orc):
         assert orc.proj_ball(px, py, rad) == pytest.approx(tuple(exp), abs=1e-15)
 
 
+def test_golden_tq_pieces(orc):
+    """Truncated-quadratic pieces (Sec. 5.2) against hand-derived cases: an interval inside
+    the band (quadratic piece), one outside it (constant), one straddling each band edge
+    and one holding both edges (lower hull of the 16 samples)."""
+    g = GOLD["tq_pieces"]
+    for case in g["cases"]:
+        f = np.full((1, 1), case["f"], np.float32)
+        wl = W.Workload("tq", 1, 1, np.array(case["gamma"]), W.TRUNC_QUAD, 0.1, f=f,
+                        a=case["a"], nu=case["nu"])
+        kind, acd, t, r = orc.Problem(wl).piece(0, case["interval"])
+        if case["kind"] == "quad":
+            assert kind == 0, case["name"]
+            assert acd == pytest.approx(case["acd"], abs=1e-7), case["name"]
+        else:
+            assert kind == 1, case["name"]
+            assert len(t) == len(case["t"]), (case["name"], t)
+            assert t == pytest.approx(case["t"], abs=1e-12), case["name"]
+            assert r == pytest.approx(case["r"], abs=1e-8), case["name"]
+
+
 def test_golden_variable_count(orc):
     """The state holds 6N(L-1)+N variables (Sec. 5) plus the 2N(L-1) primal history."""
     for H, Wd, L in GOLD["variable_count"]["cases"]:
