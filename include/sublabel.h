@@ -20,7 +20,8 @@
  *  - Device buffers are plain device pointers (hipMalloc'd or a framework's tensor
  *    storage) on the device that is current when sl_create is called. The library itself
  *    never allocates device memory: all device storage it uses lives in the caller's
- *    workspace. A handle holds one small pinned host buffer (hipHostMalloc, a few doubles;
+ *    workspace (the allocation-free sl_solve_static uses a fixed array of the library
+ *    instead). A handle holds one small pinned host buffer (hipHostMalloc, a few doubles;
  *    16 per batch member), allocated at its first synchronising report and freed by
  *    sl_destroy, as the target of the copies of the monitor and residual sums.
  *  - Work is enqueued on the hipStream_t given to sl_create (NULL = legacy stream);
@@ -286,6 +287,28 @@ sl_status sl_stereo_costs(const float *left, const float *right, int32_t H, int3
 /* Release the handle (NULL-safe). Does not free the caller's workspace; waits for the
  * handle's stream first. */
 void sl_destroy(sl_problem p);
+
+/* Allocation-free solve, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ *
+ * The same work and results (bitwise) as sl_create on a workspace of its own, then
+ * sl_run_to_gap(rel_gap, max_iters) if rel_gap > 0 (else sl_run(max_iters): no checks),
+ * sl_read_u(u_lifted_dev, u_dev) and, if report is not NULL, sl_energy(report) -- with the
+ * workspace taken from a fixed device array of the library instead of a caller's buffer.
+ * That array holds SL_STATIC_WORKSPACE_BYTES per GPU; it is reserved on every GPU the
+ * library's code is loaded on and held until the process ends. Problems whose
+ * sl_workspace_size exceeds it return SL_ERR_UNSUPPORTED before any device work.
+ * The call makes no hipMalloc, hipFree, hipHostMalloc or other allocating call, and no
+ * handle outlives it: the monitor's sums are copied into host memory of the call itself.
+ * Every call on one GPU shares that GPU's array and re-initialises the state in it, so
+ * calls in sequence are independent, but calls that overlap on one GPU (other threads or
+ * streams) race and must not be made. desc, u_lifted_dev ([k][H][W] float, may be NULL),
+ * u_dev ([H][W] float, may be NULL) and report (host, may be NULL) as for the calls above;
+ * arguments are checked first (SL_ERR_INVALID_ARG). Synchronises hip_stream before
+ * returning. */
+#define SL_STATIC_WORKSPACE_BYTES (64u * 1024u * 1024u)
+sl_status sl_solve_static(const sl_problem_desc *desc, double rel_gap, int32_t max_iters,
+                          float *u_lifted_dev, float *u_dev, sl_report *report, void *hip_stream);
 
 const char *sl_status_string(sl_status s);
 const char *sl_last_error(void);

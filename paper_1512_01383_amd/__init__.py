@@ -101,6 +101,8 @@ def lib():
         L.sl_set_residual_target.argtypes = [vp, C.c_double]
         L.sl_set_step_balance.argtypes = [vp, C.c_double]
         L.sl_get_step_balance.argtypes = [vp, C.POINTER(C.c_double)]
+        L.sl_solve_static.argtypes = [C.POINTER(Desc), C.c_double, C.c_int32, vp, vp,
+                                      C.POINTER(Report), vp]
         L.sl_destroy.argtypes = [vp]
         L.sl_destroy.restype = None
         for name in ("sl_workspace_size", "sl_create", "sl_run", "sl_run_to_gap", "sl_read_u",
@@ -109,7 +111,7 @@ def lib():
                      "sl_batch_energy", "sl_batch_read_u", "sl_batch_info", "sl_set_graphs",
                      "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
                      "sl_unrolled_backward", "sl_set_step_balance", "sl_get_step_balance",
-                     "sl_residuals", "sl_set_residual_target"):
+                     "sl_residuals", "sl_set_residual_target", "sl_solve_static"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -361,6 +363,37 @@ class BatchProblem(Problem):
 
 
 STATE_ORDER = ("u", "u_prev", "s", "s_prev", "v", "z", "px", "py", "qd")
+
+# bytes of the library's fixed device array used by solve_static (SL_STATIC_WORKSPACE_BYTES)
+STATIC_WORKSPACE_BYTES = 64 * 1024 * 1024
+
+
+def solve_static(wl, rel_gap: float = 0.0, max_iters: int = 0, storage: str = "fp32",
+                 normalize: bool = True, check_every: int = 50, adaptive: bool = False,
+                 device=None, out=None):
+    """Allocation-free solve (sl_solve_static) of a ``workloads.Workload``-like instance:
+    the library keeps the iteration state in its own fixed device array, so the call itself
+    allocates nothing. Runs to the certified gap ``rel_gap`` (> 0) within ``max_iters``
+    iterations, or exactly ``max_iters`` iterations (``rel_gap`` = 0), on torch's current
+    stream. ``out`` may give the (u_lifted [k,H,W], u [H,W]) float32 device tensors to write;
+    they are allocated here otherwise. Returns (u_lifted, u, report dict)."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda:0")
+    it = _Inst()
+    d = _make_desc(it, wl.H, wl.W, wl.gamma, wl.rho, wl.lam, wl.f, wl.a, wl.nu, wl.tau,
+                   wl.samples, storage, normalize, check_every, dev, adaptive,
+                   getattr(wl, "tv", TV_ISO))
+    if out is None:
+        out = (torch.empty((it.k, it.H, it.W), dtype=torch.float32, device=dev),
+               torch.empty((it.H, it.W), dtype=torch.float32, device=dev))
+    ul, u = out
+    rep = Report()
+    stream = torch.cuda.current_stream(dev)
+    _check(lib().sl_solve_static(C.byref(d), float(rel_gap), int(max_iters),
+                                 C.c_void_p(ul.data_ptr() if ul is not None else 0),
+                                 C.c_void_p(u.data_ptr() if u is not None else 0),
+                                 C.byref(rep), C.c_void_p(stream.cuda_stream)))
+    return ul, u, rep.as_dict()
 
 
 def stereo_costs(left, right, D: int, trunc: float, out=None, device=None):

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -184,7 +185,10 @@ struct sl_problem_ {
   double adapt_alpha = 0.5;  // current relative change of the balance (adaptive steps)
   double adapt_s = 0.003;    // target ratio of the primal to the dual residual
   int64_t adapt_count = 0;   // balance changes made so far
-  std::vector<double> gamma_in, tau_in;  // the caller's labels and sample positions (copies)
+  // the caller's labels and sample positions (copies; fixed arrays, so that a problem
+  // object can be built without any allocation)
+  double gamma_in[SL_MAX_LABELS] = {};
+  double tau_in[SL_MAX_SAMPLES] = {};
   hipStream_t st = nullptr;
   Layout lay{};
   char *ws = nullptr;
@@ -194,13 +198,16 @@ struct sl_problem_ {
   bool have_best = false;
   int check_every = 50;
   int nb_mon = 0;
-  std::vector<float> tau_host;
-  std::vector<double> taud_host;
+  float tau_host[SLI_MAXM] = {};
+  double taud_host[SLI_MAXM] = {};
   double fin[SLI_NMON];
   // pinned host staging for the small device-to-host copies of the monitor and residual
   // sums (a copy into pageable memory goes through a bounce buffer and costs ~40 us)
   double *pin = nullptr;
   size_t pin_n = 0;
+  // allocation-free problems stage those copies in this fixed host array instead
+  bool no_alloc = false;
+  double stage_fixed[16];
 
   // batch handles: sub-problems advance together in one persistent launch per iteration
   bool is_batch = false;
@@ -256,12 +263,12 @@ int piece_of(sl_rho_kind rho) {
 // positions from the copies kept in the handle; the caller's pointers are not kept).
 void fill_args(sl_problem_ *P) {
   const sl_problem_desc *d = &P->d;
-  const double *gamma = P->gamma_in.data(), *tau = P->tau_in.data();
+  const double *gamma = P->gamma_in, *tau = P->tau_in;
   IterArgs &A = P->A;
   const int L = d->L, k = L - 1;
   P->shift = d->normalize_labels ? gamma[0] : 0.0;
   P->scale = d->normalize_labels ? gamma[L - 1] - gamma[0] : 1.0;
-  std::vector<double> g(L), h(k);
+  double g[SL_MAX_LABELS], h[SL_MAX_LABELS];
   for (int j = 0; j < L; j++) g[j] = (gamma[j] - P->shift) / P->scale;
   for (int i = 0; i < k; i++) h[i] = g[i + 1] - g[i];
   A.H = d->H;
@@ -313,8 +320,6 @@ void fill_args(sl_problem_ *P) {
       P->D.per = d->nu / P->scale;
     }
   } else {
-    P->tau_host.resize(d->M);
-    P->taud_host.resize(d->M);
     for (int m = 0; m < d->M; m++) {
       P->taud_host[m] = (tau[m] - P->shift) / P->scale;
       P->tau_host[m] = (float)P->taud_host[m];
@@ -444,6 +449,12 @@ sl_status monitor_finish(sl_problem_ *P, sl_report *out) {
 
 // the handle's pinned staging buffer, grown to at least n doubles (allocated on first use)
 sl_status pinned(sl_problem_ *P, size_t n, double **out) {
+  if (P->no_alloc) {
+    if (n > sizeof(P->stage_fixed) / sizeof(double))
+      return fail(SL_ERR_UNSUPPORTED, "host staging of %zu values without allocation", n);
+    *out = P->stage_fixed;
+    return SL_OK;
+  }
   if (P->pin_n < n) {
     if (P->pin) (void)hipHostFree(P->pin);
     P->pin = nullptr;
@@ -848,6 +859,39 @@ int auto_cfg(const sl_problem_ *P) {
 
 }  // namespace
 
+static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_iters, int32_t *done);
+
+// ---------------------------------------------------------------- allocation-free solve
+// The workspace of sl_solve_static: one array per GPU, reserved when the library's code is
+// loaded on that GPU and held until the process ends. Host code never uses this name as a
+// device address: the address on each device comes from hipGetSymbolAddress (kept below).
+static __device__ __align__(256) unsigned char scratch[SL_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device, once looked up
+
+// Address of the static workspace on the current device (looked up once per device, with
+// that device current).
+sl_status static_workspace(void **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SL_ERR_UNSUPPORTED, "device ordinal %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static workspace address");
+    if (!ptr) return fail(SL_ERR_DEVICE, "static workspace address is NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sl_status_string(sl_status s) {
@@ -875,9 +919,10 @@ sl_status sl_workspace_size(const sl_problem_desc *desc, size_t *bytes) {
   return SL_OK;
 }
 
-static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
-                             sl_problem *out) {
-  *out = nullptr;
+// Set up problem P (a fresh object) on the caller's workspace: argument checks, labels and
+// steps, the input check, data planes and the zero state. Allocates nothing itself.
+static sl_status init_impl(sl_problem_ *P, const sl_problem_desc *desc, void *ws, size_t bytes,
+                           void *stream) {
   sl_status s = validate(desc);
   if (s != SL_OK) return s;
   if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
@@ -894,7 +939,6 @@ static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes
   int maxlds = 0;
   HIPCHK(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device attribute");
 
-  sl_problem_ *P = new sl_problem_();
   P->d = *desc;
   P->d.gamma = nullptr;
   P->d.f = nullptr;
@@ -908,66 +952,71 @@ static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes
   P->piece = piece_of(desc->rho);
   P->add = desc->rho != SL_RHO_SAMPLED && desc->samples != nullptr;
   P->check_every = desc->check_every > 0 ? desc->check_every : 50;
-  P->gamma_in.assign(desc->gamma, desc->gamma + desc->L);
-  if (desc->tau) P->tau_in.assign(desc->tau, desc->tau + desc->M);
+  std::copy(desc->gamma, desc->gamma + desc->L, P->gamma_in);
+  if (desc->tau) std::copy(desc->tau, desc->tau + desc->M, P->tau_in);
   fill_args(P);
   P->maxlds = maxlds;
   P->cfg = auto_cfg(P);
-  if (P->cfg < 0) {
-    delete P;
-    return fail(SL_ERR_UNSUPPORTED, "L = %d needs more LDS than a workgroup may use", desc->L);
-  }
+  if (P->cfg < 0) return fail(SL_ERR_UNSUPPORTED, "L = %d needs more LDS than a workgroup may use", desc->L);
   const long long N = lay.N;
-  auto cleanup = [&](sl_status st) {
-    delete P;
-    return st;
-  };
   // non-finite inputs are argument errors (checked before the state is touched)
   unsigned *flag = (unsigned *)(P->ws + lay.off_flag);
   unsigned hflag = 0;
-  if ((e = launch_fill_zero(P->ws + lay.off_flag, 16, P->st)) != hipSuccess) return cleanup(hip_fail(e, "fill"));
+  if ((e = launch_fill_zero(P->ws + lay.off_flag, 16, P->st)) != hipSuccess) return hip_fail(e, "fill");
   if (desc->f) hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, P->st, desc->f, N, flag);
   if (desc->samples)
     hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, P->st, desc->samples,
                        (long long)desc->M * N, flag);
-  if ((e = hipGetLastError()) != hipSuccess) return cleanup(hip_fail(e, "input check"));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "input check");
   if ((e = hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, P->st)) != hipSuccess)
-    return cleanup(hip_fail(e, "input check copy"));
-  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return cleanup(hip_fail(e, "input check sync"));
-  if (hflag) return cleanup(fail(SL_ERR_INVALID_ARG, "f or samples contain NaN or Inf"));
+    return hip_fail(e, "input check copy");
+  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return hip_fail(e, "input check sync");
+  if (hflag) return fail(SL_ERR_INVALID_ARG, "f or samples contain NaN or Inf");
 
   // zero state, data planes
   if ((e = launch_fill_zero(P->ws + lay.state_lo, lay.state_hi - lay.state_lo, P->st)) != hipSuccess)
-    return cleanup(hip_fail(e, "zero state"));
+    return hip_fail(e, "zero state");
   if (P->piece != SLI_SAMPLED) {
     float fs = (float)P->shift, is = (float)(1.0 / P->scale);
     if ((e = launch_init_fn(desc->f, (float *)(P->ws + lay.off_fn), N, fs, is, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "init f"));
+      return hip_fail(e, "init f");
     if ((e = launch_copy_planes(desc->f, (float *)(P->ws + lay.off_forig), 1, N, lay.ps, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "copy f"));
+      return hip_fail(e, "copy f");
     if (P->piece == SLI_TRUNC &&
         (e = launch_straddle_info((const float *)(P->ws + lay.off_fn), (const float *)(P->ws + lay.off_forig),
                                   (unsigned *)(P->ws + lay.off_sinfo), (unsigned *)(P->ws + lay.off_sinfod),
                                   P->A, P->D, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "straddle info"));
+      return hip_fail(e, "straddle info");
     if (P->add &&
         (e = launch_copy_planes(desc->samples, (float *)(P->ws + lay.off_w), desc->L, N, lay.ps, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "copy w"));
+      return hip_fail(e, "copy w");
   } else {
     float *tau_d = (float *)(P->ws + lay.off_tau);
     double *taud_d = (double *)(P->ws + lay.off_taud);
-    if ((e = hipMemcpyAsync(tau_d, P->tau_host.data(), 4 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "copy tau"));
-    if ((e = hipMemcpyAsync(taud_d, P->taud_host.data(), 8 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "copy tau"));
+    if ((e = hipMemcpyAsync(tau_d, P->tau_host, 4 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
+      return hip_fail(e, "copy tau");
+    if ((e = hipMemcpyAsync(taud_d, P->taud_host, 8 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
+      return hip_fail(e, "copy tau");
     float *cost = (float *)(P->ws + lay.off_cost);
     if ((e = launch_convexify(desc->samples, cost, taud_d, P->A, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "convexify"));
+      return hip_fail(e, "convexify");
     if ((e = launch_copy_planes(desc->samples, cost + (size_t)desc->M * lay.ps, desc->M, N, lay.ps, P->st)) != hipSuccess)
-      return cleanup(hip_fail(e, "copy raw samples"));
+      return hip_fail(e, "copy raw samples");
   }
   // inputs are no longer read once this returns
-  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return cleanup(hip_fail(e, "setup sync"));
+  if ((e = hipStreamSynchronize(P->st)) != hipSuccess) return hip_fail(e, "setup sync");
+  return SL_OK;
+}
+
+static sl_status create_impl(const sl_problem_desc *desc, void *ws, size_t bytes, void *stream,
+                             sl_problem *out) {
+  *out = nullptr;
+  sl_problem_ *P = new sl_problem_();
+  sl_status s = init_impl(P, desc, ws, bytes, stream);
+  if (s != SL_OK) {
+    delete P;
+    return s;
+  }
   *out = P;
   return SL_OK;
 }
@@ -989,6 +1038,12 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (max_iters < 0 || !(rel_gap >= 0.0)) return fail(SL_ERR_INVALID_ARG, "bad rel_gap / max_iters");
   if (P->is_batch) return batch_run_to_gap(P, rel_gap, max_iters, done);
+  return single_run_to_gap(P, rel_gap, max_iters, done);
+}
+
+}  // extern "C"
+
+static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_iters, int32_t *done) {
   int32_t n = 0;
   sl_report r;
   while (n < max_iters) {
@@ -1011,6 +1066,8 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
   if (done) *done = n;
   return SL_OK;
 }
+
+extern "C" {
 
 sl_status sl_read_u(sl_problem P, float *ulift, float *u) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
@@ -1490,6 +1547,33 @@ void sl_destroy(sl_problem P) {
   if (!P) return;
   (void)hipStreamSynchronize(P->st);
   delete P;
+}
+
+sl_status sl_solve_static(const sl_problem_desc *desc, double rel_gap, int32_t max_iters, float *u_lifted_dev,
+                          float *u_dev, sl_report *report, void *hip_stream) {
+  if (max_iters < 0 || !(rel_gap >= 0.0) || !isfinite(rel_gap))
+    return fail(SL_ERR_INVALID_ARG, "bad rel_gap / max_iters");
+  size_t need = 0;
+  sl_status s = sl_workspace_size(desc, &need);
+  if (s != SL_OK) return s;
+  if (need > (size_t)SL_STATIC_WORKSPACE_BYTES)
+    return fail(SL_ERR_UNSUPPORTED, "the problem needs %zu bytes of workspace; the allocation-free solve "
+                "has %zu", need, (size_t)SL_STATIC_WORKSPACE_BYTES);
+  void *ws = nullptr;
+  if ((s = static_workspace(&ws)) != SL_OK) return s;
+  sl_problem_ P;          // host object on the stack: nothing is allocated on the heap either
+  P.no_alloc = true;
+  if ((s = init_impl(&P, desc, ws, (size_t)SL_STATIC_WORKSPACE_BYTES, hip_stream)) != SL_OK) return s;
+  if (rel_gap > 0.0)
+    s = single_run_to_gap(&P, rel_gap, max_iters, nullptr);
+  else
+    s = enqueue_iters(&P, max_iters);
+  if (s == SL_OK && (u_lifted_dev || u_dev)) s = sl_read_u(&P, u_lifted_dev, u_dev);
+  if (s == SL_OK && report) s = monitor(&P, report);
+  // the next call on this device reuses the array: finish here
+  const hipError_t e = hipStreamSynchronize(P.st);
+  if (s == SL_OK && e != hipSuccess) s = hip_fail(e, "static solve sync");
+  return s;
 }
 
 }  // extern "C"

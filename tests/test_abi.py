@@ -37,7 +37,7 @@ def S():
 
 def test_library_exports_every_declared_entry_point(lib):
     names = _declared()
-    assert len(names) == 29, names   # the entry points of include/sublabel.h
+    assert len(names) == 30, names   # the entry points of include/sublabel.h
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -146,6 +146,28 @@ def test_stereo_cost_argument_checks(lib):
     assert f(p, p, 1 << 15, 1 << 14, 4, 1.0, p, None) == 2
     assert f(p, p, 8, 8, 4, -1.0, p, None) == 1
     assert f(p, p, 8, 8, 4, float("nan"), p, None) == 1
+
+
+def test_static_solve_argument_checks(lib, S):
+    """The allocation-free solve rejects bad arguments, and problems whose workspace exceeds
+    its fixed array, before any device work (the output pointers are dummies)."""
+    f = lib.sl_solve_static
+    p = C.c_void_p(256)
+    limit = int(re.search(r"#define SL_STATIC_WORKSPACE_BYTES \((\d+)u \* 1024u \* 1024u\)",
+                          open(HEADER).read()).group(1)) << 20
+    assert limit == S.STATIC_WORKSPACE_BYTES
+    big = _desc(S, 256, 256, 28)
+    assert _size(lib, big)[1] > limit
+    assert f(C.byref(big), 0.0, 10, p, p, None, None) == 2
+    assert "allocation-free" in lib.sl_last_error().decode()
+    ok = _desc(S, 64, 64, 8)
+    assert _size(lib, ok)[1] <= limit
+    assert f(C.byref(ok), 0.0, -1, p, p, None, None) == 1
+    assert f(C.byref(ok), -1e-3, 10, p, p, None, None) == 1
+    assert f(C.byref(ok), float("nan"), 10, p, p, None, None) == 1
+    assert f(None, 0.0, 10, p, p, None, None) == 1
+    bad = _desc(S, H=0)
+    assert f(C.byref(bad), 0.0, 10, p, p, None, None) == 1
 
 
 def test_binding_fails_loudly_without_the_library(S, monkeypatch):
