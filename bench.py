@@ -1,14 +1,19 @@
-"""Benchmark of the fused lifted primal-dual iteration on one MI355X.
+"""Benchmark of the lifted primal-dual iteration on one MI355X.
 
-Workload (default): the truncated-quadratic denoising problem at 256x256 with L = 20
-equispaced labels on [0,1], lambda = 0.25 (synthetic blobs + 10% outliers). One step is
-one check interval of a gap-controlled solve: 50 fused iterations followed by the FP64
-certified-gap monitor (as sl_run_to_gap does it), with inputs and state resident in HBM.
+Workload (default, --workload batch): 64 truncated-quadratic instances of mixed size
+(U{64,128,256,512}^2) and label count (U{2,4,8,16}), lambda = 0.25, solved together by one
+persistent launch per iteration with the duals stored in bf16 (FP32 arithmetic, FP64
+certificate). One step is one check interval of the gap-controlled batch solve: 48 batched
+iterations followed by every member's FP64 certified-gap monitor and step balance, with
+inputs and state resident in HBM.
 
 Reported: pixel-label-iterations/s (k = L-1 labels counted per pixel), the HIP-event
-average duration of the fused iteration kernel against its algorithmic bytes (roofline),
-the time to a 1e-3 certified relative gap, and the FP64 CPU oracle timed on a bounded
-sample of the same workload (baseline, not the target).
+average duration of the batched iteration kernel against its algorithmic bytes (roofline),
+the time for every member to reach a 1e-3 certified relative gap (bf16 with the float
+finishing phase, against the members solved one after another and the batch in float),
+the FP64 CPU oracle timed on a bounded sample of the same members (baseline, not the
+target), and single-instance kernel timings (256^2 cache-resident, 2048^2 in HBM).
+Other workloads: tq (one truncated-quadratic instance), stereo, phase, diff, labels.
 """
 from __future__ import annotations
 
@@ -24,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 50
+CHECK_BATCH = 48      # check interval of batched solves (a multiple of the 6-iteration period)
 KERNEL_SOURCES = ("paper_1512_01383_amd/csrc/pdhg_iter.hip", "paper_1512_01383_amd/csrc/device_math.hpp",
                   "paper_1512_01383_amd/csrc/internal.hpp")
 
@@ -41,10 +47,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str):
+def measured_traffic(workload_key: str, kernel: str = "pdhg_iter"):
     """HBM bytes per launch from the committed counter profile of this workload, if it
     was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", f"pdhg_iter_{workload_key}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_key}_traffic.json")
     try:
         with open(path) as f:
             prof = json.load(f)
@@ -71,7 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--storage", default=None, choices=["fp32", "bf16"],
+                    help="dual storage (default: bf16 for the batch, fp32 otherwise)")
     ap.add_argument("--tv", default="iso", choices=["iso", "aniso"],
                     help="regulariser: isotropic (l2) or anisotropic (l1) total variation")
     ap.add_argument("--kernel-iters", type=int, default=500)
@@ -81,18 +88,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--workload", default="tq",
+    ap.add_argument("--workload", default="batch",
                     choices=["tq", "stereo", "phase", "batch", "diff", "labels"],
-                    help="tq: one truncated-quadratic instance (default); batch: 64 mixed "
-                         "instances in one persistent launch per iteration; diff: forward and "
+                    help="batch: 64 mixed instances in one persistent launch per iteration "
+                         "(default); tq: one truncated-quadratic instance; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
     ap.add_argument("--study", default="tq", choices=["tq", "phase", "stereo", "norm"],
                     help="data of the label-count study: truncated quadratic or phase unwrapping")
     ap.add_argument("--batch-iters", type=int, default=240)
-    ap.add_argument("--batch-gap", type=float, default=1e-3,
-                    help="batch mode: also time every member to this certified gap with "
-                         "adaptive steps, batched and one after another (0 = skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="batch mode: skip the single-instance kernel timings")
     args = ap.parse_args()
+    if args.storage is None:
+        args.storage = "bf16" if args.workload == "batch" else "fp32"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -492,10 +500,56 @@ def bench_label_normalisation(args, dev):
     print(json.dumps(out))
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU baseline."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_cores() -> int:
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def single_kernel_timing(S, wl, storage, dev, iters=200):
+    """HIP-event average duration of the fused iteration kernel of one instance (the
+    library's stream, after a short warm-up) against its algorithmic bytes."""
+    import torch
+    g = S.Problem.from_workload(wl, storage=storage, device=dev)
+    g.run(20)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(g.stream)
+    g.run(iters)
+    ev1.record(g.stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1) / iters
+    tiling = g.get_tiling()
+    g.close()
+    nbytes = algorithmic_bytes_per_pixel(wl.k, wl.rho, wl.M, storage == "bf16", False) * wl.H * wl.W
+    return {"H": wl.H, "W": wl.W, "L": wl.L, "storage": storage, "kernel_ms": ms,
+            "pixel_label_iter_per_s": wl.H * wl.W * wl.k / (ms * 1e-3),
+            "algorithmic_bytes_per_launch": nbytes, "achieved_GBs": nbytes / (ms * 1e-3) / 1e9,
+            "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "tiling": list(tiling)}
+
+
 def bench_batch(args):
-    """64 truncated-quadratic instances of mixed size and label count advanced together
-    (persistent launch per iteration, graph-replayed period), against the same instances
-    solved one after another with the single-instance path on the same GPU."""
+    """Batched, mixed-precision solve: 64 truncated-quadratic instances of mixed size
+    (U{64,128,256,512}^2) and label count (U{2,4,8,16}) advanced together by one persistent
+    launch per iteration (graph-replayed rotation period, autotuned tiling), duals stored in
+    bf16 (FP32 arithmetic, FP64 certificate). One step is one check interval of the
+    gap-controlled batch solve: CHECK_BATCH batched iterations, every member's FP64 monitor
+    and its adaptive step balance. Also: the time for every member to reach a 1e-3
+    certified gap (bf16 with the float finishing phase), against the same members solved
+    one after another and against the batch in float; the FP64 CPU oracle on the same
+    members (bounded sample)."""
+    import numpy as np
     import torch
 
     import paper_1512_01383_amd as S
@@ -504,79 +558,169 @@ def bench_batch(args):
     wls = W.batch()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    pli = sum(w.H * w.W * w.k for w in wls)
-    n_it = (args.batch_iters + 5) // 6 * 6
+    storage = args.storage
+    pli_it = sum(w.H * w.W * w.k for w in wls)
 
-    b = S.BatchProblem(wls, storage=args.storage, device=dev)
+    b = S.BatchProblem(wls, storage=storage, device=dev, adaptive=True, check_every=CHECK_BATCH)
     tiling = b.autotune(iters=12)
-    b.run(12)
+    b.set_finishing(0)            # the throughput steps stay in the requested storage
+    stream = b.stream
+
+    def step():
+        b.run_to_gap(0.0, CHECK_BATCH)   # rel_gap 0 is never met: no member retires
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.run(n_it)
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    agg = pli * n_it / t_batch
-    bytes_it = sum(algorithmic_bytes_per_pixel(w.k, w.rho, w.M, args.storage == "bf16", False) * w.H * w.W
-                   for w in wls)
+    dt = time.perf_counter() - t0
+    value = pli_it * CHECK_BATCH * args.steps / dt
+
+    # dominant kernel: HIP events on the batch's stream around graph-replayed iterations
+    n_k = (args.batch_iters + 5) // 6 * 6
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.run(n_k)
+    ev1.record(stream)
+    ev1.synchronize()
+    kern_ms = ev0.elapsed_time(ev1) / n_k
+    bytes_launch = sum(algorithmic_bytes_per_pixel(w.k, w.rho, w.M, storage == "bf16", False) * w.H * w.W
+                       for w in wls)
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
     b.close()
 
-    # the same iterations, one instance after another
+    # the same iterations, one instance after another (single-instance path, same storage)
     t_seq = 0.0
     for w in wls:
-        g = S.Problem.from_workload(w, storage=args.storage, device=dev)
+        g = S.Problem.from_workload(w, storage=storage, device=dev)
         g.run(12)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g.run(n_it)
+        t1 = time.perf_counter()
+        g.run(n_k)
         torch.cuda.synchronize()
-        t_seq += time.perf_counter() - t0
+        t_seq += time.perf_counter() - t1
         g.close()
 
     gap = None
-    if args.batch_gap > 0:
-        b = S.BatchProblem(wls, storage=args.storage, device=dev, adaptive=True)
-        b.set_tiling(*tiling)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        done = b.run_to_gap(args.batch_gap, args.gap_max_iters)
-        t_b = time.perf_counter() - t0
-        reached = sum(1 for i in range(len(wls)) if not b.info_of(i)[1])
-        b.close()
+    if not args.no_gap:
+        gap = {"tol": 1e-3, "max_iters": args.gap_max_iters}
+        for mode in ("batch_" + storage, "batch_fp32") if storage == "bf16" else ("batch_fp32",):
+            st = "bf16" if mode == "batch_bf16" else "fp32"
+            b = S.BatchProblem(wls, storage=st, device=dev, adaptive=True, check_every=CHECK_BATCH)
+            b.set_tiling(*tiling)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            done = b.run_to_gap(1e-3, args.gap_max_iters)
+            t_b = time.perf_counter() - t1
+            reached, worst, pli16, pli32 = 0, 0.0, 0, 0
+            for i, w in enumerate(wls):
+                n_i, active = b.info_of(i)
+                _, n16 = b.storage_info(i)
+                rep = b.energy_of(i)
+                reached += (not active) and rep["rel_gap"] <= 1e-3
+                worst = max(worst, rep["rel_gap"])
+                pli16 += w.H * w.W * w.k * n16
+                pli32 += w.H * w.W * w.k * (n_i - n16)
+            b.close()
+            gap[mode] = {"seconds": t_b, "batched_iterations": done, "members_reached": int(reached),
+                         "worst_rel_gap": worst,
+                         "pixel_label_iters_bf16": pli16, "pixel_label_iters_fp32": pli32}
         t_s, reached_s = 0.0, 0
         for w in wls:
-            g = S.Problem.from_workload(w, storage=args.storage, device=dev, adaptive=True,
-                                        check_every=48)
+            g = S.Problem.from_workload(w, storage=storage, device=dev, adaptive=True,
+                                        check_every=CHECK_BATCH)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g.run_to_gap(args.batch_gap, args.gap_max_iters)
-            t_s += time.perf_counter() - t0
-            reached_s += g.energy()["rel_gap"] <= args.batch_gap
+            t1 = time.perf_counter()
+            g.run_to_gap(1e-3, args.gap_max_iters)
+            t_s += time.perf_counter() - t1
+            reached_s += g.energy()["rel_gap"] <= 1e-3
             g.close()
-        gap = {"tol": args.batch_gap, "max_iters": args.gap_max_iters, "batch_seconds": t_b,
-               "batch_iterations": done, "batch_reached": reached, "sequential_seconds": t_s,
-               "sequential_reached": int(reached_s)}
+        gap["sequential_" + storage] = {"seconds": t_s, "members_reached": int(reached_s)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        ncores = oracle.set_threads(host_cores())
+
+        def oracle_pass(n_it, budget=None):
+            """n_it FP64 iterations of each member (one more before the clock starts, so
+            first touches of the state are not timed); stops after `budget` seconds."""
+            pli, total, members = 0, 0.0, 0
+            for w in wls:
+                o = oracle.Problem(w)
+                o.run(1)
+                t1 = time.perf_counter()
+                o.run(n_it)
+                total += time.perf_counter() - t1
+                pli += w.H * w.W * w.k * n_it
+                members += 1
+                del o
+                if budget is not None and total >= budget:
+                    break
+            return pli, total, members
+
+        # one iteration of the largest member sets the sample size
+        big_m = max(wls, key=lambda w: w.H * w.W * w.k)
+        o = oracle.Problem(big_m)
+        o.run(1)
+        t1 = time.perf_counter()
+        o.run(1)
+        rate_est = big_m.H * big_m.W * big_m.k / max(time.perf_counter() - t1, 1e-6)
+        del o
+        n_it = max(1, int(args.cpu_seconds * rate_est / pli_it))
+        pli_c, dt_cpu, _ = oracle_pass(n_it)
+        oracle.set_threads(1)
+        pli_1, dt1, m1 = oracle_pass(1, budget=args.cpu_seconds / 3)
+        oracle.set_threads(ncores)
+        cpu = {"value": pli_c / dt_cpu, "unit": "pixel-label-iter/s", "cores": ncores,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{n_it} FP64 iterations of each of the 64 instances ({dt_cpu:.1f} s; "
+                         f"problems built and first touched outside the clock)",
+               "value_1_thread": pli_1 / dt1,
+               "sample_1_thread": f"1 iteration of each of the first {m1} instances ({dt1:.1f} s)"}
+
+    extra = None
+    if not args.no_extra:
+        big = W.roofline()
+        extra = {"tq256_L20_cache_resident": single_kernel_timing(
+                     S, W.truncated_quadratic(L=20, H=256, W=256), "fp32", dev),
+                 "tq2048_L16_fp32": single_kernel_timing(S, big, "fp32", dev),
+                 "tq2048_L16_bf16": single_kernel_timing(S, big, "bf16", dev)}
 
     out = {
         "metric": "lifted PDHG pixel-label-iter/s",
-        "value": agg,
+        "value": value,
         "unit": "pixel-label-iter/s",
         "n_gpus": 1,
-        "steps": n_it,
-        "warmup": 12,
-        "ms_per_step": t_batch / n_it * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "fp32" else "f32 (bf16 dual storage)",
+        "dtype": "f32" if storage == "fp32" else "f32 (bf16 dual storage)",
         "data": "synthetic",
-        "config": {"workload": "64 truncated-quadratic instances, sizes U{64,128,256,512}^2, "
-                               "L U{2,4,8,16}, lambda=0.25; step = one batched iteration",
-                   "instances": len(wls), "pixel_label_per_iter": pli, "storage": args.storage,
+        "config": {"workload": "batched mixed precision: 64 truncated-quadratic instances, sizes "
+                               "U{64,128,256,512}^2, L U{2,4,8,16}, lambda=0.25, nu=0.025, in one "
+                               f"persistent launch per iteration; step = {CHECK_BATCH} batched "
+                               "iterations + every member's FP64 gap monitor and step balance",
+                   "instances": len(wls), "pixel_label_per_iter": pli_it, "storage": storage,
                    "tiling": list(tiling)},
-        "batch": {"seconds": t_batch, "sequential_seconds": t_seq, "speedup_vs_sequential": t_seq / t_batch,
-                  "hbm_gbs_algorithmic": bytes_it * n_it / t_batch / 1e9,
-                  "hbm_frac": bytes_it * n_it / t_batch / 1e9 / HBM_PEAK_GBS},
-        "time_to_gap": gap,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"batch64_{storage}", kernel="pdhg_batch"),
+                     "kernel": "pdhg_batch_kernel", "kernel_ms": kern_ms,
+                     "algorithmic_bytes_per_launch": bytes_launch, "kernel_hash": kernel_hash()},
+        "cpu_baseline": cpu,
+        "batch": {"seconds": dt, "iterations_timed_for_kernel": n_k,
+                  "kernel_seconds_batched": kern_ms * n_k * 1e-3, "sequential_seconds": t_seq,
+                  "speedup_vs_sequential": t_seq / (kern_ms * n_k * 1e-3)},
+        "time_to_gap_1e-3": gap,
+        "single_instance": extra,
     }
     print(json.dumps(out))
 

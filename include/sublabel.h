@@ -79,8 +79,13 @@ typedef enum { SL_RHO_QUAD = 0, SL_RHO_TRUNC_QUAD = 1, SL_RHO_SAMPLED = 2,
 typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;
 
 /* Storage precision of the iteration state. FP32: everything in float. BF16_DUAL: the
- * dual fields v, z and p are stored as bfloat16 (round to nearest even); arithmetic is
- * float, energies and gaps are accumulated in double in both modes. */
+ * dual fields v, z and p are stored as bfloat16 (round to nearest even), which cuts the
+ * bytes an iteration moves per pixel from 4(14k+3) to 40k+12; arithmetic is float,
+ * energies and gaps are accumulated in double in both modes. The rounding of bf16 duals
+ * stalls the certified gap near 1e-3 relative, so sl_run_to_gap finishes in float: once
+ * the best gap of a bf16 problem has stopped improving (sl_set_finishing), its duals are
+ * widened to float in place and the solve continues (sl_set_storage does it on request).
+ * The workspace therefore keeps float-sized dual planes in both storages. */
 typedef enum { SL_STORE_FP32 = 0, SL_STORE_BF16_DUAL = 1 } sl_storage;
 
 typedef struct {
@@ -251,6 +256,21 @@ sl_status sl_get_step_balance(sl_problem p, double *c);
  * adaptive_steps = 1 is rebalanced this way from its own residuals. Synchronises the stream.
  * sl_residuals itself takes a single-problem handle (SL_ERR_UNSUPPORTED for a batch). */
 sl_status sl_residuals(sl_problem p, double *primal, double *dual);
+
+/* FP32 finishing phase of bf16 dual storage.
+ * sl_set_storage: widen the bf16 duals (v, z, p) of problem i of a batch (i = -1: every
+ *   member; a single problem takes i = -1 or 0) to float in place, exactly (every bf16
+ *   value is a float), and iterate in float from then on; SL_STORE_BF16_DUAL on a problem
+ *   that already stores floats is SL_ERR_UNSUPPORTED (no narrowing), on a bf16 problem a
+ *   no-op. Enqueued on the handle's stream (a batch synchronises it).
+ * sl_set_finishing: sl_run_to_gap widens a bf16 problem (each batch member on its own)
+ *   after stall_checks consecutive checks in which its best certified gap did not shrink by
+ *   a relative 1e-3 (default 4; 0: never widen automatically). Applies to every member.
+ * sl_storage_info: the storage problem i (0 for a single problem) uses now and the number
+ *   of iterations it ran with bf16 duals (pointers may be NULL). */
+sl_status sl_set_storage(sl_problem p, int32_t i, sl_storage storage);
+sl_status sl_set_finishing(sl_problem p, int32_t stall_checks);
+sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *iters_bf16);
 
 /* Target ratio s of the primal to the dual residual for the adaptive balance (the residual
  * norms carry different units; the balancing rule above compares primal with s * dual).

@@ -101,6 +101,9 @@ def lib():
         L.sl_set_residual_target.argtypes = [vp, C.c_double]
         L.sl_set_step_balance.argtypes = [vp, C.c_double]
         L.sl_get_step_balance.argtypes = [vp, C.POINTER(C.c_double)]
+        L.sl_set_storage.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sl_set_finishing.argtypes = [vp, C.c_int32]
+        L.sl_storage_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.sl_solve_static.argtypes = [C.POINTER(Desc), C.c_double, C.c_int32, vp, vp,
                                       C.POINTER(Report), vp]
         L.sl_destroy.argtypes = [vp]
@@ -111,7 +114,8 @@ def lib():
                      "sl_batch_energy", "sl_batch_read_u", "sl_batch_info", "sl_set_graphs",
                      "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
                      "sl_unrolled_backward", "sl_set_step_balance", "sl_get_step_balance",
-                     "sl_residuals", "sl_set_residual_target", "sl_solve_static"):
+                     "sl_residuals", "sl_set_residual_target", "sl_solve_static",
+                     "sl_set_storage", "sl_set_finishing", "sl_storage_info"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -267,6 +271,21 @@ class Problem:
         rp, rd = C_.c_double(), C_.c_double()
         _check(lib().sl_residuals(self.h, C_.byref(rp), C_.byref(rd)))
         return rp.value, rd.value
+
+    def widen(self, i: int = -1):
+        """Widen bf16 duals to float in place (problem i of a batch, -1: all)."""
+        _check(lib().sl_set_storage(self.h, int(i), STORE_FP32))
+
+    def set_finishing(self, stall_checks: int):
+        """Checks without progress of the best gap before run_to_gap widens bf16 duals
+        (0: never)."""
+        _check(lib().sl_set_finishing(self.h, int(stall_checks)))
+
+    def storage_info(self, i: int = 0):
+        """(storage now: 'fp32' or 'bf16', iterations run with bf16 duals) of problem i."""
+        st, nb = C_.c_int32(), C_.c_int64()
+        _check(lib().sl_storage_info(self.h, int(i), C_.byref(st), C_.byref(nb)))
+        return ("bf16" if st.value == STORE_BF16_DUAL else "fp32"), nb.value
 
     def set_residual_target(self, s: float):
         """Target ratio of primal to dual residual for the adaptive balance (default 0.003)."""

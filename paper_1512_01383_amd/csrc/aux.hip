@@ -509,6 +509,13 @@ __global__ void k_fill_zero(uint4 *dst, size_t n16) {
   for (; i < n16; i += stride) dst[i] = make_uint4(0, 0, 0, 0);
 }
 
+// bf16 values widened to float (exact); src and dst must not overlap
+__global__ void k_widen_bf16(const uint16_t *__restrict__ src, float *__restrict__ dst, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = ldv(src, (long long)i);
+}
+
 __global__ void k_init_fn(const float *f, float *fn, long long N, float shift, float iscale) {
   long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < N) {
@@ -685,6 +692,14 @@ hipError_t launch_readout(const float *u, float *ulift, float *uout, const IterA
                           const MonArgs &D, hipStream_t st) {
   long long N = (long long)A.H * A.W;
   hipLaunchKernelGGL(k_readout, dim3(nblk(N, 256)), dim3(256), 0, st, u, ulift, uout, A, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_bf16(const uint16_t *src, float *dst, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  unsigned nb = (unsigned)((n + 255) / 256);
+  if (nb > 65536u) nb = 65536u;
+  hipLaunchKernelGGL(k_widen_bf16, dim3(nb), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

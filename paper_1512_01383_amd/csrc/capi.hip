@@ -61,7 +61,9 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   // padding bytes per plane spread them (measured: -5 % per iteration at 2048^2)
   if (L.ps % (1LL << 18) == 0) L.ps += 320;
   const size_t pf = (size_t)L.ps * 4;
-  const size_t pd = (size_t)L.ps * (d->storage == SL_STORE_BF16_DUAL ? 2 : 4);
+  // dual planes are laid out for float in both storages: bf16 duals fill the first half of
+  // each region and can be widened in place when a solve finishes in FP32
+  const size_t pd = pf;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -181,7 +183,14 @@ struct sl_problem_ {
   MonArgs D{};
   double shift = 0, scale = 1, lam = 0;
   double *fin_dev = nullptr;  // batch member: its monitor / residual sums go to the batch's array
+  // BF16 dual storage with an FP32 finishing phase: run_to_gap widens the duals once the
+  // best certified gap has made no progress (relative 1e-3) for finish_checks checks
+  int finish_checks = 4;   // 0: never widen automatically
+  int stall = 0;           // checks without progress so far
+  double stall_ref = -1.0; // best gap at the last progress (< 0: none yet)
+  int64_t widen_at = -1;   // iteration count at which the duals were widened (-1: not yet)
   double step_c = 1.0;  // balance of dual against primal steps (sigma * c, tau / c)
+  double step_c0 = 1.0; // the balance set by the caller (adaptive steps start from it)
   double adapt_alpha = 0.5;  // current relative change of the balance (adaptive steps)
   double adapt_s = 0.003;    // target ratio of the primal to the dual residual
   int64_t adapt_count = 0;   // balance changes made so far
@@ -213,10 +222,13 @@ struct sl_problem_ {
   bool is_batch = false;
   std::vector<sl_problem_ *> sub;
   std::vector<char> active;
+  // two work lists: list 0 holds the tiles of members that store their duals in bf16,
+  // list 1 those in float; each list is advanced by its own kernel variant per iteration
   std::vector<BatchItem> items_host;
-  std::vector<int> kcount_host;
+  int nlist[2] = {0, 0};    // items per list
+  size_t list_cap = 0;      // list 1 starts at items_dev + list_cap (fixed)
   BatchItem *items_dev = nullptr;
-  int *count_dev = nullptr, *counter_dev = nullptr;
+  int *count_dev = nullptr, *counter_dev = nullptr;   // per list, 16 ints apart
   void *ptrs_dev = nullptr;
   IterArgs *args_dev = nullptr;
   double *bfin_dev = nullptr;      // 16 doubles per member: monitor sums, residual sums
@@ -229,6 +241,7 @@ struct sl_problem_ {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_cfg = -1;
+  int graph_grid[2] = {0, 0};   // grid of each list's launch in the captured graph (0: none)
   bool use_graph = true;
 
   // unrolled differentiation: caller's workspace of checkpoints, replay states and adjoints
@@ -507,6 +520,50 @@ void state_planes(sl_problem_ *P, std::vector<const void *> &pl, std::vector<int
 }
 
 
+// ------------------------------------------------------------------------ FP32 finishing phase
+
+// Widen the bf16 duals (v, z and the current p) to float in place, staged through the
+// free u_next planes (the next iteration writes them before anything reads them); from
+// then on the problem iterates with float duals. Exact: every bf16 value is a float.
+sl_status widen_duals(sl_problem_ *P) {
+  if (!P->bf16) return SL_OK;
+  const size_t kps = (size_t)P->A.k * P->lay.ps;
+  uint16_t *stage = (uint16_t *)P->ubuf((P->iu + 1) % 3);   // k float planes = 2k bf16 planes
+  struct Part {
+    size_t from, to, n;
+  };
+  const Part parts[3] = {{P->lay.off_v, P->lay.off_v, kps},
+                         {P->lay.off_z, P->lay.off_z, kps},
+                         {P->lay.off_p + (size_t)P->ip * 2 * kps * 2, P->lay.off_p + (size_t)P->ip * 2 * kps * 4,
+                          2 * kps}};
+  for (const Part &q : parts) {
+    HIPCHK(hipMemcpyAsync(stage, P->ws + q.from, q.n * 2, hipMemcpyDeviceToDevice, P->st), "widen (staging)");
+    HIPCHK(launch_widen_bf16(stage, (float *)(P->ws + q.to), q.n, P->st), "widen");
+  }
+  P->bf16 = false;
+  P->widen_at = P->iters;
+  return SL_OK;
+}
+
+// At a check of a bf16 problem: true once the best certified gap has not improved by a
+// relative 1e-3 for finish_checks checks in a row (the duals' rounding then dominates the
+// remaining progress; in float the gap keeps shrinking).
+bool finishing_due(sl_problem_ *P) {
+  if (!P->bf16 || P->finish_checks <= 0 || !P->have_best) return false;
+  const double g = P->best_P - P->best_D;
+  if (P->stall_ref < 0.0 || g < P->stall_ref * (1.0 - 1e-3)) {
+    P->stall_ref = g;
+    P->stall = 0;
+    return false;
+  }
+  return ++P->stall >= P->finish_checks;
+}
+
+void reset_finishing(sl_problem_ *P) {
+  P->stall = 0;
+  P->stall_ref = -1.0;
+}
+
 // ------------------------------------------------------------------------ batches and tuning
 
 void set_rotation(sl_problem_ *P, int64_t n) {
@@ -523,11 +580,23 @@ sl_status reset_state(sl_problem_ *P) {
     }
     P->biters = 0;
     std::fill(P->active.begin(), P->active.end(), 1);
+    for (size_t i = 0; i < P->sub.size(); i++) P->args_host[i] = P->sub[i]->A;
+    HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
+                          hipMemcpyHostToDevice, P->st),
+           "batch parameters");
+    HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
     return SL_OK;
   }
   HIPCHK(launch_fill_zero(P->ws + P->lay.state_lo, P->lay.state_hi - P->lay.state_lo, P->st), "reset");
   P->iters = 0;
   P->have_best = false;
+  reset_finishing(P);
+  if (P->widen_at >= 0) P->widen_at = 0;   // a widened problem stays in float
+  // the adaptive balance starts again from the caller's balance
+  P->step_c = P->step_c0;
+  P->adapt_alpha = 0.5;
+  P->adapt_count = 0;
+  fill_args(P);
   set_rotation(P, 0);
   return SL_OK;
 }
@@ -536,41 +605,54 @@ int batch_tiles(const sl_problem_ *q, int th) {
   return ((q->A.H + th - 1) / th) * ((q->A.W + 63) / 64);
 }
 
+// two work lists, each with room for every tile of every member (list 1 starts at a fixed
+// offset, so the pointers captured in a graph stay valid whatever the lists hold)
 size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
   size_t items = 0;
   for (int t : maxtiles) items += (size_t)t;
-  return align256(items * sizeof(BatchItem)) + 256 + align256((size_t)n * 6 * sizeof(IterPtrs<float>)) +
+  return 2 * align256(items * sizeof(BatchItem)) + 256 + align256((size_t)n * 6 * sizeof(IterPtrs<float>)) +
          align256((size_t)n * sizeof(IterArgs)) + align256((size_t)n * 16 * sizeof(double));
 }
 
-// work list of the active instances, costliest (k x tiles) first, tiles in row-major order
+// work lists of the active instances (list 0: bf16 duals, list 1: float duals), each
+// costliest (k x tiles) first, tiles in row-major order
 sl_status batch_rebuild_items(sl_problem_ *P) {
   const int th = kIterCfg[P->cfg][1];
-  std::vector<int> order;
-  for (int i = 0; i < (int)P->sub.size(); i++)
-    if (P->active[i]) order.push_back(i);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return (long long)P->sub[a]->A.k * batch_tiles(P->sub[a], th) >
-           (long long)P->sub[b]->A.k * batch_tiles(P->sub[b], th);
-  });
   P->items_host.clear();
-  for (int i : order)
-    for (int t = 0; t < batch_tiles(P->sub[i], th); t++) P->items_host.push_back({i, t});
-  P->kcount_host.assign(1, (int)P->items_host.size());
-  if (!P->items_host.empty())
-    HIPCHK(hipMemcpyAsync(P->items_dev, P->items_host.data(), P->items_host.size() * sizeof(BatchItem),
+  for (int list = 0; list < 2; list++) {
+    std::vector<int> order;
+    for (int i = 0; i < (int)P->sub.size(); i++)
+      if (P->active[i] && P->sub[i]->bf16 == (list == 0)) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return (long long)P->sub[a]->A.k * batch_tiles(P->sub[a], th) >
+             (long long)P->sub[b]->A.k * batch_tiles(P->sub[b], th);
+    });
+    const size_t before = P->items_host.size();
+    for (int i : order)
+      for (int t = 0; t < batch_tiles(P->sub[i], th); t++) P->items_host.push_back({i, t});
+    P->nlist[list] = (int)(P->items_host.size() - before);
+  }
+  int counts[32] = {};
+  counts[0] = P->nlist[0];
+  counts[16] = P->nlist[1];
+  if (P->nlist[0] > 0)
+    HIPCHK(hipMemcpyAsync(P->items_dev, P->items_host.data(), (size_t)P->nlist[0] * sizeof(BatchItem),
                           hipMemcpyHostToDevice, P->st), "work list");
-  HIPCHK(hipMemcpyAsync(P->count_dev, P->kcount_host.data(), sizeof(int), hipMemcpyHostToDevice, P->st),
-         "work count");
+  if (P->nlist[1] > 0)
+    HIPCHK(hipMemcpyAsync(P->items_dev + P->list_cap, P->items_host.data() + P->nlist[0],
+                          (size_t)P->nlist[1] * sizeof(BatchItem), hipMemcpyHostToDevice, P->st),
+           "work list");
+  HIPCHK(hipMemcpyAsync(P->count_dev, counts, sizeof counts, hipMemcpyHostToDevice, P->st), "work count");
   HIPCHK(hipStreamSynchronize(P->st), "work list sync");
   return SL_OK;
 }
 
-BatchLaunch batch_launch(sl_problem_ *P, int phase) {
+// launch of one work list (0: bf16 duals, 1: float duals) for rotation phase `phase`
+BatchLaunch batch_launch(sl_problem_ *P, int list, int phase) {
   BatchLaunch L;
-  L.items = P->items_dev;
-  L.count = P->count_dev;
-  L.counter = P->counter_dev;
+  L.items = P->items_dev + (list == 0 ? 0 : P->list_cap);
+  L.count = P->count_dev + 16 * list;
+  L.counter = P->counter_dev + 16 * list;
   L.ptrs = P->ptrs_dev;
   L.args = P->args_dev;
   L.phase = phase;
@@ -581,15 +663,25 @@ BatchLaunch batch_launch(sl_problem_ *P, int phase) {
   int dev = 0, ncu = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, P->bf16, P->cfg, P->kmax, L.tvk));
-  long long total = 0;
-  for (size_t i = 0; i < P->sub.size(); i++) total += batch_tiles(P->sub[i], kIterCfg[P->cfg][1]);
-  L.grid = (int)std::max(1LL, std::min((long long)occ * ncu, total));
+  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, list == 0, P->cfg, P->kmax, L.tvk));
+  L.grid = (int)std::max(1LL, std::min((long long)occ * ncu, (long long)P->nlist[list]));
   return L;
 }
 
+hipError_t batch_launch_lists(sl_problem_ *P, int phase, hipStream_t st) {
+  for (int list = 0; list < 2; list++) {
+    if (P->nlist[list] == 0) continue;
+    hipError_t e = launch_pdhg_batch(P->piece, P->add, list == 0, P->cfg, batch_launch(P, list, phase), st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 sl_status batch_capture(sl_problem_ *P) {
-  if (P->gexec && P->graph_cfg == P->cfg) return SL_OK;
+  int grid[2];
+  for (int list = 0; list < 2; list++) grid[list] = P->nlist[list] ? batch_launch(P, list, 0).grid : 0;
+  if (P->gexec && P->graph_cfg == P->cfg && P->graph_grid[0] == grid[0] && P->graph_grid[1] == grid[1])
+    return SL_OK;
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
   P->gexec = nullptr;
@@ -597,8 +689,7 @@ sl_status batch_capture(sl_problem_ *P) {
   if (!P->cap) HIPCHK(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "capture stream");
   HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal), "begin capture");
   hipError_t e = hipSuccess;
-  for (int ph = 0; ph < 6 && e == hipSuccess; ph++)
-    e = launch_pdhg_batch(P->piece, P->add, P->bf16, P->cfg, batch_launch(P, ph), P->cap);
+  for (int ph = 0; ph < 6 && e == hipSuccess; ph++) e = batch_launch_lists(P, ph, P->cap);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(P->cap, &g);
   if (e != hipSuccess) return hip_fail(e, "captured launch");
@@ -606,6 +697,8 @@ sl_status batch_capture(sl_problem_ *P) {
   P->graph = g;
   HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0), "graph instantiate");
   P->graph_cfg = P->cfg;
+  P->graph_grid[0] = grid[0];
+  P->graph_grid[1] = grid[1];
   return SL_OK;
 }
 
@@ -619,8 +712,7 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
       P->biters += 6;
       iters -= 6;
     } else {
-      HIPCHK(launch_pdhg_batch(P->piece, P->add, P->bf16, P->cfg, batch_launch(P, ph), P->st),
-             "batch launch");
+      HIPCHK(batch_launch_lists(P, ph, P->st), "batch launch");
       P->biters += 1;
       iters -= 1;
     }
@@ -636,6 +728,34 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
 sl_status save_duals(sl_problem_ *P);
 sl_status residuals_enqueue(sl_problem_ *P);
 void adapt_balance(sl_problem_ *P, double rp, double rd);
+
+// the 6 pointer sets (one per rotation phase) of member i into the batch's device table
+sl_status batch_member_ptrs(sl_problem_ *P, int i, bool upload) {
+  sl_problem_ *q = P->sub[i];
+  const int iu = q->iu, is = q->is, ip = q->ip;
+  const size_t one = sizeof(IterPtrs<float>);   // the bf16 variant has the same layout
+  for (int ph = 0; ph < 6; ph++) {
+    set_rotation(q, ph);
+    const IterPtrs<float> Q = iter_ptrs_f(q);
+    memcpy(&P->ptrs_host[((size_t)i * 6 + ph) * one], &Q, one);
+  }
+  q->iu = iu;
+  q->is = is;
+  q->ip = ip;
+  if (upload)
+    HIPCHK(hipMemcpyAsync((char *)P->ptrs_dev + (size_t)i * 6 * one, &P->ptrs_host[(size_t)i * 6 * one], 6 * one,
+                          hipMemcpyHostToDevice, P->st),
+           "member pointers");
+  return SL_OK;
+}
+
+// widen member i's duals to float; it moves to the float work list at the next rebuild
+sl_status batch_widen_member(sl_problem_ *P, int i) {
+  if (!P->sub[i]->bf16) return SL_OK;
+  sl_status s = widen_duals(P->sub[i]);
+  if (s == SL_OK) s = batch_member_ptrs(P, i, true);
+  return s;
+}
 
 sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
   const int chunk = std::max(6, (P->check_every + 5) / 6 * 6);
@@ -700,6 +820,9 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       }
       if (r.rel_gap <= tol) {
         P->active[i] = 0;
+        changed = true;
+      } else if (finishing_due(P->sub[i])) {
+        if ((s = batch_widen_member(P, (int)i)) != SL_OK) return s;
         changed = true;
       }
     }
@@ -1062,6 +1185,7 @@ static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_i
       return s;
     }
     if (r.rel_gap <= rel_gap) break;
+    if (finishing_due(P) && (s = widen_duals(P)) != SL_OK) return s;
   }
   if (done) *done = n;
   return SL_OK;
@@ -1111,6 +1235,7 @@ sl_status sl_load_state(sl_problem P, const void *src, size_t bytes) {
   if (s == SL_OK) {
     P->iters = 0;
     P->have_best = false;
+    reset_finishing(P);
   }
   return s;
 }
@@ -1180,9 +1305,14 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   for (int t : maxtiles) items_bytes += (size_t)t * sizeof(BatchItem);
   B->ws = base + off;
   B->items_dev = (BatchItem *)(base + off);
-  off += align256(items_bytes);
+  B->list_cap = align256(items_bytes) / sizeof(BatchItem);
+  off += 2 * align256(items_bytes);
   B->count_dev = (int *)(base + off);
-  B->counter_dev = (int *)(base + off + 128);
+  B->counter_dev = (int *)(base + off + 128);   // per list: next item, blocks done (zero between launches)
+  if (hipError_t e0 = launch_fill_zero(base + off, 256, B->st)) {
+    delete B;
+    return hip_fail(e0, "work counters");
+  }
   off += 256;
   B->ptrs_dev = base + off;
   off += align256((size_t)n * 6 * sizeof(IterPtrs<float>));
@@ -1194,14 +1324,8 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->ptrs_host.resize((size_t)n * 6 * sizeof(IterPtrs<float>));
   B->args_host.resize(n);
   for (int i = 0; i < n; i++) {
-    sl_problem_ *q = B->sub[i];
-    for (int ph = 0; ph < 6; ph++) {
-      set_rotation(q, ph);
-      IterPtrs<float> Q = iter_ptrs_f(q);   // same layout as the bf16 variant (pointers only)
-      memcpy(&B->ptrs_host[((size_t)i * 6 + ph) * sizeof(IterPtrs<float>)], &Q, sizeof(Q));
-    }
-    set_rotation(q, 0);
-    B->args_host[i] = q->A;
+    (void)batch_member_ptrs(B, i, false);
+    B->args_host[i] = B->sub[i]->A;
   }
   static_assert(sizeof(IterPtrs<float>) == sizeof(IterPtrs<uint16_t>), "pointer sets");
   hipError_t e;
@@ -1471,19 +1595,56 @@ sl_status sl_set_step_balance(sl_problem P, double c) {
   if (!(c > 0.0) || !isfinite(c)) return fail(SL_ERR_INVALID_ARG, "the balance must be finite and > 0");
   if (P->is_batch) {
     for (size_t i = 0; i < P->sub.size(); i++) {
-      P->sub[i]->step_c = c;
+      P->sub[i]->step_c = P->sub[i]->step_c0 = c;
       fill_args(P->sub[i]);
       P->args_host[i] = P->sub[i]->A;
     }
-    P->step_c = c;
+    P->step_c = P->step_c0 = c;
     HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
                           hipMemcpyHostToDevice, P->st),
            "batch parameters");
     HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
     return SL_OK;
   }
-  P->step_c = c;
+  P->step_c = P->step_c0 = c;
   fill_args(P);
+  return SL_OK;
+}
+
+sl_status sl_set_storage(sl_problem P, int32_t i, sl_storage storage) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (storage != SL_STORE_FP32 && storage != SL_STORE_BF16_DUAL) return fail(SL_ERR_INVALID_ARG, "unknown storage kind");
+  const int n = P->is_batch ? (int)P->sub.size() : 1;
+  if (i < -1 || i >= n) return fail(SL_ERR_INVALID_ARG, "problem index %d out of range", i);
+  for (int j = (i < 0 ? 0 : i); j < (i < 0 ? n : i + 1); j++) {
+    sl_problem_ *q = P->is_batch ? P->sub[j] : P;
+    if (storage == SL_STORE_BF16_DUAL && !q->bf16)
+      return fail(SL_ERR_UNSUPPORTED, "float duals are not narrowed to bf16");
+  }
+  if (storage == SL_STORE_BF16_DUAL) return SL_OK;
+  if (!P->is_batch) return widen_duals(P);
+  for (int j = (i < 0 ? 0 : i); j < (i < 0 ? n : i + 1); j++) {
+    sl_status s = batch_widen_member(P, j);
+    if (s != SL_OK) return s;
+  }
+  return batch_rebuild_items(P);
+}
+
+sl_status sl_set_finishing(sl_problem P, int32_t stall_checks) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (stall_checks < 0) return fail(SL_ERR_INVALID_ARG, "stall_checks must be >= 0");
+  P->finish_checks = stall_checks;
+  for (sl_problem_ *q : P->sub) q->finish_checks = stall_checks;
+  return SL_OK;
+}
+
+sl_status sl_storage_info(sl_problem P, int32_t i, int32_t *storage, int64_t *iters_bf16) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  const int n = P->is_batch ? (int)P->sub.size() : 1;
+  if (i < 0 || i >= n) return fail(SL_ERR_INVALID_ARG, "problem index %d out of range", i);
+  const sl_problem_ *q = P->is_batch ? P->sub[i] : P;
+  if (storage) *storage = q->bf16 ? SL_STORE_BF16_DUAL : SL_STORE_FP32;
+  if (iters_bf16) *iters_bf16 = q->bf16 ? q->iters : (q->widen_at >= 0 ? q->widen_at : 0);
   return SL_OK;
 }
 

@@ -7,6 +7,8 @@
 //   v[k], z[k]  data-term duals (float or bf16), updated in place
 //   p[2][2k]    TV duals, double-buffered (neighbour reads of the old p): px_i at plane i,
 //               py_i at plane k+i (float or bf16)
+//               (the regions of v, z and p are sized for float in both storages, so that
+//               bf16 duals can be widened in place for the FP32 finishing phase)
 //   q[1]        scalar dual of the pointwise max of the conjugates
 //   fn[1]       data image mapped to normalised label coordinates (QUAD, TRUNC_QUAD)
 //   w[L]        per-label additive values (optional)
@@ -128,6 +130,8 @@ hipError_t launch_copy_planes(const float *src, float *dst, int nplanes, long lo
 hipError_t launch_convexify(const float *samples, float *cost, const double *taud,
                             const IterArgs &A, hipStream_t st);
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t st);
+// n bf16 values widened to float; src and dst must not overlap
+hipError_t launch_widen_bf16(const uint16_t *src, float *dst, size_t n, hipStream_t st);
 // per pixel: labels and hull tangent ranges of the (at most two) truncated-quadratic
 // intervals that straddle a band edge, packed as 2 x (label:5, ml:4, mr:4) bits, label 31 = none
 // (sinfod: the same in FP64 from f_orig for the monitor, whose hull is that of the exact samples)

@@ -404,6 +404,9 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
 
 // Batched iteration: persistent blocks pull (instance, tile) work items from a counter.
 // Per-instance pointers (one set per rotation phase) and parameters come from device tables.
+// counter[0] is the next item, counter[1] the number of blocks that found the list empty;
+// both are zero when a launch starts, and the last block to leave puts them back to zero
+// (every block has made its last pull by then), so consecutive launches need no reset.
 template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     const BatchItem *__restrict__ items, const int *__restrict__ count, int *counter,
@@ -416,14 +419,19 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(s_item);
-    if (it >= n) return;
+    if (it >= n) break;
     const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
     const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
     iter_tile<PIECE, ADD, DT, G, TH, TVK>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
   }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(counter + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(counter, 0);
+      atomicExch(counter + 1, 0);
+    }
+  }
 }
-
-__global__ void k_reset_counter(int *counter) { *counter = 0; }
 
 template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
@@ -437,7 +445,6 @@ hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
 
 template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
 hipError_t launch_bt(const BatchLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, L.counter);
   hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK>), dim3(L.grid), dim3(64 * TH * G),
                      pdhg_iter_lds_bytes(L.kmax, TH), st, L.items, L.count, L.counter,
                      (const IterPtrs<DT> *)L.ptrs, L.args, L.phase);

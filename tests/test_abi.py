@@ -37,7 +37,7 @@ def S():
 
 def test_library_exports_every_declared_entry_point(lib):
     names = _declared()
-    assert len(names) == 30, names   # the entry points of include/sublabel.h
+    assert len(names) == 33, names   # the entry points of include/sublabel.h
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -82,8 +82,9 @@ def test_workspace_size_covers_the_state_and_grows(lib, S):
     s_small = _size(lib, _desc(S, 64, 64, 8))[1]
     assert _size(lib, _desc(S, 64, 128, 8))[1] > s_small
     assert _size(lib, _desc(S, 64, 64, 16))[1] > s_small
-    # BF16 dual storage needs less than FP32
-    assert _size(lib, _desc(S, 64, 64, 8, storage=1))[1] < s_small
+    # BF16 dual storage keeps float-sized dual planes (widened in place for the FP32
+    # finishing phase), so it needs the same workspace as FP32
+    assert _size(lib, _desc(S, 64, 64, 8, storage=1))[1] == s_small
 
 
 def test_argument_checks(lib, S):

@@ -256,27 +256,33 @@ def test_bf16_single_iteration(orc, name, wl):
 
 
 def test_bf16_energy_error_at_convergence(orc):
-    """ROF 64x64: the FP32 path reaches the FP64 optimum within 1e-5 relative; with BF16
-    dual storage the iteration stalls at a quantisation floor. Its bound: a stored dual
-    carries a relative RNE error of at most 2^-9 ~ 1.95e-3, and the TV part of the primal
-    energy is linear in the resulting jitter of u, so the certified primal value may sit
-    up to ~2^-9 relative above the optimum (measured: primal 1.17e-3, dual 3.2e-4, flat
-    from 1000 to 24000 iterations). The errors are printed per result."""
+    """ROF 64x64 against the FP64 oracle. FP32 storage: 3000 iterations reach the optimum
+    within 1e-5 relative. BF16 dual storage alone stalls at a rounding floor (a stored dual
+    carries a relative error of up to 2^-9; measured on this problem: primal 1.17e-3 above
+    the optimum, flat from 1000 to 24000 iterations), so the gap-controlled solve finishes
+    in float: once the best gap stops improving, the duals are widened in place and the
+    solve continues to the 1e-3 certified gap, which bounds the energy error by 1e-3. The
+    errors and the iterations of each phase are printed per result."""
     wl = W.rof()
     o = orc.Problem(wl)
-    ro, _ = None, None
     o.run(6000)
     ro = o.monitor()
-    for storage in ("fp32", "bf16"):
-        g = S.Problem.from_workload(wl, storage=storage)
-        g.run(3000)
-        e = g.energy()
-        err_p = _rel(e["best_primal"], ro["best_primal"])
-        err_d = _rel(e["best_dual"], ro["best_dual"])
-        print(f"{storage}: primal {e['best_primal']:.8g} dual {e['best_dual']:.8g} "
-              f"rel gap {e['rel_gap']:.2e}; vs FP64 oracle (6000 its) primal {err_p:.2e} dual {err_d:.2e}")
-        bound = 1e-5 if storage == "fp32" else 2.0 ** -9
-        assert err_p < bound and err_d < bound
-        # certified bounds stay bounds of the FP64 optimum (up to the FP64 oracle's gap)
-        assert e["best_dual"] <= ro["best_primal"] * (1 + 1e-6)
-        assert e["best_primal"] >= ro["best_dual"] * (1 - 1e-6)
+    g = S.Problem.from_workload(wl, storage="fp32")
+    g.run(3000)
+    e = g.energy()
+    err_p, err_d = _rel(e["best_primal"], ro["best_primal"]), _rel(e["best_dual"], ro["best_dual"])
+    print(f"fp32 3000 its: primal {err_p:.2e} dual {err_d:.2e} vs FP64 oracle (6000 its)")
+    assert err_p < 1e-5 and err_d < 1e-5
+    g = S.Problem.from_workload(wl, storage="bf16")
+    done = g.run_to_gap(1e-3, 20000)
+    e = g.energy()
+    storage, n16 = g.storage_info()
+    err_p, err_d = _rel(e["best_primal"], ro["best_primal"]), _rel(e["best_dual"], ro["best_dual"])
+    print(f"bf16 + finishing: {done} its ({n16} with bf16 duals, now {storage}); rel gap "
+          f"{e['rel_gap']:.2e}; vs FP64 oracle primal {err_p:.2e} dual {err_d:.2e}")
+    assert e["rel_gap"] <= 1e-3
+    assert err_p <= 1e-3 and err_d <= 1e-3
+    assert 0 < n16 <= done
+    # certified bounds stay bounds of the FP64 optimum (up to the FP64 oracle's gap)
+    assert e["best_dual"] <= ro["best_primal"] * (1 + 1e-6)
+    assert e["best_primal"] >= ro["best_dual"] * (1 - 1e-6)
