@@ -243,6 +243,18 @@ struct sl_problem_ {
   int graph_cfg = -1;
   int graph_grid[2] = {0, 0};   // grid of each list's launch in the captured graph (0: none)
   bool use_graph = true;
+  // graphs of the work at a check, over every active member: 0 the duals saved before the
+  // measured iteration, 1 the residual sums, 2 the monitors and the copy of all sums to the
+  // host; each valid for one (membership version, rotation phase)
+  hipGraph_t chk_graph[3] = {};
+  hipGraphExec_t chk_exec[3] = {};
+  long long chk_key[3] = {-1, -1, -1};
+  long long members_version = 0;   // bumped whenever the work lists are rebuilt
+  // side streams (default priority) that the per-member chains of a check are spread over,
+  // and the events that fork them from and join them to the capturing stream
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
 
   // unrolled differentiation: caller's workspace of checkpoints, replay states and adjoints
   char *uws = nullptr;
@@ -252,6 +264,15 @@ struct sl_problem_ {
 
   ~sl_problem_() {
     for (sl_problem_ *q : sub) delete q;
+    for (int g = 0; g < 3; g++) {
+      if (chk_exec[g]) (void)hipGraphExecDestroy(chk_exec[g]);
+      if (chk_graph[g]) (void)hipGraphDestroy(chk_graph[g]);
+    }
+    for (int j = 0; j < kSide; j++) {
+      if (side[j]) (void)hipStreamDestroy(side[j]);
+      if (join_ev[j]) (void)hipEventDestroy(join_ev[j]);
+    }
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (pin) (void)hipHostFree(pin);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -632,6 +653,7 @@ sl_status batch_rebuild_items(sl_problem_ *P) {
       for (int t = 0; t < batch_tiles(P->sub[i], th); t++) P->items_host.push_back({i, t});
     P->nlist[list] = (int)(P->items_host.size() - before);
   }
+  P->members_version++;
   int counts[32] = {};
   counts[0] = P->nlist[0];
   counts[16] = P->nlist[1];
@@ -726,8 +748,75 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
 }
 
 sl_status save_duals(sl_problem_ *P);
-sl_status residuals_enqueue(sl_problem_ *P);
+sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev = nullptr);
 void adapt_balance(sl_problem_ *P, double rp, double rd);
+
+// Run `enqueue(stream)` (work of every active member at a check) from graph slot g: captured
+// on the private stream once per key and replayed on the batch's stream (each member's work
+// goes to the stream it is handed), or enqueued directly when graphs are off.
+template <class F>
+sl_status batch_check_graph(sl_problem_ *P, int g, F enqueue) {
+  if (!P->use_graph) return enqueue(P->st);
+  const long long key = P->members_version * 8 + P->biters % 6;
+  if (!P->chk_exec[g] || P->chk_key[g] != key) {
+    if (P->chk_exec[g]) (void)hipGraphExecDestroy(P->chk_exec[g]);
+    if (P->chk_graph[g]) (void)hipGraphDestroy(P->chk_graph[g]);
+    P->chk_exec[g] = nullptr;
+    P->chk_graph[g] = nullptr;
+    P->chk_key[g] = -1;
+    if (!P->cap) HIPCHK(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "capture stream");
+    HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    const sl_status s = enqueue(P->cap);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->cap, &gr);
+    if (s != SL_OK) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    P->chk_graph[g] = gr;
+    HIPCHK(hipGraphInstantiate(&P->chk_exec[g], gr, nullptr, nullptr, 0), "graph instantiate");
+    P->chk_key[g] = key;
+  }
+  HIPCHK(hipGraphLaunch(P->chk_exec[g], P->st), "graph launch");
+  return SL_OK;
+}
+
+// member work enqueued on stream st (the member's own stream restored afterwards)
+template <class F>
+sl_status on_stream(sl_problem_ *q, hipStream_t st, F fn) {
+  hipStream_t own = q->st;
+  q->st = st;
+  const sl_status s = fn(q);
+  q->st = own;
+  return s;
+}
+
+// The chains fn(member) of the members for which use(i) holds, spread round-robin over the
+// side streams: forked from `st` and joined back to it, so that the members' small kernels
+// can run side by side (each chain stays in order on its stream).
+template <class U, class F>
+sl_status fork_members(sl_problem_ *P, hipStream_t st, U use, F fn) {
+  for (int j = 0; j < sl_problem_::kSide; j++) {
+    if (!P->side[j]) HIPCHK(hipStreamCreateWithFlags(&P->side[j], hipStreamNonBlocking), "side stream");
+    if (!P->join_ev[j]) HIPCHK(hipEventCreateWithFlags(&P->join_ev[j], hipEventDisableTiming), "event");
+  }
+  if (!P->fork_ev) HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming), "event");
+  HIPCHK(hipEventRecord(P->fork_ev, st), "fork");
+  for (int j = 0; j < sl_problem_::kSide; j++) HIPCHK(hipStreamWaitEvent(P->side[j], P->fork_ev, 0), "fork");
+  int next = 0;
+  for (size_t i = 0; i < P->sub.size(); i++) {
+    if (!use(i)) continue;
+    const sl_status s = on_stream(P->sub[i], P->side[next], fn);
+    if (s != SL_OK) return s;
+    next = (next + 1) % sl_problem_::kSide;
+  }
+  for (int j = 0; j < sl_problem_::kSide; j++) {
+    HIPCHK(hipEventRecord(P->join_ev[j], P->side[j]), "join");
+    HIPCHK(hipStreamWaitEvent(st, P->join_ev[j], 0), "join");
+  }
+  return SL_OK;
+}
 
 // the 6 pointer sets (one per rotation phase) of member i into the batch's device table
 sl_status batch_member_ptrs(sl_problem_ *P, int i, bool upload) {
@@ -759,35 +848,56 @@ sl_status batch_widen_member(sl_problem_ *P, int i) {
 
 sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
   const int chunk = std::max(6, (P->check_every + 5) / 6 * 6);
-  int32_t n = 0;
-  while (n < max_iters) {
+  const size_t n = P->sub.size();
+  double *stage = nullptr;
+  sl_status s = pinned(P, P->bfin_host.size(), &stage);
+  if (s != SL_OK) return s;
+  auto active_adaptive = [&](size_t i) { return P->active[i] && P->sub[i]->d.adaptive_steps; };
+  int32_t done_n = 0;
+  while (done_n < max_iters) {
     bool any = false, adapt = false;
-    for (size_t i = 0; i < P->sub.size(); i++) {
+    for (size_t i = 0; i < n; i++) {
       any |= P->active[i] != 0;
-      adapt |= P->active[i] && P->sub[i]->d.adaptive_steps;
+      adapt |= active_adaptive(i);
     }
     if (!any) break;
-    const int c = std::min(chunk, max_iters - n);
-    sl_status s;
+    const int c = std::min(chunk, max_iters - done_n);
     if (adapt) {
       // as for a single problem: the interval's last iteration measures each member's
-      // residuals, which rebalance that member's steps (parameter table re-uploaded; a
-      // captured graph reads it from device memory)
+      // residuals, which rebalance that member's steps
       if ((s = batch_enqueue(P, c - 1)) != SL_OK) return s;
-      for (size_t i = 0; i < P->sub.size(); i++)
-        if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = save_duals(P->sub[i])) != SL_OK) return s;
+      s = batch_check_graph(P, 0, [&](hipStream_t st) {
+        return fork_members(P, st, active_adaptive, [](sl_problem_ *q) { return save_duals(q); });
+      });
+      if (s != SL_OK) return s;
       if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
-      for (size_t i = 0; i < P->sub.size(); i++)
-        if (P->active[i] && P->sub[i]->d.adaptive_steps && (s = residuals_enqueue(P->sub[i])) != SL_OK) return s;
-      double *stage = nullptr;
-      if ((s = pinned(P, P->bfin_host.size(), &stage)) != SL_OK) return s;
-      HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double),
-                            hipMemcpyDeviceToHost, P->st),
-             "residual copy");
-      HIPCHK(hipStreamSynchronize(P->st), "residual sync");
-      memcpy(P->bfin_host.data(), stage, P->bfin_host.size() * sizeof(double));
-      for (size_t i = 0; i < P->sub.size(); i++) {
-        if (!P->active[i] || !P->sub[i]->d.adaptive_steps) continue;
+      s = batch_check_graph(P, 1, [&](hipStream_t st) {
+        return fork_members(P, st, active_adaptive, [P](sl_problem_ *q) {
+          size_t i = 0;
+          while (P->sub[i] != q) i++;
+          return residuals_enqueue(q, P->args_dev + i);
+        });
+      });
+      if (s != SL_OK) return s;
+    } else if ((s = batch_enqueue(P, c)) != SL_OK) {
+      return s;
+    }
+    done_n += c;
+    // every active member's monitor, then one copy of all sums and one wait
+    s = batch_check_graph(P, 2, [&](hipStream_t st) {
+      const sl_status r = fork_members(P, st, [&](size_t i) { return P->active[i] != 0; },
+                                       [](sl_problem_ *q) { return monitor_enqueue(q); });
+      if (r != SL_OK) return r;
+      HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+             "check copy");
+      return SL_OK;
+    });
+    if (s != SL_OK) return s;
+    HIPCHK(hipStreamSynchronize(P->st), "check sync");
+    memcpy(P->bfin_host.data(), stage, P->bfin_host.size() * sizeof(double));
+    if (adapt) {
+      for (size_t i = 0; i < n; i++) {
+        if (!active_adaptive(i)) continue;
         adapt_balance(P->sub[i], P->bfin_host[i * 16 + 8], P->bfin_host[i * 16 + 9]);
         P->args_host[i] = P->sub[i]->A;
       }
@@ -795,27 +905,14 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
                             hipMemcpyHostToDevice, P->st),
              "batch parameters");
       HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
-    } else if ((s = batch_enqueue(P, c)) != SL_OK) {
-      return s;
     }
-    n += c;
-    // every active member's monitor, then one copy and one wait for all of them
-    for (size_t i = 0; i < P->sub.size(); i++)
-      if (P->active[i] && (s = monitor_enqueue(P->sub[i])) != SL_OK) return s;
-    double *stage = nullptr;
-    if ((s = pinned(P, P->bfin_host.size(), &stage)) != SL_OK) return s;
-    HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double),
-                          hipMemcpyDeviceToHost, P->st),
-           "monitor copy");
-    HIPCHK(hipStreamSynchronize(P->st), "monitor sync");
-    memcpy(P->bfin_host.data(), stage, P->bfin_host.size() * sizeof(double));
     bool changed = false;
-    for (size_t i = 0; i < P->sub.size(); i++) {
+    for (size_t i = 0; i < n; i++) {
       if (!P->active[i]) continue;
       memcpy(P->sub[i]->fin, &P->bfin_host[i * 16], 7 * sizeof(double));
       sl_report r;
       if ((s = monitor_finish(P->sub[i], &r)) != SL_OK) {
-        if (done) *done = n;
+        if (done) *done = done_n;
         return s;
       }
       if (r.rel_gap <= tol) {
@@ -828,7 +925,7 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
     }
     if (changed && (s = batch_rebuild_items(P)) != SL_OK) return s;
   }
-  if (done) *done = n;
+  if (done) *done = done_n;
   return SL_OK;
 }
 
@@ -852,7 +949,7 @@ double *res_out(sl_problem_ *P) {
 
 // residual norms of the iteration that followed save_duals, enqueued (2 sums at res_out(P));
 // residuals_of_last also waits for them
-sl_status residuals_enqueue(sl_problem_ *P) {
+sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
   const int k = P->A.k;
   const size_t pdb = (size_t)P->lay.ps * P->esz();
   char *ys = P->ws + P->lay.off_ysave;
@@ -870,7 +967,7 @@ sl_status residuals_enqueue(sl_problem_ *P) {
   R.p = P->pbuf(P->ip);
   R.po = P->pbuf(1 - P->ip);
   R.part = (double *)(P->ws + P->lay.off_rpart);
-  HIPCHK(launch_residuals(P->bf16, R, P->A, res_out(P), P->st), "residuals");
+  HIPCHK(launch_residuals(P->bf16, R, P->A, res_out(P), P->st, A_dev), "residuals");
   return SL_OK;
 }
 

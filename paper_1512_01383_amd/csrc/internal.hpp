@@ -179,4 +179,6 @@ struct ResPtrs {
   double *part;
 };
 int residual_blocks(const IterArgs &A);
-hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st);
+// A_dev (may be NULL): read the parameters from this device copy of A instead of the argument
+hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st,
+                            const IterArgs *A_dev = nullptr);

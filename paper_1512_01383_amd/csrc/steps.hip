@@ -14,7 +14,7 @@ namespace {
 constexpr int RB = 256;
 
 template <typename DT>
-__global__ __launch_bounds__(RB) void k_residuals(ResPtrs R, IterArgs A) {
+__device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs &A) {
   __shared__ double sp_[RB], sd_[RB];
   const DT *v = (const DT *)R.v, *z = (const DT *)R.z, *vo = (const DT *)R.vo, *zo = (const DT *)R.zo;
   const DT *p = (const DT *)R.p, *po = (const DT *)R.po;
@@ -76,6 +76,18 @@ __global__ __launch_bounds__(RB) void k_residuals(ResPtrs R, IterArgs A) {
   }
 }
 
+template <typename DT>
+__global__ __launch_bounds__(RB) void k_residuals(ResPtrs R, IterArgs A) {
+  residuals_body<DT>(R, A);
+}
+
+// the same with the problem's parameters read from device memory (a batch's table, which
+// the adaptive balance rewrites between checks while a captured graph keeps its arguments)
+template <typename DT>
+__global__ __launch_bounds__(RB) void k_residuals_tab(ResPtrs R, const IterArgs *__restrict__ Ap) {
+  residuals_body<DT>(R, *Ap);
+}
+
 __global__ __launch_bounds__(RB) void k_sum_pairs(const double *part, int nb, double *out) {
   __shared__ double a[RB], b[RB];
   double x = 0.0, y = 0.0;
@@ -107,12 +119,19 @@ int residual_blocks(const IterArgs &A) {
   return (int)(nb < 1024 ? nb : 1024);
 }
 
-hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st) {
+hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, double *out, hipStream_t st,
+                            const IterArgs *A_dev) {
   const int nb = residual_blocks(A);
-  if (bf16)
+  if (A_dev) {
+    if (bf16)
+      hipLaunchKernelGGL(k_residuals_tab<uint16_t>, dim3(nb), dim3(RB), 0, st, R, A_dev);
+    else
+      hipLaunchKernelGGL(k_residuals_tab<float>, dim3(nb), dim3(RB), 0, st, R, A_dev);
+  } else if (bf16) {
     hipLaunchKernelGGL(k_residuals<uint16_t>, dim3(nb), dim3(RB), 0, st, R, A);
-  else
+  } else {
     hipLaunchKernelGGL(k_residuals<float>, dim3(nb), dim3(RB), 0, st, R, A);
+  }
   hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, st, (const double *)R.part, nb, out);
   return hipGetLastError();
 }

@@ -93,12 +93,16 @@ def test_adaptive_run_reaches_gap_and_brackets_oracle(orc):
     assert g2.get_step_balance() == c and g2.energy()["best_primal"] == e["best_primal"]
 
 
-def test_batch_adaptive_members_equal_lone_adaptive_runs():
+@pytest.mark.parametrize("graphs", [True, False], ids=["graphs", "eager"])
+def test_batch_adaptive_members_equal_lone_adaptive_runs(graphs):
     """Every batch member is rebalanced from its own residuals exactly as a lone adaptive
-    solve with the same tiling and check interval: same iterations, same iterates."""
+    solve with the same tiling and check interval: same iterations, same iterates, whether
+    the iterations and the per-check work (saved duals, residuals, monitors) are replayed
+    from graphs or launched eagerly."""
     wls = [W.truncated_quadratic(L=4, H=24, W=70, seed=61), W.truncated_quadratic(L=6, H=30, W=64, seed=62),
            W.truncated_quadratic(L=8, H=16, W=90, seed=63)]
     b = S.BatchProblem(wls, check_every=48, adaptive=True)
+    b.set_graphs(graphs)
     tiling = b.get_tiling()
     b.run_to_gap(1e-3, 30000)
     for i, wl in enumerate(wls):
