@@ -197,13 +197,14 @@ sl_status sl_batch_info(sl_problem p, int32_t i, int64_t *iters, int32_t *active
 sl_status sl_set_graphs(sl_problem p, int32_t enable);
 
 /* Tile-shape autotuner: times `iters` iterations with every tiling that fits, keeps the
- * fastest, then resets the iteration state to its initial value (call it before
- * iterating). With a cache file (may be NULL) a tiling measured before for the same
- * device, kernel variant, label count and size bucket (power of two of the pixel count) is
- * reused without timing, and new measurements are appended as lines "key|tiling". The
- * chosen (label_groups, tile_rows) are returned (pointers may be NULL). Synchronises. */
+ * fastest, then resets the iteration state (and the adaptive step balance) to its initial
+ * value (call it before iterating). With a cache file (may be NULL) a tiling measured
+ * before for the same device, kernel variant (data term, storage, TV kind), label count and
+ * size bucket (power of two of the pixel count) is reused without timing, and new
+ * measurements are appended as lines "key|tiling". The chosen (label_groups, tile_rows,
+ * tile_cols) are returned (pointers may be NULL). Synchronises. */
 sl_status sl_autotune(sl_problem p, int32_t iters, const char *cache_path, int32_t *label_groups,
-                      int32_t *tile_rows);
+                      int32_t *tile_rows, int32_t *tile_cols);
 
 /* Unrolled differentiation (gradients of a function of the read-out u after K iterations
  * with respect to f, lambda and the additive values w, for learning data terms).
@@ -280,14 +281,18 @@ sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *it
  * and > 0. */
 sl_status sl_set_residual_target(sl_problem p, double s);
 
-/* Tuning knobs of the fused iteration: a block works on a tile of 64 columns x
+/* Tuning knobs of the fused iteration: a block works on a tile of tile_cols columns x
  * tile_rows rows with label_groups groups of wavefronts, each walking a contiguous chunk
- * of the labels. Supported (label_groups, tile_rows): (1,4), (1,8), (2,4), (2,8), (4,4);
- * (0,0) restores the automatic choice made by sl_create. The iterates differ between
- * tilings only by FP32 rounding of the label-chunk partial sums. Returns
- * SL_ERR_UNSUPPORTED if the tiling needs more LDS than a workgroup may use. */
-sl_status sl_set_tiling(sl_problem p, int32_t label_groups, int32_t tile_rows);
-sl_status sl_get_tiling(sl_problem p, int32_t *label_groups, int32_t *tile_rows);
+ * of the labels; with tile_cols = 128 every lane handles two horizontally adjacent pixels
+ * (64- and 32-bit accesses instead of 32- and 16-bit ones: half the memory instructions per
+ * pixel; the image width must be even, in a batch every member's). Supported (label_groups,
+ * tile_rows): (1,4), (1,8), (2,4), (2,8), (4,4), each with tile_cols 64 or 128; (0,0,0)
+ * restores the automatic choice made by sl_create. The iterates differ between tilings only
+ * by FP32 rounding of the label-chunk partial sums (tilings with the same label_groups give
+ * bitwise the same iterates). Returns SL_ERR_UNSUPPORTED if the tiling needs more LDS than a
+ * workgroup may use, or pixel pairs on an odd width. */
+sl_status sl_set_tiling(sl_problem p, int32_t label_groups, int32_t tile_rows, int32_t tile_cols);
+sl_status sl_get_tiling(sl_problem p, int32_t *label_groups, int32_t *tile_rows, int32_t *tile_cols);
 
 /* Matching costs of the stereo experiment (Sec. 5.4), the sampled data term of a stereo
  * problem (samples for SL_RHO_SAMPLED with tau_m = m, m = 0..D-1): for every pixel (r, c)

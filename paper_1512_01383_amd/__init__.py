@@ -84,16 +84,17 @@ def lib():
         L.sl_state_size.argtypes = [vp, C.POINTER(sz)]
         L.sl_save_state.argtypes = [vp, vp, sz]
         L.sl_load_state.argtypes = [vp, vp, sz]
-        L.sl_set_tiling.argtypes = [vp, C.c_int32, C.c_int32]
+        L.sl_set_tiling.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.sl_stereo_costs.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, vp]
-        L.sl_get_tiling.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sl_get_tiling.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.sl_batch_workspace_size.argtypes = [C.POINTER(Desc), C.c_int32, C.POINTER(sz)]
         L.sl_batch_create.argtypes = [C.POINTER(Desc), C.c_int32, vp, sz, vp, C.POINTER(vp)]
         L.sl_batch_energy.argtypes = [vp, C.c_int32, C.POINTER(Report)]
         L.sl_batch_read_u.argtypes = [vp, C.c_int32, vp, vp]
         L.sl_batch_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
         L.sl_set_graphs.argtypes = [vp, C.c_int32]
-        L.sl_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sl_autotune.argtypes = [vp, C.c_int32, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]
         L.sl_unrolled_workspace_size.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(sz)]
         L.sl_unrolled_forward.argtypes = [vp, C.c_int32, C.c_int32, vp, sz]
         L.sl_unrolled_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -301,20 +302,20 @@ class Problem:
         return c.value
 
     def autotune(self, iters: int = 20, cache: Optional[str] = None):
-        """Pick the fastest tiling (resets the iteration state); returns (groups, rows)."""
-        g, t = C.c_int32(), C.c_int32()
+        """Pick the fastest tiling (resets the iteration state); returns (groups, rows, cols)."""
+        g, t, c = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().sl_autotune(self.h, int(iters), cache.encode() if cache else None,
-                                 C.byref(g), C.byref(t)))
-        return g.value, t.value
+                                 C.byref(g), C.byref(t), C.byref(c)))
+        return g.value, t.value, c.value
 
-    def set_tiling(self, label_groups: int, tile_rows: int):
-        """(0, 0) restores the automatic choice."""
-        _check(lib().sl_set_tiling(self.h, int(label_groups), int(tile_rows)))
+    def set_tiling(self, label_groups: int, tile_rows: int, tile_cols: int = 64):
+        """(0, 0, 0) restores the automatic choice; tile_cols 128 = two pixels per lane."""
+        _check(lib().sl_set_tiling(self.h, int(label_groups), int(tile_rows), int(tile_cols)))
 
     def get_tiling(self):
-        g, t = C.c_int32(), C.c_int32()
-        _check(lib().sl_get_tiling(self.h, C.byref(g), C.byref(t)))
-        return g.value, t.value
+        g, t, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().sl_get_tiling(self.h, C.byref(g), C.byref(t), C.byref(c)))
+        return g.value, t.value, c.value
 
     def close(self):
         if getattr(self, "h", None):

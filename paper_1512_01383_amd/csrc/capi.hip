@@ -622,8 +622,10 @@ sl_status reset_state(sl_problem_ *P) {
   return SL_OK;
 }
 
-int batch_tiles(const sl_problem_ *q, int th) {
-  return ((q->A.H + th - 1) / th) * ((q->A.W + 63) / 64);
+// tiles of member q in launch configuration cfg (tile_rows x 64 * pixels-per-lane)
+int batch_tiles(const sl_problem_ *q, int cfg) {
+  const int th = kIterCfg[cfg][1], tw = 64 * kIterCfg[cfg][2];
+  return ((q->A.H + th - 1) / th) * ((q->A.W + tw - 1) / tw);
 }
 
 // two work lists, each with room for every tile of every member (list 1 starts at a fixed
@@ -638,19 +640,19 @@ size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
 // work lists of the active instances (list 0: bf16 duals, list 1: float duals), each
 // costliest (k x tiles) first, tiles in row-major order
 sl_status batch_rebuild_items(sl_problem_ *P) {
-  const int th = kIterCfg[P->cfg][1];
+  const int cfg = P->cfg;   // tiles per member depend on the launch configuration
   P->items_host.clear();
   for (int list = 0; list < 2; list++) {
     std::vector<int> order;
     for (int i = 0; i < (int)P->sub.size(); i++)
       if (P->active[i] && P->sub[i]->bf16 == (list == 0)) order.push_back(i);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      return (long long)P->sub[a]->A.k * batch_tiles(P->sub[a], th) >
-             (long long)P->sub[b]->A.k * batch_tiles(P->sub[b], th);
+      return (long long)P->sub[a]->A.k * batch_tiles(P->sub[a], cfg) >
+             (long long)P->sub[b]->A.k * batch_tiles(P->sub[b], cfg);
     });
     const size_t before = P->items_host.size();
     for (int i : order)
-      for (int t = 0; t < batch_tiles(P->sub[i], th); t++) P->items_host.push_back({i, t});
+      for (int t = 0; t < batch_tiles(P->sub[i], cfg); t++) P->items_host.push_back({i, t});
     P->nlist[list] = (int)(P->items_host.size() - before);
   }
   P->members_version++;
@@ -1051,9 +1053,20 @@ sl_status unrolled_check(const sl_problem_ *P, int K, int C) {
   return SL_OK;
 }
 
+// the configuration's LDS fits a workgroup, and pixel pairs (two pixels per lane) only for
+// even image widths (every member's, in a batch)
 bool cfg_fits(const sl_problem_ *P, int cfg) {
   const int k = P->is_batch ? P->kmax : P->A.k;
-  return pdhg_iter_lds_bytes(k, kIterCfg[cfg][1]) + pdhg_iter_static_lds(cfg) <= (size_t)P->maxlds;
+  if (kIterCfg[cfg][2] == 2) {
+    if (P->is_batch) {
+      for (const sl_problem_ *q : P->sub)
+        if (q->A.W % 2) return false;
+    } else if (P->A.W % 2) {
+      return false;
+    }
+  }
+  return pdhg_iter_lds_bytes(k, kIterCfg[cfg][0], kIterCfg[cfg][1], kIterCfg[cfg][2]) + pdhg_iter_static_lds(cfg) <=
+         (size_t)P->maxlds;
 }
 
 // Label groups: one wavefront walks all labels of its row unless the image has too few
@@ -1474,7 +1487,7 @@ sl_status sl_set_graphs(sl_problem P, int32_t enable) {
 // iteration state to its initial value. With a cache file, a tiling measured before for
 // the same device, kernel variant, label count and size bucket is reused.
 sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32_t *label_groups,
-                      int32_t *tile_rows) {
+                      int32_t *tile_rows, int32_t *tile_cols) {
   if (!P || iters < 1) return fail(SL_ERR_INVALID_ARG, "need a handle and iters >= 1");
   int dev = 0;
   HIPCHK(hipGetDevice(&dev), "device");
@@ -1488,8 +1501,10 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
   int nb = 0;
   while ((1LL << nb) < N) nb++;
   char key[256];
-  snprintf(key, sizeof key, "%s piece=%d add=%d bf16=%d batch=%d k=%d n2=%d", prop.gcnArchName, P->piece,
-           (int)P->add, (int)P->bf16, (int)P->is_batch, P->is_batch ? P->kmax : P->A.k, nb);
+  int tv = P->A.aniso;
+  for (const sl_problem_ *q : P->sub) tv |= q->A.aniso;
+  snprintf(key, sizeof key, "%s piece=%d add=%d bf16=%d tv=%d batch=%d k=%d n2=%d", prop.gcnArchName, P->piece,
+           (int)P->add, (int)P->bf16, tv, (int)P->is_batch, P->is_batch ? P->kmax : P->A.k, nb);
   int best = -1;
   if (cache_path) {
     FILE *fp = fopen(cache_path, "r");
@@ -1508,9 +1523,16 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
     }
   }
   if (best < 0) {
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0), "event");
-    HIPCHK(hipEventCreate(&e1), "event");
+    struct Events {   // destroyed on every return path
+      hipEvent_t a = nullptr, b = nullptr;
+      ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } ev;
+    HIPCHK(hipEventCreate(&ev.a), "event");
+    HIPCHK(hipEventCreate(&ev.b), "event");
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     float best_ms = 1e30f;
     for (int c = 0; c < SLI_NCFG; c++) {
       if (!cfg_fits(P, c)) continue;
@@ -1530,8 +1552,6 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
         best = c;
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (best < 0) return fail(SL_ERR_UNSUPPORTED, "no tiling fits");
     if (cache_path) {
       FILE *fp = fopen(cache_path, "a");
@@ -1548,6 +1568,7 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
   HIPCHK(hipStreamSynchronize(P->st), "autotune sync");
   if (label_groups) *label_groups = kIterCfg[best][0];
   if (tile_rows) *tile_rows = kIterCfg[best][1];
+  if (tile_cols) *tile_cols = 64 * kIterCfg[best][2];
   return SL_OK;
 }
 
@@ -1765,27 +1786,30 @@ sl_status sl_get_step_balance(sl_problem P, double *c) {
   return SL_OK;
 }
 
-sl_status sl_set_tiling(sl_problem P, int32_t label_groups, int32_t tile_rows) {
+sl_status sl_set_tiling(sl_problem P, int32_t label_groups, int32_t tile_rows, int32_t tile_cols) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
-  if (label_groups == 0 && tile_rows == 0) {
+  if (label_groups == 0 && tile_rows == 0 && tile_cols == 0) {
     P->cfg = auto_cfg(P);
     if (P->is_batch) return batch_rebuild_items(P);
     return SL_OK;
   }
   for (int c = 0; c < SLI_NCFG; c++)
-    if (kIterCfg[c][0] == label_groups && kIterCfg[c][1] == tile_rows) {
-      if (!cfg_fits(P, c)) return fail(SL_ERR_UNSUPPORTED, "tiling needs more LDS than a workgroup may use");
+    if (kIterCfg[c][0] == label_groups && kIterCfg[c][1] == tile_rows && 64 * kIterCfg[c][2] == tile_cols) {
+      if (!cfg_fits(P, c))
+        return fail(SL_ERR_UNSUPPORTED, "tiling needs more LDS than a workgroup may use, or an even image width");
       P->cfg = c;
       if (P->is_batch) return batch_rebuild_items(P);
       return SL_OK;
     }
-  return fail(SL_ERR_INVALID_ARG, "unsupported tiling (%d label groups, %d rows)", label_groups, tile_rows);
+  return fail(SL_ERR_INVALID_ARG, "unsupported tiling (%d label groups, %d rows, %d columns)", label_groups,
+              tile_rows, tile_cols);
 }
 
-sl_status sl_get_tiling(sl_problem P, int32_t *label_groups, int32_t *tile_rows) {
-  if (!P || !label_groups || !tile_rows) return fail(SL_ERR_INVALID_ARG, "NULL argument");
+sl_status sl_get_tiling(sl_problem P, int32_t *label_groups, int32_t *tile_rows, int32_t *tile_cols) {
+  if (!P || !label_groups || !tile_rows || !tile_cols) return fail(SL_ERR_INVALID_ARG, "NULL argument");
   *label_groups = kIterCfg[P->cfg][0];
   *tile_rows = kIterCfg[P->cfg][1];
+  *tile_cols = 64 * kIterCfg[P->cfg][2];
   return SL_OK;
 }
 

@@ -70,9 +70,11 @@ struct IterPtrs {
 };
 
 // Host-side launchers (pdhg_iter.hip, aux.hip).
-// Launch configurations of the fused iteration: kIterCfg[c] = {label groups, tile rows}.
-#define SLI_NCFG 5
-extern const int kIterCfg[SLI_NCFG][2];
+// Launch configurations of the fused iteration: kIterCfg[c] = {label groups, tile rows,
+// pixels per lane}; a tile is 64 * pixels-per-lane columns wide. Two pixels per lane need an
+// even image width.
+#define SLI_NCFG 10
+extern const int kIterCfg[SLI_NCFG][3];
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
                             const void *ptrs, hipStream_t st);
 
@@ -93,7 +95,7 @@ struct BatchLaunch {
 hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
                              hipStream_t st);
 int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax, int tvk);  // blocks per CU
-size_t pdhg_iter_lds_bytes(int k, int tile_rows);   // dynamic LDS
+size_t pdhg_iter_lds_bytes(int k, int label_groups, int tile_rows, int px);   // dynamic LDS
 size_t pdhg_iter_static_lds(int cfg);
 
 // Double-precision problem parameters for the monitor (the certificate is evaluated for

@@ -59,60 +59,141 @@ __device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx
   proj_K(px, py, rad, aniso);
 }
 
+// PX consecutive pixels of one lane (PX = 1 or 2) at byte offset `off` of a plane: one
+// 32- or 64-bit range-checked buffer access (with PX = 2 the image width is even, so a
+// lane's pair never straddles a row end and its offset is 8-byte aligned, 4 for bf16)
+template <int PX>
+__device__ __forceinline__ void bldn(float (&o)[PX], const float *base, unsigned bytes, unsigned off) {
+  if constexpr (PX == 1) {
+    o[0] = bld(base, bytes, off);
+  } else {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(base, bytes), (int)off, 0, 0);
+    o[0] = __builtin_bit_cast(float, (unsigned)x[0]);
+    o[1] = __builtin_bit_cast(float, (unsigned)x[1]);
+  }
+}
+template <int PX>
+__device__ __forceinline__ void bldvn(float (&o)[PX], const float *base, unsigned bytes, unsigned off) {
+  bldn<PX>(o, base, bytes, off);
+}
+template <int PX>
+__device__ __forceinline__ void bldvn(float (&o)[PX], const uint16_t *base, unsigned bytes, unsigned off) {
+  if constexpr (PX == 1) {
+    o[0] = bldv(base, bytes, off);
+  } else {
+    const unsigned x = __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(base, bytes), (int)off, 0, 0);
+    o[0] = __uint_as_float(x << 16);
+    o[1] = __uint_as_float(x & 0xFFFF0000u);
+  }
+}
+template <int PX>
+__device__ __forceinline__ void bstn(float *base, unsigned bytes, unsigned off, const float (&x)[PX]) {
+  if constexpr (PX == 1) {
+    bst(base, bytes, off, x[0]);
+  } else {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i v = {__builtin_bit_cast(int, x[0]), __builtin_bit_cast(int, x[1])};
+    __builtin_amdgcn_raw_buffer_store_b64(v, plane_rsrc(base, bytes), (int)off, 0, 0);
+  }
+}
+template <int PX>
+__device__ __forceinline__ void bstvn(float *base, unsigned bytes, unsigned off, const float (&x)[PX]) {
+  bstn<PX>(base, bytes, off, x);
+}
+template <int PX>
+__device__ __forceinline__ void bstvn(uint16_t *base, unsigned bytes, unsigned off, const float (&x)[PX]) {
+  if constexpr (PX == 1) {
+    bstv(base, bytes, off, x[0]);
+  } else {
+    const unsigned v = (unsigned)f2bf(x[0]) | ((unsigned)f2bf(x[1]) << 16);
+    __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(base, bytes), (int)off, 0, 0);
+  }
+}
+
 // One iteration on one tile of one problem (all labels of its pixels). TVK selects the
 // projection onto K (SLI_TV_*): fixed at compile time for a lone problem, read from the
-// problem's parameters in a batch that mixes both kinds.
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+// problem's parameters in a batch that mixes both kinds. Every lane owns PX horizontally
+// adjacent pixels of its row (PX = 2 halves the memory and address instructions per pixel;
+// the arithmetic per pixel and its order are the same, so the iterates are bitwise those
+// of PX = 1 with the same label groups).
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs &A, int tile,
                                           float *dyn) {
-  constexpr int NP = TW * TH;   // pixels of a tile = threads of a label group
+  constexpr int NL = TW * TH;     // lanes of a label group
+  constexpr int NP = NL * PX;     // pixels of a tile; LDS index of (pixel e of a lane, lane) is e*NL+lt
+  constexpr int TWX = TW * PX;    // tile width in pixels
+  constexpr bool REG = PX == 1 && G == 1;   // straddle results stay in registers
   __shared__ float ex[G][NP];      // per-chunk partial sums (reused: sbar sums, then v sums)
-  __shared__ float stv[G > 1 ? 2 : 1][NP], stz[G > 1 ? 2 : 1][NP];  // straddle results (G > 1)
+  __shared__ float stv[REG ? 1 : 2][REG ? 1 : NP], stz[REG ? 1 : 2][REG ? 1 : NP];  // straddle results
   float *lsb = dyn;               // [k][NP] sbar
   float *lsa = dyn + A.k * NP;    // [k][NP] s, then the partial s update
 
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps;
   const int tid = threadIdx.x;
-  const int grp = __builtin_amdgcn_readfirstlane(tid / NP);  // one group per wavefront
-  const int lt = tid - grp * NP;
+  const int grp = __builtin_amdgcn_readfirstlane(tid / NL);  // one group per wavefront
+  const int lt = tid - grp * NL;
   const int tx = lt & 63, ty = lt >> 6;                     // one image row per wavefront
 
-  const int ntc = (W + TW - 1) / TW;
+  const int ntc = (W + TWX - 1) / TWX;
   const int r0 = (tile / ntc) * TH;
-  const int c0 = (tile % ntc) * TW;
-  const int r = r0 + ty, c = c0 + tx;
-  const bool in = r < H && c < W;
-  const long long xo = (long long)r * W + c;
+  const int c0 = (tile % ntc) * TWX;
+  const int r = r0 + ty, cb = c0 + tx * PX;                 // row, first column of the lane's pixels
+  const bool in = r < H && cb < W;
+  const long long xo = (long long)r * W + cb;
   const unsigned xb = (unsigned)xo * 4u, db = (unsigned)xo * (unsigned)sizeof(DT);
   // plane sizes and this lane's offsets for the range-checked buffer accesses
   const unsigned nb4 = (unsigned)(H * W) * 4u, nbd = (unsigned)(H * W) * (unsigned)sizeof(DT);
   const unsigned xm = in ? xb : kOOB, dm = in ? db : kOOB;
-  const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
-  const float tau_u = A.tau_c / (1.f + (float)deg);
+  float tau_u[PX];
+#pragma unroll
+  for (int e = 0; e < PX; e++) {
+    const int c = cb + e;
+    const int deg = (c < W - 1) + (c > 0) + (r < H - 1) + (r > 0);
+    tau_u[e] = A.tau_c / (1.f + (float)deg);
+  }
 
   // this group's label chunk
   const int chn = (k + G - 1) / G;
   const int i0 = grp * chn;
   const int i1 = min(k, i0 + chn);
 
-  // several groups: the straddle information is loaded first and this group's straddle
-  // inputs are gathered before the exchange of the chunk sums, so their latency overlaps
-  // the wait at its barrier (one group has no barrier there and loads them later)
-  const unsigned info_g = (G > 1 && PIECE == SLI_TRUNC && in) ? ldb(P.sinfo, xb) : 0xFFFFFFFFu;
+  // straddle information: loaded first with several groups (this group's straddle inputs are
+  // gathered before the exchange of the chunk sums, so their latency overlaps the wait at its
+  // barrier) or with pixel pairs; one group of single pixels loads it later
+  unsigned info[PX];
+#pragma unroll
+  for (int e = 0; e < PX; e++) info[e] = 0xFFFFFFFFu;
+  if (PIECE == SLI_TRUNC && in && !REG) {
+    if constexpr (PX == 1) {
+      info[0] = ldb(P.sinfo, xb);
+    } else {
+      const auto x = __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(P.sinfo, nb4), (int)xm, 0, 0);
+      info[0] = (unsigned)x[0];
+      info[1] = (unsigned)x[1];
+    }
+  }
 
   // ---- phase A: over-relaxed multiplier of the chunk, its weighted sum
-  float Tc = 0.f;
+  float Tc[PX];
+#pragma unroll
+  for (int e = 0; e < PX; e++) Tc[e] = 0.f;
   for (int i = i0; i < i1; i++) {
-    const float s = bld(P.s + (size_t)(i) * ps, nb4, xm);
-    const float sb = 2.f * s - bld(P.spi + (size_t)(i) * ps, nb4, xm);
-    Tc += A.h[i] * sb;
-    lsa[i * NP + lt] = s;
-    lsb[i * NP + lt] = sb;
+    float s[PX], sp[PX];
+    bldn<PX>(s, P.s + (size_t)(i) * ps, nb4, xm);
+    bldn<PX>(sp, P.spi + (size_t)(i) * ps, nb4, xm);
+#pragma unroll
+    for (int e = 0; e < PX; e++) {
+      const float sb = 2.f * s[e] - sp[e];
+      Tc[e] += A.h[i] * sb;
+      lsa[i * NP + e * NL + lt] = s[e];
+      lsb[i * NP + e * NL + lt] = sb;
+    }
   }
+  // several groups of single pixels: this group's straddle inputs, gathered early
   float gu = 0.f, gv = 0.f, gz = 0.f, gwl = 0.f, gwh = 0.f;
-  if (G > 1 && PIECE == SLI_TRUNC && in && grp < 2) {
-    const int i = (int)((info_g >> (13 * grp)) & 31u);
+  if (G > 1 && PX == 1 && PIECE == SLI_TRUNC && in && grp < 2) {
+    const int i = (int)((info[0] >> (13 * grp)) & 31u);
     if (i != 31) {
       gu = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
       gv = ldvb(P.vi + (size_t)(i) * ps, db);
@@ -123,86 +204,130 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       }
     }
   }
-  if (G > 1) ex[grp][lt] = Tc;
-  const float qd = bld(P.qdi, nb4, xm);
-  const float fc = PIECE != SLI_SAMPLED ? bld(P.fn, nb4, xm) : 0.f;
-  if (G > 1) __syncthreads();
-  float T = 0.f, base = 0.f;
+  if (!REG) {
 #pragma unroll
-  for (int g = 0; g < G; g++) {
-    const float e = G > 1 ? ex[g][lt] : Tc;
-    T += e;
-    if (g > grp) base += e;
+    for (int e = 0; e < PX; e++) ex[grp][e * NL + lt] = Tc[e];
   }
-  const float qn = qd - A.sig_q * (1.f + T);
-  float suf = base + Tc;   // sum_{j >= i0} h_j sbar_j
+  float qd[PX], fc[PX];
+  bldn<PX>(qd, P.qdi, nb4, xm);
+  if (PIECE != SLI_SAMPLED) {
+    bldn<PX>(fc, P.fn, nb4, xm);
+  } else {
+#pragma unroll
+    for (int e = 0; e < PX; e++) fc[e] = 0.f;
+  }
+  if (G > 1) __syncthreads();
+  float qn[PX], suf[PX];   // suf: sum_{j >= i0} h_j sbar_j
+#pragma unroll
+  for (int e = 0; e < PX; e++) {
+    float T = 0.f, base = 0.f;
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+      const float x = G > 1 ? ex[g][e * NL + lt] : Tc[e];
+      T += x;
+      if (g > grp) base += x;
+    }
+    qn[e] = qd[e] - A.sig_q * (1.f + T);
+    suf[e] = base + Tc[e];
+  }
 
   // ---- straddling truncated-quadratic intervals (at most two per pixel; their labels and
   // hull tangent range come precomputed), projected ahead of the label walk. Slot 0 is
   // done by group 0 and slot 1 by group 1 for every pixel of the tile (one group does both
-  // when G = 1), whichever group owns the label; the owner picks the result up from LDS.
-  // The suffix sum is formed exactly as the owner's walk forms it.
-  int si0 = -1, si1 = -1;
-  float sv0 = 0.f, sz0 = 0.f, sv1 = 0.f, sz1 = 0.f;   // G = 1: the results stay in registers
+  // when G = 1), whichever group owns the label; the owner picks the result up from LDS
+  // (or, with one group of single pixels, from registers). The suffix sum is formed exactly
+  // as the owner's walk forms it.
+  int si0[PX], si1[PX];
+#pragma unroll
+  for (int e = 0; e < PX; e++) si0[e] = si1[e] = -1;
+  float sv0 = 0.f, sz0 = 0.f, sv1 = 0.f, sz1 = 0.f;   // REG only
   if (PIECE == SLI_TRUNC && in) {
-    const unsigned info = G > 1 ? info_g : ldb(P.sinfo, xb);
-    if (G > 1) {
-      if ((info & 31u) != 31u) si0 = (int)(info & 31u);
-      if (((info >> 13) & 31u) != 31u) si1 = (int)((info >> 13) & 31u);
-    }
-    const int s_lo = G == 1 ? 0 : grp, s_hi = G == 1 ? 2 : min(grp + 1, 2);
+    if constexpr (REG) {
+      const unsigned inf = ldb(P.sinfo, xb);
 #pragma unroll 1
-    for (int slot = s_lo; slot < s_hi; slot++) {   // one copy of the projection code
-      const unsigned f = info >> (13 * slot);
-      const int i = (int)(f & 31u);
-      if (G == 1 ? (i < i0 || i >= i1) : i == 31) continue;
-      const int ml = (int)((f >> 5) & 15u), mr = (int)((f >> 9) & 15u);
-      float run;                        // the owner's sum_{j > i} h_j sbar_j, formed as its walk does
-      if (G == 1) {
-        run = suf;
+      for (int slot = 0; slot < 2; slot++) {   // one copy of the projection code
+        const unsigned f = inf >> (13 * slot);
+        const int i = (int)(f & 31u);
+        if (i < i0 || i >= i1) continue;
+        const int ml = (int)((f >> 5) & 15u), mr = (int)((f >> 9) & 15u);
+        float run = suf[0];             // the walk's sum_{j > i} h_j sbar_j, formed as it does
         for (int j = i0; j <= i; j++) run -= A.h[j] * lsb[j * NP + lt];
-      } else {
+        const float g0 = A.gam[i], g1 = A.gam[i + 1];
+        const float sb = lsb[i * NP + lt];
+        const float ub = 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
+        float v = ldvb(P.vi + (size_t)(i) * ps, db) + A.sig[i] * (ub + run - g0 * sb);
+        float z = ldvb(P.zi + (size_t)(i) * ps, db) + A.sig[i] * sb;
+        float y = v * A.ih[i], w = z * A.ih[i];
+        float bs = 0.f, cs = 0.f;
+        if (ADD) {
+          const float wl = ldb(P.wadd + (size_t)(i) * ps, xb);
+          const float wh = ldb(P.wadd + (size_t)(i + 1) * ps, xb);
+          bs = (wh - wl) * A.ih[i];
+          cs = -wl + bs * g0;
+          y -= bs;
+          w -= cs;
+        }
+        proj_tq_chain(A.a, fc[0], A.nu, g0, g1, ml, mr, y, w);
+        if (ADD) {
+          y += bs;
+          w += cs;
+        }
+        if (slot == 0) {
+          si0[0] = i;
+          sv0 = A.h[i] * y;
+          sz0 = A.h[i] * w;
+        } else {
+          si1[0] = i;
+          sv1 = A.h[i] * y;
+          sz1 = A.h[i] * w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PX; e++) {
+        if ((info[e] & 31u) != 31u) si0[e] = (int)(info[e] & 31u);
+        if (((info[e] >> 13) & 31u) != 31u) si1[e] = (int)((info[e] >> 13) & 31u);
+      }
+      const int s_lo = G == 1 ? 0 : grp, s_hi = G == 1 ? 2 : min(grp + 1, 2);
+#pragma unroll 1
+      for (int jj = s_lo * PX; jj < s_hi * PX; jj++) {   // (slot, pixel) pairs: one copy of the code
+        const int slot = jj / PX, e = jj - slot * PX;
+        const unsigned xe = xb + 4u * (unsigned)e, de = db + (unsigned)sizeof(DT) * (unsigned)e;
+        const unsigned f = (PX == 1 ? info[0] : ldb(P.sinfo, xe)) >> (13 * slot);
+        const int i = (int)(f & 31u);
+        if (i == 31) continue;
+        const int ml = (int)((f >> 5) & 15u), mr = (int)((f >> 9) & 15u);
         const int og = i / chn;         // group owning label i
         float ob = 0.f;
 #pragma unroll
         for (int g = 0; g < G; g++)
-          if (g > og) ob += ex[g][lt];
-        run = ob + ex[og][lt];
-        for (int j = og * chn; j <= i; j++) run -= A.h[j] * lsb[j * NP + lt];
-      }
-      const float g0 = A.gam[i], g1 = A.gam[i + 1];
-      const float sb = lsb[i * NP + lt];
-      const float ub = G > 1 ? gu : 2.f * ldb(P.u + (size_t)(i) * ps, xb) - ldb(P.up + (size_t)(i) * ps, xb);
-      float v = (G > 1 ? gv : ldvb(P.vi + (size_t)(i) * ps, db)) + A.sig[i] * (ub + run - g0 * sb);
-      float z = (G > 1 ? gz : ldvb(P.zi + (size_t)(i) * ps, db)) + A.sig[i] * sb;
-      float y = v * A.ih[i], w = z * A.ih[i];
-      float bs = 0.f, cs = 0.f;
-      if (ADD) {
-        const float wl = G > 1 ? gwl : ldb(P.wadd + (size_t)(i) * ps, xb);
-        const float wh = G > 1 ? gwh : ldb(P.wadd + (size_t)(i + 1) * ps, xb);
-        bs = (wh - wl) * A.ih[i];
-        cs = -wl + bs * g0;
-        y -= bs;
-        w -= cs;
-      }
-      proj_tq_chain(A.a, fc, A.nu, g0, g1, ml, mr, y, w);
-      if (ADD) {
-        y += bs;
-        w += cs;
-      }
-      if (G == 1) {
-        if (slot == 0) {
-          si0 = i;
-          sv0 = A.h[i] * y;
-          sz0 = A.h[i] * w;
-        } else {
-          si1 = i;
-          sv1 = A.h[i] * y;
-          sz1 = A.h[i] * w;
+          if (g > og) ob += ex[g][e * NL + lt];
+        float run = ob + ex[og][e * NL + lt];   // the owner's sum_{j > i} h_j sbar_j
+        for (int j = og * chn; j <= i; j++) run -= A.h[j] * lsb[j * NP + e * NL + lt];
+        const float g0 = A.gam[i], g1 = A.gam[i + 1];
+        const float sb = lsb[i * NP + e * NL + lt];
+        const bool early = G > 1 && PX == 1;  // inputs gathered before the barrier
+        const float ub = early ? gu : 2.f * ldb(P.u + (size_t)(i) * ps, xe) - ldb(P.up + (size_t)(i) * ps, xe);
+        float v = (early ? gv : ldvb(P.vi + (size_t)(i) * ps, de)) + A.sig[i] * (ub + run - g0 * sb);
+        float z = (early ? gz : ldvb(P.zi + (size_t)(i) * ps, de)) + A.sig[i] * sb;
+        float y = v * A.ih[i], w = z * A.ih[i];
+        float bs = 0.f, cs = 0.f;
+        if (ADD) {
+          const float wl = early ? gwl : ldb(P.wadd + (size_t)(i) * ps, xe);
+          const float wh = early ? gwh : ldb(P.wadd + (size_t)(i + 1) * ps, xe);
+          bs = (wh - wl) * A.ih[i];
+          cs = -wl + bs * g0;
+          y -= bs;
+          w -= cs;
         }
-      } else {
-        stv[slot][lt] = A.h[i] * y;
-        stz[slot][lt] = A.h[i] * w;
+        const float fce = PX == 1 ? fc[0] : ldb(P.fn, xe);
+        proj_tq_chain(A.a, fce, A.nu, g0, g1, ml, mr, y, w);
+        if (ADD) {
+          y += bs;
+          w += cs;
+        }
+        stv[slot][e * NL + lt] = A.h[i] * y;
+        stz[slot][e * NL + lt] = A.h[i] * w;
       }
     }
   }
@@ -212,10 +337,10 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   // ---- label walk: every wavefront on its own (no barrier). The stencil needs ubar on
   // the rows above and below and p on the row above: each wavefront loads those rows and
   // recomputes p of the row above (the same expression its owner evaluates, so bitwise the
-  // same value); the left and right neighbours within the row come from the adjacent lane,
-  // and at the tile's edges from a four-lane gather of ubar at (r, c0-1), (r+1, c0-1),
-  // (r, c0+64), (r-1, c0+64) and p at (r, c0-1). The next label step's loads are in flight
-  // during the current one.
+  // same value); the left and right neighbours within the row come from the lane's other
+  // pixel or the adjacent lane, and at the tile's edges from a four-lane gather of ubar at
+  // (r, c0-1), (r+1, c0-1), (r, c0+TWX), (r-1, c0+TWX) and p at (r, c0-1). The next label
+  // step's loads are in flight during the current one.
   const unsigned W4 = (unsigned)W * 4u, WD = (unsigned)W * (unsigned)sizeof(DT);
   const unsigned xm_up = (in && r > 0) ? xb - W4 : kOOB;        // row above
   const unsigned xm_dn = (in && r + 1 < H) ? xb + W4 : kOOB;    // row below
@@ -228,43 +353,52 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     er = r + 1;
     ev = c0 > 0 && r + 1 < H;
   } else if (tx == 2) {
-    ec = c0 + TW;
-    ev = c0 + TW < W && r < H;
+    ec = c0 + TWX;
+    ev = c0 + TWX < W && r < H;
   } else if (tx == 3) {
     er = r - 1;
-    ec = c0 + TW;
-    ev = c0 + TW < W && r > 0 && r <= H;
+    ec = c0 + TWX;
+    ev = c0 + TWX < W && r > 0 && r <= H;
   }
   const unsigned em = ev ? (unsigned)((long long)er * W + ec) * 4u : kOOB;
   const unsigned eml = (tx == 0 && c0 > 0 && r < H) ? (unsigned)((long long)r * W + c0 - 1) * (unsigned)sizeof(DT) : kOOB;
   struct Step {
-    float u, up, uu, uup, ud, udp, px, py, pxu, pyu, v, z, eu, eup, epx, epy, wh;
+    float u[PX], up[PX], uu[PX], uup[PX], ud[PX], udp[PX], px[PX], py[PX], pxu[PX], pyu[PX], v[PX], z[PX],
+        wh[PX];
+    float eu, eup, epx, epy;
   };
   // past the chunk the planes have size 0 (nothing is read)
   auto load_step = [&](int i, Step &o) {
     const unsigned b4 = i < i1 ? nb4 : 0u, bd = i < i1 ? nbd : 0u;
     const float *pu = P.u + (size_t)i * ps, *pup = P.up + (size_t)i * ps;
     const DT *ppx = P.pin + (size_t)i * ps, *ppy = P.pin + (size_t)(k + i) * ps;
-    o.u = bld(pu, b4, xm);
-    o.up = bld(pup, b4, xm);
-    o.uu = bld(pu, b4, xm_up);
-    o.uup = bld(pup, b4, xm_up);
-    o.ud = bld(pu, b4, xm_dn);
-    o.udp = bld(pup, b4, xm_dn);
-    o.px = bldv(ppx, bd, dm);
-    o.py = bldv(ppy, bd, dm);
-    o.pxu = bldv(ppx, bd, dm_up);
-    o.pyu = bldv(ppy, bd, dm_up);
-    o.v = bldv(P.vi + (size_t)i * ps, bd, dm);
-    o.z = bldv(P.zi + (size_t)i * ps, bd, dm);
+    bldn<PX>(o.u, pu, b4, xm);
+    bldn<PX>(o.up, pup, b4, xm);
+    bldn<PX>(o.uu, pu, b4, xm_up);
+    bldn<PX>(o.uup, pup, b4, xm_up);
+    bldn<PX>(o.ud, pu, b4, xm_dn);
+    bldn<PX>(o.udp, pup, b4, xm_dn);
+    bldvn<PX>(o.px, ppx, bd, dm);
+    bldvn<PX>(o.py, ppy, bd, dm);
+    bldvn<PX>(o.pxu, ppx, bd, dm_up);
+    bldvn<PX>(o.pyu, ppy, bd, dm_up);
+    bldvn<PX>(o.v, P.vi + (size_t)i * ps, bd, dm);
+    bldvn<PX>(o.z, P.zi + (size_t)i * ps, bd, dm);
     o.eu = bld(pu, b4, em);
     o.eup = bld(pup, b4, em);
     o.epx = bldv(ppx, bd, eml);
     o.epy = bldv(ppy, bd, eml);
-    o.wh = ADD ? bld(P.wadd + (size_t)(i + 1) * ps, b4, xm) : 0.f;
+    if (ADD) {
+      bldn<PX>(o.wh, P.wadd + (size_t)(i + 1) * ps, b4, xm);
+    } else {
+#pragma unroll
+      for (int e = 0; e < PX; e++) o.wh[e] = 0.f;
+    }
   };
-  float pre = 0.f;                  // sum of the chunk's new v so far
-  float wlo = (ADD && i0 < i1) ? bld(P.wadd + (size_t)(i0) * ps, nb4, xm) : 0.f;
+  float pre[PX], wlo[PX];           // sum of the chunk's new v so far; additive value at label i
+#pragma unroll
+  for (int e = 0; e < PX; e++) pre[e] = wlo[e] = 0.f;
+  if (ADD && i0 < i1) bldn<PX>(wlo, P.wadd + (size_t)(i0) * ps, nb4, xm);
 
   auto label_step = [&](int i, const Step &cu, Step &nx) {
     // one group: the block's rows stay in step, so a row fetched for its neighbours is
@@ -274,87 +408,109 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     const float rad = A.lam * A.h[i];
     const float spg = A.sig_p;
     const bool aniso = TVK == SLI_TV_PER_PROBLEM ? A.aniso != 0 : TVK == SLI_TV_BOX;
-    const float ub = 2.f * cu.u - cu.up;
-    const float ubu = 2.f * cu.uu - cu.uup;
-    const float ubd = 2.f * cu.ud - cu.udp;
+    float ub[PX], ubu[PX], ubd[PX];
+#pragma unroll
+    for (int e = 0; e < PX; e++) {
+      ub[e] = 2.f * cu.u[e] - cu.up[e];
+      ubu[e] = 2.f * cu.uu[e] - cu.uup[e];
+      ubd[e] = 2.f * cu.ud[e] - cu.udp[e];
+    }
     const float eub = 2.f * cu.eu - cu.eup;
     const float ubL = rdlane(eub, 0), ubLd = rdlane(eub, 1), ubR = rdlane(eub, 2), ubRu = rdlane(eub, 3);
     // lane shifts with every lane active (a lane masked off would read as out of range)
-    const float ubr = from_right(ub, ubR), ubur = from_right(ubu, ubRu);
-    // own p
-    float px = cu.px, py = cu.py;
-    p_step(px, py, spg, (c < W - 1) ? ubr - ub : 0.f, (r < H - 1) ? ubd - ub : 0.f, rad, aniso);
-    // p of the row above (only its y part enters div p)
-    float pxu = cu.pxu, pyu = cu.pyu;
-    p_step(pxu, pyu, spg, (c < W - 1) ? ubur - ubu : 0.f, ub - ubu, rad, aniso);
+    const float ubrn = from_right(ub[0], ubR), ubrun = from_right(ubu[0], ubRu);
+    float px[PX], py[PX], pxu[PX], pyu[PX];
+#pragma unroll
+    for (int e = 0; e < PX; e++) {
+      const int c = cb + e;
+      const float ubr = e + 1 < PX ? ub[e + 1 < PX ? e + 1 : 0] : ubrn;
+      const float ubur = e + 1 < PX ? ubu[e + 1 < PX ? e + 1 : 0] : ubrun;
+      // own p
+      px[e] = cu.px[e];
+      py[e] = cu.py[e];
+      p_step(px[e], py[e], spg, (c < W - 1) ? ubr - ub[e] : 0.f, (r < H - 1) ? ubd[e] - ub[e] : 0.f, rad, aniso);
+      // p of the row above (only its y part enters div p)
+      pxu[e] = cu.pxu[e];
+      pyu[e] = cu.pyu[e];
+      p_step(pxu[e], pyu[e], spg, (c < W - 1) ? ubur - ubu[e] : 0.f, ub[e] - ubu[e], rad, aniso);
+    }
     // p at (r, c0-1) for lane 0's left neighbour (only its x part enters div p)
     float pxL = rdlane(cu.epx, 0), pyL = rdlane(cu.epy, 0);
-    p_step(pxL, pyL, spg, rdlane(ub, 0) - ubL, (r < H - 1) ? ubLd - ubL : 0.f, rad, aniso);
-    const float pxl = from_left(px, pxL);
+    p_step(pxL, pyL, spg, rdlane(ub[0], 0) - ubL, (r < H - 1) ? ubLd - ubL : 0.f, rad, aniso);
+    const float pxln = from_left(px[PX - 1], pxL);
 
     // lanes outside the image and steps past the chunk store nothing
-    bstv(P.pout + (size_t)(i) * ps, nbd, dm, px);
-    bstv(P.pout + (size_t)((k + i)) * ps, nbd, dm, py);
-    float dv = 0.f;
-    if (c < W - 1) dv += px;
-    if (c > 0) dv -= pxl;
-    if (r < H - 1) dv += py;
-    if (r > 0) dv -= pyu;
+    bstvn<PX>(P.pout + (size_t)(i) * ps, nbd, dm, px);
+    bstvn<PX>(P.pout + (size_t)((k + i)) * ps, nbd, dm, py);
     const float g0 = A.gam[i], g1 = A.gam[i + 1], hi = A.h[i], ih = A.ih[i];
-    const float s = lsa[i * NP + lt];
-    const float sb = lsb[i * NP + lt];
-    suf -= hi * sb;
-    float v, z;
-    const float whi = cu.wh;
-    if (PIECE == SLI_TRUNC && i == si0) {
-      v = G == 1 ? sv0 : stv[0][lt];
-      z = G == 1 ? sz0 : stz[0][lt];
-    } else if (PIECE == SLI_TRUNC && i == si1) {
-      v = G == 1 ? sv1 : stv[1][lt];
-      z = G == 1 ? sz1 : stz[1][lt];
-    } else {
-      v = cu.v + A.sig[i] * (ub + suf - g0 * sb);
-      z = cu.z + A.sig[i] * sb;
-      float y = v * ih, w = z * ih;
-      float bs = 0.f, cs = 0.f;
-      if (ADD) {
-        bs = (whi - wlo) * ih;
-        cs = -wlo + bs * g0;
-        y -= bs;
-        w -= cs;
-      }
-      if (PIECE == SLI_QUAD) {
-        proj_quad(A.a, A.ia, piece_centre(fc, g0, g1, A.per, A.iper), g0, g1, A.ig0[i], A.ig1[i], y, w);
-      } else if (PIECE == SLI_TRUNC) {
-        // not straddling: inside the band (quadratic) or outside it (constant nu)
-        if (fc - A.del <= g0 && g1 <= fc + A.del)
-          proj_quad(A.a, A.ia, fc, g0, g1, A.ig0[i], A.ig1[i], y, w);
-        else
-          proj_flat(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w);
+    float v[PX], z[PX], sn[PX], un[PX];
+#pragma unroll
+    for (int e = 0; e < PX; e++) {
+      const int c = cb + e;
+      const float pxl = e > 0 ? px[e > 0 ? e - 1 : 0] : pxln;
+      float dv = 0.f;
+      if (c < W - 1) dv += px[e];
+      if (c > 0) dv -= pxl;
+      if (r < H - 1) dv += py[e];
+      if (r > 0) dv -= pyu[e];
+      const float s = lsa[i * NP + e * NL + lt];
+      const float sb = lsb[i * NP + e * NL + lt];
+      suf[e] -= hi * sb;
+      const float whi = cu.wh[e];
+      if (PIECE == SLI_TRUNC && i == si0[e]) {
+        v[e] = REG ? sv0 : stv[0][REG ? 0 : e * NL + lt];
+        z[e] = REG ? sz0 : stz[0][REG ? 0 : e * NL + lt];
+      } else if (PIECE == SLI_TRUNC && i == si1[e]) {
+        v[e] = REG ? sv1 : stv[REG ? 0 : 1][REG ? 0 : e * NL + lt];
+        z[e] = REG ? sz1 : stz[REG ? 0 : 1][REG ? 0 : e * NL + lt];
       } else {
-        PLProj pl;
-        pl.init(y, w);
-        const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
-        for (int m = m0; m <= m1; m++) pl.push(P.tau[m], bld(P.cost + (size_t)(m) * ps, nb4, xm));
-        pl.finish(y, w);
+        float ve = cu.v[e] + A.sig[i] * (ub[e] + suf[e] - g0 * sb);
+        float ze = cu.z[e] + A.sig[i] * sb;
+        float y = ve * ih, w = ze * ih;
+        float bs = 0.f, cs = 0.f;
+        if (ADD) {
+          bs = (whi - wlo[e]) * ih;
+          cs = -wlo[e] + bs * g0;
+          y -= bs;
+          w -= cs;
+        }
+        if (PIECE == SLI_QUAD) {
+          proj_quad(A.a, A.ia, piece_centre(fc[e], g0, g1, A.per, A.iper), g0, g1, A.ig0[i], A.ig1[i], y, w);
+        } else if (PIECE == SLI_TRUNC) {
+          // not straddling: inside the band (quadratic) or outside it (constant nu)
+          if (fc[e] - A.del <= g0 && g1 <= fc[e] + A.del)
+            proj_quad(A.a, A.ia, fc[e], g0, g1, A.ig0[i], A.ig1[i], y, w);
+          else
+            proj_flat(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w);
+        } else {
+          PLProj pl;
+          pl.init(y, w);
+          const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
+          for (int m = m0; m <= m1; m++)
+            pl.push(P.tau[m], bld(P.cost + (size_t)(m) * ps, nb4, xm + 4u * (unsigned)e));
+          pl.finish(y, w);
+        }
+        if (ADD) {
+          y += bs;
+          w += cs;
+        }
+        v[e] = hi * y;
+        z[e] = hi * w;
       }
-      if (ADD) {
-        y += bs;
-        w += cs;
-      }
-      v = hi * y;
-      z = hi * w;
+      if (ADD) wlo[e] = whi;
+      sn[e] = s - A.taus[i] * (z[e] - hi * qn[e] + hi * pre[e] - g0 * v[e]);
+      pre[e] += v[e];
+      un[e] = cu.u[e] - tau_u[e] * (v[e] - dv);
     }
-    if (ADD) wlo = whi;
-    bstv(P.v + (size_t)(i) * ps, nbd, dm, v);
-    bstv(P.z + (size_t)(i) * ps, nbd, dm, z);
-    const float sn = s - A.taus[i] * (z - hi * qn + hi * pre - g0 * v);
-    pre += v;
-    bst(P.un + (size_t)(i) * ps, nb4, xm, cu.u - tau_u * (v - dv));
-    if (G == 1)
-      bst(P.sp + (size_t)(i) * ps, nb4, xm, sn);
-    else
-      lsa[i * NP + lt] = sn;
+    bstvn<PX>(P.v + (size_t)(i) * ps, nbd, dm, v);
+    bstvn<PX>(P.z + (size_t)(i) * ps, nbd, dm, z);
+    bstn<PX>(P.un + (size_t)(i) * ps, nb4, xm, un);
+    if (G == 1) {
+      bstn<PX>(P.sp + (size_t)(i) * ps, nb4, xm, sn);
+    } else {
+#pragma unroll
+      for (int e = 0; e < PX; e++) lsa[i * NP + e * NL + lt] = sn[e];
+    }
   };
   // two step buffers in turn: a step consumes one and fills the other. With one label
   // group (large images, batches) an odd last step runs inside the loop: peeled after the
@@ -380,18 +536,28 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
 
   // ---- prefix of the new v over the earlier chunks: correction of the s update
   if (G > 1) {
-    ex[grp][lt] = pre;   // every read of the sbar sums precedes the barrier after the straddles
-    __syncthreads();
-    float vb = 0.f;
 #pragma unroll
-    for (int g = 0; g < G; g++)
-      if (g < grp) vb += ex[g][lt];
-    for (int j = i0; j < i1; j++) bst(P.sp + (size_t)(j) * ps, nb4, xm, lsa[j * NP + lt] - A.taus[j] * (A.h[j] * vb));
+    for (int e = 0; e < PX; e++) ex[grp][e * NL + lt] = pre[e];   // every read of the sbar sums precedes the barrier after the straddles
+    __syncthreads();
+    float vb[PX];
+#pragma unroll
+    for (int e = 0; e < PX; e++) {
+      vb[e] = 0.f;
+#pragma unroll
+      for (int g = 0; g < G; g++)
+        if (g < grp) vb[e] += ex[g][e * NL + lt];
+    }
+    for (int j = i0; j < i1; j++) {
+      float sv[PX];
+#pragma unroll
+      for (int e = 0; e < PX; e++) sv[e] = lsa[j * NP + e * NL + lt] - A.taus[j] * (A.h[j] * vb[e]);
+      bstn<PX>(P.sp + (size_t)(j) * ps, nb4, xm, sv);
+    }
   }
-  if (grp == 0) bst(P.qd, nb4, xm, qn);
+  if (grp == 0) bstn<PX>(P.qd, nb4, xm, qn);
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, IterArgs A) {
   extern __shared__ float dyn[];
   // XCD-aware tile order: blocks b, b+8, b+16, ... run on one XCD; give it a contiguous run
@@ -399,7 +565,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
   const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
   const int per = nb >> 3, rem = nb & 7;
   const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-  iter_tile<PIECE, ADD, DT, G, TH, TVK>(P, A, tile, dyn);
+  iter_tile<PIECE, ADD, DT, G, TH, TVK, PX>(P, A, tile, dyn);
 }
 
 // Batched iteration: persistent blocks pull (instance, tile) work items from a counter.
@@ -407,7 +573,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
 // counter[0] is the next item, counter[1] the number of blocks that found the list empty;
 // both are zero when a launch starts, and the last block to leave puts them back to zero
 // (every block has made its last pull by then), so consecutive launches need no reset.
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     const BatchItem *__restrict__ items, const int *__restrict__ count, int *counter,
     const IterPtrs<DT> *__restrict__ ptrs, const IterArgs *__restrict__ args, int phase) {
@@ -422,7 +588,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
     if (it >= n) break;
     const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
     const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
-    iter_tile<PIECE, ADD, DT, G, TH, TVK>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
+    iter_tile<PIECE, ADD, DT, G, TH, TVK, PX>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
   }
   if (threadIdx.x == 0) {
     __threadfence();
@@ -433,56 +599,55 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
   }
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
-  const int ntc = (A.W + TW - 1) / TW, ntr = (A.H + TH - 1) / TH;
-  const size_t lds = pdhg_iter_lds_bytes(A.k, TH);
+  const int ntc = (A.W + TW * PX - 1) / (TW * PX), ntr = (A.H + TH - 1) / TH;
+  const size_t lds = pdhg_iter_lds_bytes(A.k, G, TH, PX);
   const IterPtrs<DT> &P = *static_cast<const IterPtrs<DT> *>(ptrs);
-  hipLaunchKernelGGL((pdhg_iter_kernel<PIECE, ADD, DT, G, TH, TVK>), dim3(ntc * ntr), dim3(64 * TH * G),
+  hipLaunchKernelGGL((pdhg_iter_kernel<PIECE, ADD, DT, G, TH, TVK, PX>), dim3(ntc * ntr), dim3(64 * TH * G),
                      lds, st, P, A);
   return hipGetLastError();
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 hipError_t launch_bt(const BatchLaunch &L, hipStream_t st) {
-  hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK>), dim3(L.grid), dim3(64 * TH * G),
-                     pdhg_iter_lds_bytes(L.kmax, TH), st, L.items, L.count, L.counter,
+  hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK, PX>), dim3(L.grid), dim3(64 * TH * G),
+                     pdhg_iter_lds_bytes(L.kmax, G, TH, PX), st, L.items, L.count, L.counter,
                      (const IterPtrs<DT> *)L.ptrs, L.args, L.phase);
   return hipGetLastError();
 }
 
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK>
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 int occ_t(int kmax) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK>,
-                                                   64 * TH * G, pdhg_iter_lds_bytes(kmax, TH)) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK, PX>,
+                                                   64 * TH * G, pdhg_iter_lds_bytes(kmax, G, TH, PX)) != hipSuccess)
     return 0;
   return nb;
 }
 
-#define SLI_DISPATCH_CFG(FN, ...)                                   \
-  switch (cfg) {                                                     \
-    case 0: return FN<PIECE, ADD, DT, 1, 4, TVK>(__VA_ARGS__);            \
-    case 1: return FN<PIECE, ADD, DT, 1, 8, TVK>(__VA_ARGS__);            \
-    case 2: return FN<PIECE, ADD, DT, 2, 4, TVK>(__VA_ARGS__);            \
-    case 3: return FN<PIECE, ADD, DT, 2, 8, TVK>(__VA_ARGS__);            \
-    default: return FN<PIECE, ADD, DT, 4, 4, TVK>(__VA_ARGS__);           \
+// launch configurations (label groups, tile rows, pixels per lane); kIterCfg below
+#define SLI_DISPATCH_CFG(FN, ...)                                      \
+  switch (cfg) {                                                        \
+    case 0: return FN<PIECE, ADD, DT, 1, 4, TVK, 1>(__VA_ARGS__);       \
+    case 1: return FN<PIECE, ADD, DT, 1, 8, TVK, 1>(__VA_ARGS__);       \
+    case 2: return FN<PIECE, ADD, DT, 2, 4, TVK, 1>(__VA_ARGS__);       \
+    case 3: return FN<PIECE, ADD, DT, 2, 8, TVK, 1>(__VA_ARGS__);       \
+    case 4: return FN<PIECE, ADD, DT, 4, 4, TVK, 1>(__VA_ARGS__);       \
+    case 5: return FN<PIECE, ADD, DT, 1, 4, TVK, 2>(__VA_ARGS__);       \
+    case 6: return FN<PIECE, ADD, DT, 1, 8, TVK, 2>(__VA_ARGS__);       \
+    case 7: return FN<PIECE, ADD, DT, 2, 4, TVK, 2>(__VA_ARGS__);       \
+    case 8: return FN<PIECE, ADD, DT, 2, 8, TVK, 2>(__VA_ARGS__);       \
+    default: return FN<PIECE, ADD, DT, 4, 4, TVK, 2>(__VA_ARGS__);      \
   }
 
 template <int PIECE, bool ADD, typename DT, int TVK>
 hipError_t launch_bg(int cfg, const BatchLaunch &L, hipStream_t st) { SLI_DISPATCH_CFG(launch_bt, L, st) }
 template <int PIECE, bool ADD, typename DT, int TVK>
 int occ_g(int cfg, int kmax) { SLI_DISPATCH_CFG(occ_t, kmax) }
-
 template <int PIECE, bool ADD, typename DT, int TVK>
 hipError_t launch_g(int cfg, const IterArgs &A, const void *ptrs, hipStream_t st) {
-  switch (cfg) {
-    case 0: return launch_t<PIECE, ADD, DT, 1, 4, TVK>(A, ptrs, st);
-    case 1: return launch_t<PIECE, ADD, DT, 1, 8, TVK>(A, ptrs, st);
-    case 2: return launch_t<PIECE, ADD, DT, 2, 4, TVK>(A, ptrs, st);
-    case 3: return launch_t<PIECE, ADD, DT, 2, 8, TVK>(A, ptrs, st);
-    default: return launch_t<PIECE, ADD, DT, 4, 4, TVK>(A, ptrs, st);
-  }
+  SLI_DISPATCH_CFG(launch_t, A, ptrs, st)
 }
 
 template <int PIECE, bool ADD, int TVK>
@@ -534,14 +699,20 @@ int occ_p(int piece, bool add, bool bf16, int cfg, int kmax) {
 
 }  // namespace
 
-// launch configurations: (label groups, tile rows)
-const int kIterCfg[SLI_NCFG][2] = {{1, 4}, {1, 8}, {2, 4}, {2, 8}, {4, 4}};
+// launch configurations: (label groups, tile rows, pixels per lane)
+const int kIterCfg[SLI_NCFG][3] = {{1, 4, 1}, {1, 8, 1}, {2, 4, 1}, {2, 8, 1}, {4, 4, 1},
+                                   {1, 4, 2}, {1, 8, 2}, {2, 4, 2}, {2, 8, 2}, {4, 4, 2}};
 
-size_t pdhg_iter_lds_bytes(int k, int th) { return (size_t)2 * k * TW * th * sizeof(float); }
+size_t pdhg_iter_lds_bytes(int k, int g, int th, int px) {
+  (void)g;
+  return (size_t)2 * k * TW * th * px * sizeof(float);
+}
 
 size_t pdhg_iter_static_lds(int cfg) {
-  const int G = kIterCfg[cfg][0], TH = kIterCfg[cfg][1];
-  return sizeof(float) * (size_t)(G + (G > 1 ? 4 : 2)) * TW * TH;   // ex, stv, stz
+  const int G = kIterCfg[cfg][0], TH = kIterCfg[cfg][1], PX = kIterCfg[cfg][2];
+  const size_t np = (size_t)TW * TH * PX;
+  const bool reg = PX == 1 && G == 1;
+  return sizeof(float) * ((size_t)G * np + (reg ? 2 : 4 * np));   // ex, stv, stz
 }
 
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,

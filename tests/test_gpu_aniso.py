@@ -26,7 +26,7 @@ import paper_1512_01383_amd as S  # noqa: E402
 from tests.test_gpu_parity import (_bf16_round, _gpu_state, _load_same_state,  # noqa: E402
                                    _rel, _sampled_workload)
 
-TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)]
+from tests.gpu_tilings import TILING_IDS, TILINGS, use_tiling  # noqa: E402
 
 
 def _aniso(wl):
@@ -60,11 +60,12 @@ def _pair(wl, orc, storage="fp32"):
     return S.Problem.from_workload(wl, storage=storage), orc.Problem(wl)
 
 
-@pytest.mark.parametrize("tiling", TILINGS, ids=[f"g{a}t{b}" for a, b in TILINGS])
+@pytest.mark.parametrize("tiling", TILINGS, ids=TILING_IDS)
 @pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
 def test_single_iteration_from_random_state(orc, name, wl, tiling):
     g, o = _pair(wl, orc)
-    g.set_tiling(*tiling)
+    if not use_tiling(g, tiling, wl.W, wl.k):
+        return
     st = W.random_state(21, wl.k, wl.H, wl.W)
     _load_same_state(g, o, st)
     g.run(1)
@@ -134,9 +135,9 @@ def test_bf16_single_iteration(orc):
         assert np.all(err <= tol * (1.0 + np.abs(ref[n]))), (n, err.max())
 
 
-@pytest.mark.parametrize("tiling", [(1, 4), (2, 8)], ids=["g1t4", "g2t8"])
+@pytest.mark.parametrize("tiling", [(1, 4, 64), (2, 8, 64), (1, 4, 128)], ids=["g1t4c64", "g2t8c64", "g1t4c128"])
 def test_batch_mixing_both_kinds_equals_lone_solves(tiling):
-    shapes = [(9, 131, 5), (40, 90, 10), (1, 70, 2), (17, 200, 8)]
+    shapes = [(9, 130, 5), (40, 90, 10), (1, 70, 2), (17, 200, 8)]
     wls = [W.truncated_quadratic(L=L, H=H, W=Wd, seed=60 + j) for j, (H, Wd, L) in enumerate(shapes)]
     wls = [_aniso(w) if j % 2 == 0 else w for j, w in enumerate(wls)]
     iters = 13

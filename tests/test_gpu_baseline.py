@@ -22,17 +22,18 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_1512_01383_amd as S  # noqa: E402
 from tests.test_gpu_parity import _gpu_state, _load_same_state  # noqa: E402
 
-TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)]
+from tests.gpu_tilings import TILING_IDS, TILINGS, use_tiling  # noqa: E402
 CASES = [("tq_L6", W.baseline_lifting(W.truncated_quadratic(L=6, H=9, W=131, seed=41))),
          ("tq_L16", W.baseline_lifting(W.truncated_quadratic(L=16, H=7, W=70, seed=42)))]
 
 
-@pytest.mark.parametrize("tiling", TILINGS, ids=[f"g{a}t{b}" for a, b in TILINGS])
+@pytest.mark.parametrize("tiling", TILINGS, ids=TILING_IDS)
 @pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
 def test_single_iteration_from_random_state(orc, name, wl, tiling):
     g = S.Problem.from_workload(wl)
     o = orc.Problem(wl)
-    g.set_tiling(*tiling)
+    if not use_tiling(g, tiling, wl.W, wl.k):
+        return
     st = W.random_state(31, wl.k, wl.H, wl.W)
     _load_same_state(g, o, st)
     g.run(1)

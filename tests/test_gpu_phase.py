@@ -20,18 +20,19 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_1512_01383_amd as S  # noqa: E402
 from tests.test_gpu_parity import _gpu_state, _load_same_state, _rel  # noqa: E402
 
-TILINGS = [(1, 4), (1, 8), (2, 4), (2, 8), (4, 4)]
+from tests.gpu_tilings import TILING_IDS, TILINGS, use_tiling  # noqa: E402
 CASES = [("L8", W.phase_unwrapping(seed=51, H=9, W=131, L=8)),
          ("L5_lam", W.phase_unwrapping(seed=52, H=13, W=70, L=5, lam=0.2)),
          ("L16", W.phase_unwrapping(seed=53, H=6, W=64, L=16, lam=0.05))]
 
 
-@pytest.mark.parametrize("tiling", TILINGS, ids=[f"g{a}t{b}" for a, b in TILINGS])
+@pytest.mark.parametrize("tiling", TILINGS, ids=TILING_IDS)
 @pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
 def test_single_iteration_from_random_state(orc, name, wl, tiling):
     g = S.Problem.from_workload(wl)
     o = orc.Problem(wl)
-    g.set_tiling(*tiling)
+    if not use_tiling(g, tiling, wl.W, wl.k):
+        return
     st = W.random_state(41, wl.k, wl.H, wl.W)
     _load_same_state(g, o, st)
     g.run(1)
@@ -136,7 +137,7 @@ def test_adaptive_run_unwraps():
     assert np.mean(np.abs(err) < np.pi) > 0.95
 
 
-@pytest.mark.parametrize("tiling", [(1, 4), (4, 4)], ids=["g1t4", "g4t4"])
+@pytest.mark.parametrize("tiling", [(1, 4, 64), (4, 4, 128)], ids=["g1t4c64", "g4t4c128"])
 def test_periodic_with_anisotropic_tv(orc, tiling):
     """Both options together: periodic pieces and the l-inf box projection."""
     wl = W.phase_unwrapping(seed=57, H=10, W=100, L=6, lam=0.3)
