@@ -683,6 +683,15 @@ def bench_batch(args):
                "value_1_thread": pli_1 / dt1,
                "sample_1_thread": f"1 iteration of each of the first {m1} instances ({dt1:.1f} s)"}
 
+    if args.calibrate_copy:
+        # a plain 256 MiB device-to-device copy: the counters' reading for known bytes
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
+
     extra = None
     if not args.no_extra:
         big = W.roofline()
