@@ -129,7 +129,8 @@ def main():
     wl.tv = 1 if args.tv == "aniso" else 0
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    g = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY, device=dev)
+    g = S.Problem.from_workload(wl, storage=args.storage, check_every=CHECK_EVERY, device=dev,
+                                adaptive=False)
     stream = g.stream
     k, N = wl.k, wl.H * wl.W
 

@@ -109,8 +109,9 @@ typedef struct {
   int32_t check_every;     /* iterations between gap checks in sl_run_to_gap (>= 1)      */
   int32_t normalize_labels;/* 1: iterate on the labels mapped affinely onto [0,1] (an
                               exact reparametrisation; energies are unchanged)            */
-  int32_t adaptive_steps;  /* 1: sl_run_to_gap balances the steps by the residuals (see
-                              sl_residuals); 0: fixed steps. In a batch, per member.      */
+  int32_t adaptive_steps;  /* 1 (recommended): sl_run_to_gap balances the steps by the
+                              residuals (see sl_residuals); 0: fixed steps (the iteration
+                              of sl_run is the same). In a batch, per member.             */
 } sl_problem_desc;
 
 #define SL_MAX_LABELS 28      /* k = L-1 <= 27                                           */
@@ -249,14 +250,31 @@ sl_status sl_get_step_balance(sl_problem p, double *c);
 /* Runs one iteration and returns the l1 norms (FP64) of its residuals: with dx and dy the
  * changes of the primal (u, s) and dual (v, z, p, q) variables over the iteration,
  * primal = |T^-1 dx - K^T dy|_1 and dual = |Sigma^-1 dy - K dx|_1 (T, Sigma the current
- * diagonal steps). With adaptive_steps = 1, sl_run_to_gap takes such a measurement at the
- * end of every check interval and rescales the balance c: if the primal residual
- * exceeds 1.5 s times the dual one (s: sl_set_residual_target), the primal steps grow by
- * 1/(1 - alpha); if it is below s/1.5 times the dual one, the dual steps do (alpha = 0.5,
- * times 0.95 after every change; c stays in [1/4096, 4096]). In a batch, every member with
- * adaptive_steps = 1 is rebalanced this way from its own residuals. Synchronises the stream.
- * sl_residuals itself takes a single-problem handle (SL_ERR_UNSUPPORTED for a batch). */
-sl_status sl_residuals(sl_problem p, double *primal, double *dual);
+ * diagonal steps), and the sizes of the variables at the new iterate, ny = |(v, z, p, q)|_1
+ * and nx = |(u, s)|_1 (may be NULL). With adaptive_steps = 1, sl_run_to_gap takes such a
+ * measurement at the end of every check interval and rescales the balance c (residual
+ * balancing, the adaptive primal-dual method cited in Sec. 4): with the measures
+ * P = primal / ny and D = dual / nx (scaled rule, the default: the primal residual carries
+ * the units of the duals and the dual residual those of the primal, so the test does not
+ * depend on the scale of the data term or of lambda) or the raw norms P = primal,
+ * D = dual, and the target s (default 0.2): if P exceeds 1.5 s D the primal steps grow by
+ * 1/(1 - alpha); if P is below s D / 1.5 the dual steps do (alpha = 0.5, times 0.95 after
+ * every change; c stays in [1/4096, 4096]). In a batch, every member with
+ * adaptive_steps = 1 is rebalanced this way from its own residuals. Synchronises the
+ * stream. sl_residuals itself takes a single-problem handle (SL_ERR_UNSUPPORTED for a
+ * batch). */
+sl_status sl_residuals(sl_problem p, double *primal, double *dual, double *ny, double *nx);
+
+/* Target ratio s of the adaptive balance (default 0.2; the rule is kept).
+ * SL_ERR_INVALID_ARG unless s is finite and > 0. */
+sl_status sl_set_residual_target(sl_problem p, double s);
+
+/* Choose the balancing rule: scaled = 1 (default) compares the residuals relative to the
+ * variables' sizes, scaled = 0 the raw norms, each with target s (the raw norms carry
+ * different units: on truncated-quadratic denoising s = 0.003 suited them). Applies to
+ * every member of a batch. SL_ERR_INVALID_ARG unless scaled is 0 or 1 and s is finite and
+ * > 0. */
+sl_status sl_set_balance_rule(sl_problem p, int32_t scaled, double s);
 
 /* FP32 finishing phase of bf16 dual storage.
  * sl_set_storage: widen the bf16 duals (v, z, p) of problem i of a batch (i = -1: every
@@ -272,14 +290,6 @@ sl_status sl_residuals(sl_problem p, double *primal, double *dual);
 sl_status sl_set_storage(sl_problem p, int32_t i, sl_storage storage);
 sl_status sl_set_finishing(sl_problem p, int32_t stall_checks);
 sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *iters_bf16);
-
-/* Target ratio s of the primal to the dual residual for the adaptive balance (the residual
- * norms carry different units; the balancing rule above compares primal with s * dual).
- * Default 0.003, chosen by measurement: on truncated-quadratic denoising with 2 to 20
- * labels it reaches a 1e-3 certified gap in the fewest iterations of the values tried
- * (1 settles at c near 1, several times slower). SL_ERR_INVALID_ARG unless s is finite
- * and > 0. */
-sl_status sl_set_residual_target(sl_problem p, double s);
 
 /* Tuning knobs of the fused iteration: a block works on a tile of tile_cols columns x
  * tile_rows rows with label_groups groups of wavefronts, each walking a contiguous chunk

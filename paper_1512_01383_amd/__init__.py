@@ -98,7 +98,9 @@ def lib():
         L.sl_unrolled_workspace_size.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(sz)]
         L.sl_unrolled_forward.argtypes = [vp, C.c_int32, C.c_int32, vp, sz]
         L.sl_unrolled_backward.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
-        L.sl_residuals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.sl_residuals.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.sl_set_balance_rule.argtypes = [vp, C.c_int32, C.c_double]
         L.sl_set_residual_target.argtypes = [vp, C.c_double]
         L.sl_set_step_balance.argtypes = [vp, C.c_double]
         L.sl_get_step_balance.argtypes = [vp, C.POINTER(C.c_double)]
@@ -116,7 +118,7 @@ def lib():
                      "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
                      "sl_unrolled_backward", "sl_set_step_balance", "sl_get_step_balance",
                      "sl_residuals", "sl_set_residual_target", "sl_solve_static",
-                     "sl_set_storage", "sl_set_finishing", "sl_storage_info"):
+                     "sl_set_storage", "sl_set_finishing", "sl_storage_info", "sl_set_balance_rule"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -180,7 +182,7 @@ class Problem:
     def __init__(self, H: int, W: int, gamma, rho: int, lam: float, f=None, a: float = 1.0,
                  nu: float = 0.0, tau=None, samples=None, storage: str = "fp32",
                  normalize: bool = True, check_every: int = 50, device=None,
-                 adaptive: bool = False, tv: int = TV_ISO):
+                 adaptive: bool = True, tv: int = TV_ISO):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()
@@ -269,9 +271,18 @@ class Problem:
 
     def residuals(self):
         """Run one iteration; return the l1 norms (primal, dual) of its residuals."""
-        rp, rd = C_.c_double(), C_.c_double()
-        _check(lib().sl_residuals(self.h, C_.byref(rp), C_.byref(rd)))
-        return rp.value, rd.value
+        return self.residuals_full()[:2]
+
+    def residuals_full(self):
+        """Run one iteration; return (primal, dual, |K^T y|, |K x|), l1 norms."""
+        rp, rd, ky, kx = C_.c_double(), C_.c_double(), C_.c_double(), C_.c_double()
+        _check(lib().sl_residuals(self.h, C_.byref(rp), C_.byref(rd), C_.byref(ky), C_.byref(kx)))
+        return rp.value, rd.value, ky.value, kx.value
+
+    def set_balance_rule(self, scaled: bool, s: float):
+        """Adaptive balance: raw residual norms (scaled=False) or residuals relative to
+        |K^T y| and |K x| (scaled=True), compared with target ratio s."""
+        _check(lib().sl_set_balance_rule(self.h, 1 if scaled else 0, float(s)))
 
     def widen(self, i: int = -1):
         """Widen bf16 duals to float in place (problem i of a batch, -1: all)."""
@@ -289,7 +300,7 @@ class Problem:
         return ("bf16" if st.value == STORE_BF16_DUAL else "fp32"), nb.value
 
     def set_residual_target(self, s: float):
-        """Target ratio of primal to dual residual for the adaptive balance (default 0.003)."""
+        """Target ratio of the adaptive balance (default 0.2, scaled rule)."""
         _check(lib().sl_set_residual_target(self.h, float(s)))
 
     def set_step_balance(self, c: float):
@@ -334,7 +345,7 @@ class BatchProblem(Problem):
     iteration (sl_batch_create). ``instances`` are ``workloads.Workload``-like objects."""
 
     def __init__(self, instances, storage: str = "fp32", normalize: bool = True,
-                 check_every: int = 48, device=None, adaptive: bool = False):
+                 check_every: int = 48, device=None, adaptive: bool = True):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda:0")
         L_ = lib()

@@ -98,9 +98,9 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
     IterArgs A{};
     A.H = d->H;
     A.W = d->W;
-    L.off_rpart = take((size_t)residual_blocks(A) * 16);
+    L.off_rpart = take((size_t)residual_blocks(A) * 32);
   }
-  L.off_rfin = take(16);
+  L.off_rfin = take(32);
   L.total = o;
   return L;
 }
@@ -192,7 +192,8 @@ struct sl_problem_ {
   double step_c = 1.0;  // balance of dual against primal steps (sigma * c, tau / c)
   double step_c0 = 1.0; // the balance set by the caller (adaptive steps start from it)
   double adapt_alpha = 0.5;  // current relative change of the balance (adaptive steps)
-  double adapt_s = 0.003;    // target ratio of the primal to the dual residual
+  double adapt_s = 0.2;      // target ratio of the primal to the dual residual measure
+  int adapt_scaled = 1;      // 1: compare the residuals relative to |y| and |x|; 0: raw norms
   int64_t adapt_count = 0;   // balance changes made so far
   // the caller's labels and sample positions (copies; fixed arrays, so that a problem
   // object can be built without any allocation)
@@ -751,7 +752,7 @@ sl_status batch_enqueue(sl_problem_ *P, int iters) {
 
 sl_status save_duals(sl_problem_ *P);
 sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev = nullptr);
-void adapt_balance(sl_problem_ *P, double rp, double rd);
+void adapt_balance(sl_problem_ *P, const double *res);
 
 // Run `enqueue(stream)` (work of every active member at a check) from graph slot g: captured
 // on the private stream once per key and replayed on the batch's stream (each member's work
@@ -900,7 +901,7 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
     if (adapt) {
       for (size_t i = 0; i < n; i++) {
         if (!active_adaptive(i)) continue;
-        adapt_balance(P->sub[i], P->bfin_host[i * 16 + 8], P->bfin_host[i * 16 + 9]);
+        adapt_balance(P->sub[i], &P->bfin_host[i * 16 + 8]);
         P->args_host[i] = P->sub[i]->A;
       }
       HIPCHK(hipMemcpyAsync(P->args_dev, P->args_host.data(), P->args_host.size() * sizeof(IterArgs),
@@ -949,8 +950,8 @@ double *res_out(sl_problem_ *P) {
   return P->fin_dev ? P->fin_dev + 8 : (double *)(P->ws + P->lay.off_rfin);
 }
 
-// residual norms of the iteration that followed save_duals, enqueued (2 sums at res_out(P));
-// residuals_of_last also waits for them
+// residual norms of the iteration that followed save_duals, enqueued (4 sums at res_out(P):
+// primal, dual, |K^T y|, |K x|); residuals_of_last also waits for them
 sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
   const int k = P->A.k;
   const size_t pdb = (size_t)P->lay.ps * P->esz();
@@ -973,31 +974,43 @@ sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
   return SL_OK;
 }
 
-sl_status residuals_of_last(sl_problem_ *P, double *rp, double *rd) {
+sl_status residuals_of_last(sl_problem_ *P, double *res) {
   sl_status s = residuals_enqueue(P);
   if (s != SL_OK) return s;
   double *h = nullptr;
-  if ((s = pinned(P, 2, &h)) != SL_OK) return s;
-  HIPCHK(hipMemcpyAsync(h, res_out(P), 2 * sizeof(double), hipMemcpyDeviceToHost, P->st), "residual copy");
+  if ((s = pinned(P, 4, &h)) != SL_OK) return s;
+  HIPCHK(hipMemcpyAsync(h, res_out(P), 4 * sizeof(double), hipMemcpyDeviceToHost, P->st), "residual copy");
   HIPCHK(hipStreamSynchronize(P->st), "residual sync");
-  *rp = h[0];
-  *rd = h[1];
+  for (int j = 0; j < 4; j++) res[j] = h[j];
   return SL_OK;
 }
 
-// One iteration with the residual norms of its step (primal, dual; l1, FP64).
-sl_status iterate_with_residuals(sl_problem_ *P, double *rp, double *rd) {
+// One iteration with the residual norms of its step (primal, dual; l1, FP64) and the scales
+// |K^T y| and |K x| at its end.
+sl_status iterate_with_residuals(sl_problem_ *P, double *res) {
   sl_status s = save_duals(P);
   if (s == SL_OK) s = enqueue_iters(P, 1);
-  if (s == SL_OK) s = residuals_of_last(P, rp, rd);
+  if (s == SL_OK) s = residuals_of_last(P, res);
   return s;
 }
 
-// Residual balancing: a primal residual more than 1.5 times s times the dual one enlarges
-// the primal steps (c *= 1 - alpha), one below s times the dual one divided by 1.5 enlarges
-// the dual steps (c /= 1 - alpha); every change shrinks alpha by 0.95 (alpha starts at 0.5).
-void adapt_balance(sl_problem_ *P, double rp, double rd) {
+// Residual balancing (adaptive primal-dual method of Goldstein, Li, Yuan, Esser and
+// Baraniuk, cited in Sec. 4): a primal residual more than 1.5 times s times the dual one
+// enlarges the primal steps (c *= 1 - alpha), one below s times the dual one divided by 1.5
+// enlarges the dual steps (c /= 1 - alpha); every change shrinks alpha by 0.95 (alpha starts
+// at 0.5). The raw rule compares the two l1 norms with the target s; the scaled rule (the
+// default) compares each residual relative to the size of the variables whose units it
+// carries, |y| for the primal and |x| for the dual residual, which makes the test free of
+// the units of the data term and of lambda. (Relative to |K^T y| instead, the primal measure
+// grows without bound: the primal part of this saddle problem has no prox term, so K^T y
+// vanishes at the optimum.)
+void adapt_balance(sl_problem_ *P, const double *res) {
   const double delta = 1.5, eta = 0.95;
+  double rp = res[0], rd = res[1];
+  if (P->adapt_scaled) {
+    rp /= std::max(res[2], 1e-300);
+    rd /= std::max(res[3], 1e-300);
+  }
   const double sd = P->adapt_s * rd;
   double c = P->step_c;
   if (rp > delta * sd)
@@ -1285,9 +1298,9 @@ static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_i
     if (s != SL_OK) return s;
     if (P->d.adaptive_steps) {
       // the check interval's last iteration measures the residuals that steer the balance
-      double rp = 0.0, rd = 0.0;
-      if ((s = iterate_with_residuals(P, &rp, &rd)) != SL_OK) return s;
-      adapt_balance(P, rp, rd);
+      double res[4];
+      if ((s = iterate_with_residuals(P, res)) != SL_OK) return s;
+      adapt_balance(P, res);
     }
     n += chunk;
     if ((s = monitor(P, &r)) != SL_OK) {
@@ -1774,10 +1787,30 @@ sl_status sl_set_residual_target(sl_problem P, double s) {
   return SL_OK;
 }
 
-sl_status sl_residuals(sl_problem P, double *primal, double *dual) {
+sl_status sl_residuals(sl_problem P, double *primal, double *dual, double *kty, double *kx) {
   if (!P || !primal || !dual) return fail(SL_ERR_INVALID_ARG, "NULL argument");
   if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "residuals of a batch are not built");
-  return iterate_with_residuals(P, primal, dual);
+  double res[4];
+  const sl_status s = iterate_with_residuals(P, res);
+  if (s != SL_OK) return s;
+  *primal = res[0];
+  *dual = res[1];
+  if (kty) *kty = res[2];
+  if (kx) *kx = res[3];
+  return SL_OK;
+}
+
+sl_status sl_set_balance_rule(sl_problem P, int32_t scaled, double s) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (scaled != 0 && scaled != 1) return fail(SL_ERR_INVALID_ARG, "scaled must be 0 or 1");
+  if (!(s > 0.0) || !isfinite(s)) return fail(SL_ERR_INVALID_ARG, "the target must be finite and > 0");
+  P->adapt_scaled = scaled;
+  P->adapt_s = s;
+  for (sl_problem_ *q : P->sub) {
+    q->adapt_scaled = scaled;
+    q->adapt_s = s;
+  }
+  return SL_OK;
 }
 
 sl_status sl_get_step_balance(sl_problem P, double *c) {

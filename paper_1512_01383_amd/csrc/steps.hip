@@ -4,8 +4,10 @@
 //
 // With dx = x_k - x_{k+1} and dy = y_k - y_{k+1} (x = (u, s), y = (v, z, p, q)):
 //   r_p = T^-1 dx - K^T dy,   r_d = Sigma^-1 dy - K dx,
-// and the kernel sums |r_p| and |r_d| over all entries (FP64 accumulation, fixed order:
-// every thread owns a fixed set of pixels, blocks write partial sums, one block adds them).
+// and the kernel sums |r_p| and |r_d| over all entries, and the sizes of the two sides'
+// variables at the new iterate, |y_{k+1}| and |x_{k+1}| (l1 norms, FP64 accumulation,
+// fixed order: every thread owns a fixed set of pixels, blocks write partial sums, one
+// block adds them).
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -15,12 +17,12 @@ constexpr int RB = 256;
 
 template <typename DT>
 __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs &A) {
-  __shared__ double sp_[RB], sd_[RB];
+  __shared__ double sp_[RB], sd_[RB], sx_[RB], sy_[RB];
   const DT *v = (const DT *)R.v, *z = (const DT *)R.z, *vo = (const DT *)R.vo, *zo = (const DT *)R.zo;
   const DT *p = (const DT *)R.p, *po = (const DT *)R.po;
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps, N = (long long)H * W;
-  double accp = 0.0, accd = 0.0;
+  double accp = 0.0, accd = 0.0, acckx = 0.0, accky = 0.0;
   for (long long x = (long long)blockIdx.x * RB + threadIdx.x; x < N; x += (long long)gridDim.x * RB) {
     const int r = (int)(x / W), c = (int)(x - (long long)r * W);
     const bool hr = c < W - 1, hl = c > 0, hd = r < H - 1, hu = r > 0;
@@ -57,22 +59,33 @@ __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs 
       const float rdx = dpx / A.sig_p - gx, rdy = dpy / A.sig_p - gy;
       accp += (double)fabsf(rpu) + (double)fabsf(rps);
       accd += (double)fabsf(rdv) + (double)fabsf(rdz) + (double)fabsf(rdx) + (double)fabsf(rdy);
+      // the variables at the new iterate: x = (u, s), y = (v, z, p, q)
+      acckx += (double)fabsf(R.u[o + x]) + (double)fabsf(R.s[o + x]);
+      accky += (double)fabsf(ldv(v, o + x)) + (double)fabsf(ldv(z, o + x)) + (double)fabsf(ldv(p, o + x)) +
+               (double)fabsf(ldv(p, oy + x));
     }
     accd += (double)fabsf(dq / A.sig_q + T);
+    accky += (double)fabsf(R.q[x]);
   }
   sp_[threadIdx.x] = accp;
   sd_[threadIdx.x] = accd;
+  sx_[threadIdx.x] = acckx;
+  sy_[threadIdx.x] = accky;
   __syncthreads();
   for (int s = RB / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
       sp_[threadIdx.x] += sp_[threadIdx.x + s];
       sd_[threadIdx.x] += sd_[threadIdx.x + s];
+      sx_[threadIdx.x] += sx_[threadIdx.x + s];
+      sy_[threadIdx.x] += sy_[threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    R.part[2 * blockIdx.x] = sp_[0];
-    R.part[2 * blockIdx.x + 1] = sd_[0];
+    R.part[4 * blockIdx.x] = sp_[0];
+    R.part[4 * blockIdx.x + 1] = sd_[0];
+    R.part[4 * blockIdx.x + 2] = sy_[0];   // |y|, the scale of the primal residual
+    R.part[4 * blockIdx.x + 3] = sx_[0];   // |x|, the scale of the dual residual
   }
 }
 
@@ -88,27 +101,19 @@ __global__ __launch_bounds__(RB) void k_residuals_tab(ResPtrs R, const IterArgs 
   residuals_body<DT>(R, *Ap);
 }
 
-__global__ __launch_bounds__(RB) void k_sum_pairs(const double *part, int nb, double *out) {
-  __shared__ double a[RB], b[RB];
-  double x = 0.0, y = 0.0;
-  for (int j = threadIdx.x; j < nb; j += RB) {
-    x += part[2 * j];
-    y += part[2 * j + 1];
-  }
+// block q (0..3) adds column q of the per-block quadruples, in block order
+__global__ __launch_bounds__(RB) void k_sum_quads(const double *part, int nb, double *out) {
+  __shared__ double a[RB];
+  const int q = blockIdx.x;
+  double x = 0.0;
+  for (int j = threadIdx.x; j < nb; j += RB) x += part[4 * j + q];
   a[threadIdx.x] = x;
-  b[threadIdx.x] = y;
   __syncthreads();
   for (int s = RB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      a[threadIdx.x] += a[threadIdx.x + s];
-      b[threadIdx.x] += b[threadIdx.x + s];
-    }
+    if ((int)threadIdx.x < s) a[threadIdx.x] += a[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    out[0] = a[0];
-    out[1] = b[0];
-  }
+  if (threadIdx.x == 0) out[q] = a[0];
 }
 
 }  // namespace
@@ -132,6 +137,6 @@ hipError_t launch_residuals(bool bf16, const ResPtrs &R, const IterArgs &A, doub
   } else {
     hipLaunchKernelGGL(k_residuals<float>, dim3(nb), dim3(RB), 0, st, R, A);
   }
-  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RB), 0, st, (const double *)R.part, nb, out);
+  hipLaunchKernelGGL(k_sum_quads, dim3(4), dim3(RB), 0, st, (const double *)R.part, nb, out);
   return hipGetLastError();
 }

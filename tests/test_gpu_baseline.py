@@ -52,7 +52,7 @@ def test_run_to_gap_brackets_independent_baseline_solve():
     costs = rng.uniform(0, 1, size=(L, H, Wd)).astype(np.float32)
     lam = 0.15
     wl = W.Workload("p2", H, Wd, gamma, W.SAMPLED, lam, tau=gamma.copy(), samples=costs)
-    g = S.Problem.from_workload(wl)
+    g = S.Problem.from_workload(wl, adaptive=False)
     g.run_to_gap(1e-5, 60000)
     rep = g.energy()
     Pb, Db = ck.baseline_lifting(costs.astype(np.float64), gamma, lam, iters=40000, tol=1e-9)

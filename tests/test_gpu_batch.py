@@ -153,7 +153,7 @@ def test_batch_member_matches_oracle(orc):
 def test_batch_run_to_gap_retires_members():
     wls = [W.truncated_quadratic(L=2, H=32, W=32, seed=1)]
     wls += [W.truncated_quadratic(L=L, H=24, W=70, seed=90 + L) for L in (4, 6)]
-    b = S.BatchProblem(wls, check_every=48)
+    b = S.BatchProblem(wls, check_every=48, adaptive=False)
     tol = 2e-2                     # the oracle reaches it after 576, 2304 and 5568 iterations
     done = b.run_to_gap(tol, 20000)
     assert done <= 20000

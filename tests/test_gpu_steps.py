@@ -34,12 +34,16 @@ def test_residual_norms_match_oracle(orc, c):
     g.set_step_balance(c)
     g.run(37)
     before = _state(g)
-    rp, rd = g.residuals()
+    rp, rd, kty, kx = g.residuals_full()
     after = _state(g)
     o = orc.Problem(wl, step_balance=c)
     rpo, rdo = o.residual_norms(before, after)
-    print(f"c={c}: gpu {rp:.9g} {rd:.9g} oracle {rpo:.9g} {rdo:.9g}")
+    # the scales of the scaled balancing rule: |y| and |x| (l1) at the new iterate
+    kxo = sum(np.abs(after[n]).sum() for n in ("u", "s"))
+    ktyo = sum(np.abs(after[n]).sum() for n in ("v", "z", "px", "py", "qd"))
+    print(f"c={c}: gpu {rp:.9g} {rd:.9g} {kty:.9g} {kx:.9g} oracle {rpo:.9g} {rdo:.9g} {ktyo:.9g} {kxo:.9g}")
     assert abs(rp - rpo) <= 1e-5 * rpo and abs(rd - rdo) <= 1e-5 * rdo
+    assert abs(kty - ktyo) <= 1e-5 * ktyo and abs(kx - kxo) <= 1e-5 * kxo
 
 
 def test_balance_matches_oracle_iteration(orc):
@@ -78,7 +82,7 @@ def test_adaptive_run_reaches_gap_and_brackets_oracle(orc):
     c = g.get_step_balance()
     assert 1 / 4096 <= c <= 4096 and c != 1.0
     # same problem, fixed steps: slower
-    f = S.Problem.from_workload(wl)
+    f = S.Problem.from_workload(wl, adaptive=False)
     nf = f.run_to_gap(1e-3, n)
     assert f.energy()["rel_gap"] > 1e-3 or nf >= n
     # the certified interval contains the relaxed optimum the oracle brackets
