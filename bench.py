@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="batch",
-                    choices=["tq", "stereo", "phase", "batch", "diff", "labels"],
+                    choices=["tq", "stereo", "phase", "batch", "diff", "labels", "cpu"],
                     help="batch: 64 mixed instances in one persistent launch per iteration "
                          "(default); tq: one truncated-quadratic instance; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
@@ -119,6 +119,8 @@ def main():
         return bench_diff(args)
     if args.workload == "labels":
         return bench_labels(args)
+    if args.workload == "cpu":
+        return bench_cpu(args)
 
     if args.workload == "stereo":
         wl = W.stereo()            # sampled costs, 384x288, 64 disparities, L = 8
@@ -731,6 +733,125 @@ def bench_batch(args):
                   "speedup_vs_sequential": t_seq / (kern_ms * n_k * 1e-3)},
         "time_to_gap_1e-3": gap,
         "single_instance": extra,
+    }
+    print(json.dumps(out))
+
+
+def bench_cpu(args):
+    """CPU baselines of the other workloads beside the GPU (the FP64 oracle on the host's
+    cores, and on one thread; a baseline, not a target): ROF 64^2 L=2 for its 2000
+    iterations, the sampled-cost stereo problem for its 1000 iterations (timed on a bounded
+    sample), the differentiation workload (K = 200 forward and reverse), and the paper-style
+    relative energy error (E - E*)/E* of the GPU solve at a 1e-3 certified gap on ROF, with
+    E* the midpoint of the oracle's certified interval after up to 100 000 FP64 iterations
+    (its relative width is reported; below 1e-7)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1512_01383_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ncores = oracle.set_threads(host_cores())
+    rows = {}
+
+    def gpu_iters(wl, n):
+        g = S.Problem.from_workload(wl, device=dev)
+        g.run(5)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(g.stream)
+        g.run(n)
+        ev1.record(g.stream)
+        ev1.synchronize()
+        g.close()
+        return ev0.elapsed_time(ev1) * 1e-3
+
+    def cpu_iters(wl, n, threads):
+        oracle.set_threads(threads)
+        o = oracle.Problem(wl)
+        o.run(1)
+        t0 = time.perf_counter()
+        o.run(n)
+        dt = time.perf_counter() - t0
+        oracle.set_threads(ncores)
+        return dt
+
+    # ROF: the 2000 iterations, and the paper-style error at a 1e-3 certified gap
+    rof = W.rof()
+    pl = rof.H * rof.W * rof.k
+    t_g = gpu_iters(rof, 2000)
+    t_c = cpu_iters(rof, 2000, ncores)
+    t_1 = cpu_iters(rof, 2000, 1)
+    o = oracle.Problem(rof)
+    rep_o = oracle.run_to_gap(o, 1e-9, 100000, check_every=500)   # E* known to its certified gap
+    e_star = 0.5 * (rep_o["best_primal"] + rep_o["best_dual"])
+    g = S.Problem.from_workload(rof, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_gap = g.run_to_gap(1e-3, 60000)
+    t_gap = time.perf_counter() - t0
+    e = g.energy()
+    g.close()
+    rows["rof64_L2_2000its"] = {
+        "gpu_seconds": t_g, "gpu_pli_per_s": pl * 2000 / t_g,
+        "cpu_seconds": t_c, "cpu_pli_per_s": pl * 2000 / t_c, "cpu_1thread_seconds": t_1,
+        "e_star": e_star, "e_star_rel_gap": rep_o["rel_gap"], "e_star_iterations": rep_o["iters"],
+        "gpu_to_1e-3": {"iterations": n_gap, "seconds": t_gap, "rel_gap": e["rel_gap"],
+                        "primal_rel_error": (e["best_primal"] - e_star) / e_star,
+                        "e_nonconvex_rel_error": (e["e_nonconvex"] - e_star) / e_star}}
+
+    # stereo: 1000 iterations on the GPU; the oracle on a bounded sample
+    st = W.stereo()
+    pl = st.H * st.W * st.k
+    t_g = gpu_iters(st, 1000)
+    n_c = 60
+    t_c = cpu_iters(st, n_c, ncores)
+    t_1 = cpu_iters(st, 6, 1)
+    rows["stereo384x288_L8_1000its"] = {
+        "gpu_seconds": t_g, "gpu_pli_per_s": pl * 1000 / t_g,
+        "cpu_pli_per_s": pl * n_c / t_c, "cpu_seconds_est_1000its": t_c / n_c * 1000,
+        "cpu_sample": f"{n_c} iterations ({t_c:.1f} s)", "cpu_1thread_pli_per_s": pl * 6 / t_1}
+
+    # differentiation: K = 200 unrolled iterations, checkpoint every 20 (GPU) / full tape (oracle)
+    wl = W.differentiation()
+    tgt = torch.as_tensor(wl.target, device=dev)
+    p = S.Problem.from_workload(wl, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.unrolled_forward(200, 20)
+    _, u = p.read_u()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p.unrolled_backward(2.0 * (u - tgt))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    p.close()
+    o = oracle.Problem(wl)
+    c0 = time.perf_counter()
+    o.unrolled_forward(200)
+    _, uo = o.read_u()
+    c1 = time.perf_counter()
+    o.unrolled_backward(2.0 * (uo - wl.target.astype(np.float64)))
+    c2 = time.perf_counter()
+    del o
+    rows["diff256_L8_K200"] = {"gpu_forward_s": t1 - t0, "gpu_backward_s": t2 - t1,
+                               "cpu_forward_s": c1 - c0, "cpu_backward_s": c2 - c1}
+
+    out = {
+        "metric": "lifted PDHG pixel-label-iter/s",
+        "value": rows["rof64_L2_2000its"]["gpu_pli_per_s"],
+        "unit": "pixel-label-iter/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": rows["rof64_L2_2000its"]["gpu_seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "CPU baselines: ROF 64x64 L=2 2000 iterations, sampled stereo 384x288 "
+                               "L=8 1000 iterations, unrolled differentiation 256x256 L=8 K=200",
+                   "step": "one pass over the three workloads"},
+        "cpu": {"cores": ncores, "cpu_model": cpu_model(), "kind": "oracle"},
+        "workloads": rows,
     }
     print(json.dumps(out))
 

@@ -41,6 +41,10 @@ def _make_function():
         @staticmethod
         def backward(ctx, gu):
             prob = ctx.prob
+            if prob is None:
+                raise RuntimeError("unrolled_solve supports one backward pass per forward pass "
+                                   "(its checkpoints are released after it); run the forward "
+                                   "again instead of retain_graph=True")
             need_f, need_lam, need_w = ctx.needs_input_grad[:3]
             gf, gl, gw = prob.unrolled_backward(gu.contiguous(), want_f=need_f,
                                                 want_w=need_w and ctx.has_w)

@@ -189,6 +189,10 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
   }
 }
 
+// maximum that keeps a NaN operand (fmax drops it): a non-finite dual point must give a
+// non-finite bound, not the maximum over its finite labels
+__device__ __forceinline__ double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
+
 // norm of the regulariser: l2 (isotropic TV) or l1 (anisotropic TV)
 __device__ __forceinline__ double tv_norm(const IterArgs &A, double gx, double gy) {
   return A.aniso ? fabs(gx) + fabs(gy) : sqrt(gx * gx + gy * gy);
@@ -367,7 +371,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
       }
       make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
       const double y = vh * D.ih[i];
-      mloc = fmax(mloc, pre - D.gam[i] * y + conj_full(P, y));
+      mloc = max_nan(mloc, pre - D.gam[i] * y + conj_full(P, y));
       pre += vh;
       ub += D.h[i] * fmin(fmax((double)cur.u, 0.0), 1.0);
       cur = nxt;
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
     double base = 0.0, mx = -INFINITY, tsum = D.gam[0];
 #pragma unroll
     for (int g = 0; g < MT; g++) {
-      mx = fmax(mx, base + xa[g][lane]);
+      mx = max_nan(mx, base + xa[g][lane]);
       base += xb[g][lane];
       tsum += xu[g][lane];
     }

@@ -3,6 +3,7 @@
 // bookkeeping and the state save / load.
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -41,6 +42,36 @@ sl_status hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Solver trace: with the environment variable SL_TRACE set (to "1" or "stderr" for standard
+// error, else to a file path, appended to), sl_run_to_gap writes one JSON object per line for
+// every check and every change of a problem's dual storage. Read at every call.
+struct Trace {
+  FILE *f = nullptr;
+  bool own = false;
+  explicit Trace(bool enabled) {
+    const char *e = enabled ? getenv("SL_TRACE") : nullptr;
+    if (!e || !*e || strcmp(e, "0") == 0) return;
+    if (strcmp(e, "1") == 0 || strcmp(e, "stderr") == 0) {
+      f = stderr;
+    } else {
+      f = fopen(e, "a");
+      own = f != nullptr;
+    }
+  }
+  ~Trace() {
+    if (own) fclose(f);
+  }
+  void line(const char *fmt, ...) __attribute__((format(printf, 2, 3))) {
+    if (!f) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vfprintf(f, fmt, ap);
+    va_end(ap);
+    fputc('\n', f);
+    fflush(f);
+  }
+};
 
 struct Layout {
   long long N, ps;
@@ -850,6 +881,7 @@ sl_status batch_widen_member(sl_problem_ *P, int i) {
 }
 
 sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_t *done) {
+  Trace tr(true);
   const int chunk = std::max(6, (P->check_every + 5) / 6 * 6);
   const size_t n = P->sub.size();
   double *stage = nullptr;
@@ -910,6 +942,8 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       HIPCHK(hipStreamSynchronize(P->st), "batch parameters");
     }
     bool changed = false;
+    int n_active = 0;
+    double worst = 0.0;
     for (size_t i = 0; i < n; i++) {
       if (!P->active[i]) continue;
       memcpy(P->sub[i]->fin, &P->bfin_host[i * 16], 7 * sizeof(double));
@@ -918,14 +952,23 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
         if (done) *done = done_n;
         return s;
       }
+      n_active++;
+      worst = std::max(worst, r.rel_gap);
       if (r.rel_gap <= tol) {
         P->active[i] = 0;
         changed = true;
+        tr.line("{\"event\": \"retire\", \"member\": %d, \"iters\": %lld, \"rel_gap\": %.6g, \"primal\": %.17g, "
+                "\"dual\": %.17g, \"balance\": %.6g, \"storage\": \"%s\"}",
+                (int)i, (long long)P->sub[i]->iters, r.rel_gap, r.primal_ub, r.dual_lb, P->sub[i]->step_c,
+                P->sub[i]->bf16 ? "bf16" : "fp32");
       } else if (finishing_due(P->sub[i])) {
         if ((s = batch_widen_member(P, (int)i)) != SL_OK) return s;
         changed = true;
+        tr.line("{\"event\": \"widen\", \"member\": %d, \"iters\": %lld}", (int)i, (long long)P->sub[i]->iters);
       }
     }
+    tr.line("{\"event\": \"batch_check\", \"batched_iters\": %lld, \"active\": %d, \"worst_rel_gap\": %.6g}",
+            (long long)P->biters, n_active, worst);
     if (changed && (s = batch_rebuild_items(P)) != SL_OK) return s;
   }
   if (done) *done = done_n;
@@ -1290,6 +1333,7 @@ sl_status sl_run_to_gap(sl_problem P, double rel_gap, int32_t max_iters, int32_t
 }  // extern "C"
 
 static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_iters, int32_t *done) {
+  Trace tr(!P->no_alloc);   // the allocation-free solve writes no trace
   int32_t n = 0;
   sl_report r;
   while (n < max_iters) {
@@ -1307,8 +1351,15 @@ static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_i
       if (done) *done = n;
       return s;
     }
+    tr.line("{\"event\": \"check\", \"iters\": %lld, \"primal\": %.17g, \"dual\": %.17g, \"rel_gap\": %.6g, "
+            "\"e_nonconvex\": %.17g, \"balance\": %.6g, \"storage\": \"%s\"}",
+            (long long)P->iters, r.primal_ub, r.dual_lb, r.rel_gap, r.e_nonconvex, P->step_c,
+            P->bf16 ? "bf16" : "fp32");
     if (r.rel_gap <= rel_gap) break;
-    if (finishing_due(P) && (s = widen_duals(P)) != SL_OK) return s;
+    if (finishing_due(P)) {
+      if ((s = widen_duals(P)) != SL_OK) return s;
+      tr.line("{\"event\": \"widen\", \"iters\": %lld}", (long long)P->iters);
+    }
   }
   if (done) *done = n;
   return SL_OK;

@@ -6,9 +6,9 @@ adjoint recursion adds rounding of order K * 2^-24 per step count. Where a proje
 lies within rounding of the boundary between two parts of a graph (segment / kink, ball
 surface), FP32 and FP64 may pick different parts, which changes that entry's local Jacobian;
 such points are rare and their effect stays local. Held to: relative L2 error of the f and w
-gradients <= 1e-3 (2e-3 for the 200-iteration 256 x 256 workload) with every entry within
-2e-2 of the largest magnitude, the lambda gradient within 1e-4 relative (measured: 2e-7 ..
-9e-4, lambda 1e-6 .. 6e-6).
+gradients <= 1e-3 (also for the 200-iteration 256 x 256 workload) with every entry within
+1e-2 of the largest magnitude, the lambda gradient within 1e-4 relative (measured: rel L2
+2e-7 .. 9e-4, worst entry up to 6.6e-3 on the 256 x 256 workload, lambda 1e-6 .. 6e-6).
 """
 import numpy as np
 import pytest
@@ -67,7 +67,7 @@ def _check_close(got, ref, name, l2=1e-3):
     err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
     worst = np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
     print(f"{name}: rel L2 {err:.2e}, worst entry {worst:.2e} of max", flush=True)
-    assert err <= l2 and worst <= 2e-2, (name, err, worst)
+    assert err <= l2 and worst <= 1e-2, (name, err, worst)
 
 
 @pytest.mark.parametrize("name,wl,K,C", CASES, ids=[c[0] for c in CASES])
@@ -134,6 +134,12 @@ def test_autograd_function_matches_c_abi(orc):
     assert np.array_equal(f.grad.cpu().numpy(), gf)
     assert np.array_equal(w.grad.cpu().numpy(), gw)
     assert lam.grad.item() == gl
+    # one backward pass per forward pass: a second one (retain_graph) is a clear error
+    u = unrolled_solve(f, lam, w, gamma=wl.gamma, a=wl.a, nu=wl.nu, K=5, C=5)
+    loss = ((u - tgt) ** 2).sum()
+    loss.backward(retain_graph=True)
+    with pytest.raises(RuntimeError, match="one backward pass"):
+        loss.backward()
 
 
 def test_unrolled_errors():
@@ -176,8 +182,9 @@ def test_differentiation_workload_full_size(orc):
     _, uo = o.read_u()
     assert np.abs(u - uo).max() <= 1e-5
     gfo, glo, gwo = o.unrolled_backward(2.0 * (u.astype(np.float64) - wl.target))
-    # 200 iterations over 458k pixel-labels meet more part-boundary decisions (p on the
-    # ball surface in flat regions): measured rel L2 5.6e-4 (f) and 8.9e-4 (w)
-    _check_close(gf, gfo, "grad f", l2=2e-3)
-    _check_close(gw, gwo, "grad w", l2=2e-3)
+    # held to the 1e-3 relative bound of the adjoint (measured rel L2 5.6e-4 for f and 8.9e-4
+    # for w: 200 iterations over 458k pixel-labels meet more part-boundary decisions, p on the
+    # ball surface in flat regions, where FP32 and FP64 may differentiate different parts)
+    _check_close(gf, gfo, "grad f", l2=1e-3)
+    _check_close(gw, gwo, "grad w", l2=1e-3)
     assert abs(gl - glo) <= 1e-4 * abs(glo), (gl, glo)
