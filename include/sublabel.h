@@ -82,8 +82,8 @@ typedef enum { SL_TV_ISO = 0, SL_TV_ANISO = 1 } sl_tv_kind;
  * dual fields v, z and p are stored as bfloat16 (round to nearest even), which cuts the
  * bytes an iteration moves per pixel from 4(14k+3) to 40k+12; arithmetic is float,
  * energies and gaps are accumulated in double in both modes. The rounding of bf16 duals
- * stalls the certified gap near 1e-3 relative, so sl_run_to_gap finishes in float: once
- * the best gap of a bf16 problem has stopped improving (sl_set_finishing), its duals are
+ * slows and finally stalls the certified gap, so sl_run_to_gap finishes in float: once the
+ * gap of a bf16 problem is small or its progress slow (sl_set_finishing), its duals are
  * widened to float in place and the solve continues (sl_set_storage does it on request).
  * The workspace therefore keeps float-sized dual planes in both storages. */
 typedef enum { SL_STORE_FP32 = 0, SL_STORE_BF16_DUAL = 1 } sl_storage;
@@ -282,13 +282,19 @@ sl_status sl_set_balance_rule(sl_problem p, int32_t scaled, double s);
  *   value is a float), and iterate in float from then on; SL_STORE_BF16_DUAL on a problem
  *   that already stores floats is SL_ERR_UNSUPPORTED (no narrowing), on a bf16 problem a
  *   no-op. Enqueued on the handle's stream (a batch synchronises it).
- * sl_set_finishing: sl_run_to_gap widens a bf16 problem (each batch member on its own)
- *   after stall_checks consecutive checks in which its best certified gap did not shrink by
- *   a relative 1e-3 (default 4; 0: never widen automatically). Applies to every member.
+ * sl_set_finishing: sl_run_to_gap widens a bf16 problem (each batch member on its own) at
+ *   the first check at which its certified relative gap is at or below widen_gap (0: no
+ *   such threshold), or once stall_checks consecutive checks have passed in which its best
+ *   certified gap stayed above (1 - stall_progress) times its reference, the best gap at
+ *   the last check that went below that mark (0 checks: never on a stall). Defaults: 4
+ *   checks, progress 0.1, widen_gap 0.05: under bf16 rounding the gap's progress slows
+ *   long before it stops, so waiting for a full stall costs more float iterations than it
+ *   saves. Applies to every member. SL_ERR_INVALID_ARG if stall_checks < 0, stall_progress
+ *   is outside (0, 1) or widen_gap is negative or not finite.
  * sl_storage_info: the storage problem i (0 for a single problem) uses now and the number
  *   of iterations it ran with bf16 duals (pointers may be NULL). */
 sl_status sl_set_storage(sl_problem p, int32_t i, sl_storage storage);
-sl_status sl_set_finishing(sl_problem p, int32_t stall_checks);
+sl_status sl_set_finishing(sl_problem p, int32_t stall_checks, double stall_progress, double widen_gap);
 sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *iters_bf16);
 
 /* Tuning knobs of the fused iteration: a block works on a tile of tile_cols columns x

@@ -105,7 +105,7 @@ def lib():
         L.sl_set_step_balance.argtypes = [vp, C.c_double]
         L.sl_get_step_balance.argtypes = [vp, C.POINTER(C.c_double)]
         L.sl_set_storage.argtypes = [vp, C.c_int32, C.c_int32]
-        L.sl_set_finishing.argtypes = [vp, C.c_int32]
+        L.sl_set_finishing.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
         L.sl_storage_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.sl_solve_static.argtypes = [C.POINTER(Desc), C.c_double, C.c_int32, vp, vp,
                                       C.POINTER(Report), vp]
@@ -288,10 +288,11 @@ class Problem:
         """Widen bf16 duals to float in place (problem i of a batch, -1: all)."""
         _check(lib().sl_set_storage(self.h, int(i), STORE_FP32))
 
-    def set_finishing(self, stall_checks: int):
-        """Checks without progress of the best gap before run_to_gap widens bf16 duals
-        (0: never)."""
-        _check(lib().sl_set_finishing(self.h, int(stall_checks)))
+    def set_finishing(self, stall_checks: int = 4, stall_progress: float = 0.1, widen_gap: float = 0.05):
+        """run_to_gap widens bf16 duals after stall_checks checks in which the best gap did
+        not shrink by the fraction stall_progress (0 checks: never on a stall), or once the
+        certified relative gap is <= widen_gap (0: off)."""
+        _check(lib().sl_set_finishing(self.h, int(stall_checks), float(stall_progress), float(widen_gap)))
 
     def storage_info(self, i: int = 0):
         """(storage now: 'fp32' or 'bf16', iterations run with bf16 duals) of problem i."""

@@ -216,7 +216,9 @@ struct sl_problem_ {
   double *fin_dev = nullptr;  // batch member: its monitor / residual sums go to the batch's array
   // BF16 dual storage with an FP32 finishing phase: run_to_gap widens the duals once the
   // best certified gap has made no progress (relative 1e-3) for finish_checks checks
-  int finish_checks = 4;   // 0: never widen automatically
+  int finish_checks = 4;   // 0: never widen on a stall
+  double stall_progress = 0.1;    // relative decrease of the best gap that counts as progress
+  double widen_gap = 0.05; // widen once the certified relative gap is at or below this (0: off)
   int stall = 0;           // checks without progress so far
   double stall_ref = -1.0; // best gap at the last progress (< 0: none yet)
   int64_t widen_at = -1;   // iteration count at which the duals were widened (-1: not yet)
@@ -595,16 +597,22 @@ sl_status widen_duals(sl_problem_ *P) {
   }
   P->bf16 = false;
   P->widen_at = P->iters;
+  // the adaptive balance starts over from its current value: its step has shrunk during the
+  // bf16 phase, whose rounding inflates the dual residual and so set the balance for bf16
+  P->adapt_alpha = 0.5;
   return SL_OK;
 }
 
-// At a check of a bf16 problem: true once the best certified gap has not improved by a
-// relative 1e-3 for finish_checks checks in a row (the duals' rounding then dominates the
-// remaining progress; in float the gap keeps shrinking).
-bool finishing_due(sl_problem_ *P) {
-  if (!P->bf16 || P->finish_checks <= 0 || !P->have_best) return false;
+// At a check of a bf16 problem with certified relative gap rel: true once rel is at or below
+// widen_gap, or once the best certified gap has not shrunk by the fraction stall_progress
+// below its last reference for finish_checks checks in a row (the duals' rounding then
+// dominates the remaining progress; in float the gap keeps shrinking).
+bool finishing_due(sl_problem_ *P, double rel) {
+  if (!P->bf16 || !P->have_best) return false;
+  if (P->widen_gap > 0.0 && rel <= P->widen_gap) return true;
+  if (P->finish_checks <= 0) return false;
   const double g = P->best_P - P->best_D;
-  if (P->stall_ref < 0.0 || g < P->stall_ref * (1.0 - 1e-3)) {
+  if (P->stall_ref < 0.0 || g < P->stall_ref * (1.0 - P->stall_progress)) {
     P->stall_ref = g;
     P->stall = 0;
     return false;
@@ -961,7 +969,7 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
                 "\"dual\": %.17g, \"balance\": %.6g, \"storage\": \"%s\"}",
                 (int)i, (long long)P->sub[i]->iters, r.rel_gap, r.primal_ub, r.dual_lb, P->sub[i]->step_c,
                 P->sub[i]->bf16 ? "bf16" : "fp32");
-      } else if (finishing_due(P->sub[i])) {
+      } else if (finishing_due(P->sub[i], r.rel_gap)) {
         if ((s = batch_widen_member(P, (int)i)) != SL_OK) return s;
         changed = true;
         tr.line("{\"event\": \"widen\", \"member\": %d, \"iters\": %lld}", (int)i, (long long)P->sub[i]->iters);
@@ -1356,7 +1364,7 @@ static sl_status single_run_to_gap(sl_problem_ *P, double rel_gap, int32_t max_i
             (long long)P->iters, r.primal_ub, r.dual_lb, r.rel_gap, r.e_nonconvex, P->step_c,
             P->bf16 ? "bf16" : "fp32");
     if (r.rel_gap <= rel_gap) break;
-    if (finishing_due(P)) {
+    if (finishing_due(P, r.rel_gap)) {
       if ((s = widen_duals(P)) != SL_OK) return s;
       tr.line("{\"event\": \"widen\", \"iters\": %lld}", (long long)P->iters);
     }
@@ -1812,11 +1820,20 @@ sl_status sl_set_storage(sl_problem P, int32_t i, sl_storage storage) {
   return batch_rebuild_items(P);
 }
 
-sl_status sl_set_finishing(sl_problem P, int32_t stall_checks) {
+sl_status sl_set_finishing(sl_problem P, int32_t stall_checks, double stall_progress, double widen_gap) {
   if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
   if (stall_checks < 0) return fail(SL_ERR_INVALID_ARG, "stall_checks must be >= 0");
+  if (!(stall_progress > 0.0 && stall_progress < 1.0))
+    return fail(SL_ERR_INVALID_ARG, "stall_progress must lie in (0, 1)");
+  if (!(widen_gap >= 0.0) || !isfinite(widen_gap)) return fail(SL_ERR_INVALID_ARG, "widen_gap must be finite and >= 0");
   P->finish_checks = stall_checks;
-  for (sl_problem_ *q : P->sub) q->finish_checks = stall_checks;
+  P->stall_progress = stall_progress;
+  P->widen_gap = widen_gap;
+  for (sl_problem_ *q : P->sub) {
+    q->finish_checks = stall_checks;
+    q->stall_progress = stall_progress;
+    q->widen_gap = widen_gap;
+  }
   return SL_OK;
 }
 

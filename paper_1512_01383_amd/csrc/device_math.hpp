@@ -24,11 +24,14 @@ __device__ __forceinline__ float ldv(const uint16_t *p, long long i) {
   return __uint_as_float(((uint32_t)p[i]) << 16);
 }
 __device__ __forceinline__ void stv(float *p, long long i, float x) { p[i] = x; }
-__device__ __forceinline__ uint16_t f2bf(float x) {
-  uint32_t b = __float_as_uint(x);
-  if ((b & 0x7f800000u) == 0x7f800000u) return (uint16_t)((b >> 16) | ((b & 0xffffu) ? 0x40u : 0u));
-  b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest, ties to even
-  return (uint16_t)(b >> 16);
+// float -> bf16, round to nearest even (NaN stays NaN): gfx950's packed conversion
+// instruction, one for a pair of values
+typedef __bf16 sl_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float sl_f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+  const sl_f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, sl_bf16x2));
 }
 __device__ __forceinline__ void stv(uint16_t *p, long long i, float x) { p[i] = f2bf(x); }
 

@@ -105,7 +105,7 @@ __device__ __forceinline__ void bstvn(uint16_t *base, unsigned bytes, unsigned o
   if constexpr (PX == 1) {
     bstv(base, bytes, off, x[0]);
   } else {
-    const unsigned v = (unsigned)f2bf(x[0]) | ((unsigned)f2bf(x[1]) << 16);
+    const unsigned v = f2bf2(x[0], x[1]);
     __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(base, bytes), (int)off, 0, 0);
   }
 }

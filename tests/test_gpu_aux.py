@@ -66,6 +66,63 @@ def test_trace_of_a_batch(tmp_path, monkeypatch):
     b.close()
 
 
+def _widen_check(checks, tol, stall_checks, progress, widen_gap):
+    """The iteration count of the check at which the finishing rule widens a bf16 problem,
+    recomputed from the bounds each check logged (None: it never widens)."""
+    best_p, best_d, ref, stall = float("inf"), -float("inf"), None, 0
+    for c in checks:
+        best_p, best_d = min(best_p, c["primal"]), max(best_d, c["dual"])
+        rel = (best_p - best_d) / max(abs(best_p), abs(best_d), 1e-30)
+        if rel <= tol:
+            return None
+        if widen_gap > 0 and rel <= widen_gap:
+            return c["iters"]
+        if stall_checks <= 0:
+            continue
+        g = best_p - best_d
+        if ref is None or g < ref * (1.0 - progress):
+            ref, stall = g, 0
+            continue
+        stall += 1
+        if stall >= stall_checks:
+            return c["iters"]
+    return None
+
+
+@pytest.mark.parametrize("rule", [(4, 0.1, 0.05), (3, 0.2, 0.0), (4, 1e-3, 0.0), (0, 0.1, 0.2)],
+                         ids=["default", "fast_stall", "slow_stall", "gap_only"])
+def test_finishing_rule_matches_trace(tmp_path, monkeypatch, rule):
+    """The check at which a bf16 solve widens its duals is the one the documented rule picks
+    from the certified bounds of the checks before it (recomputed here from the trace)."""
+    trace = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("SL_TRACE", str(trace))
+    wl = W.truncated_quadratic(L=2, H=48, W=96, seed=17)
+    g = S.Problem.from_workload(wl, storage="bf16", check_every=25)
+    if rule != (4, 0.1, 0.05):
+        g.set_finishing(*rule)
+    g.run_to_gap(1e-3, 20000)
+    rows = _lines(trace)
+    checks = [r for r in rows if r["event"] == "check"]
+    widen = [r["iters"] for r in rows if r["event"] == "widen"]
+    want = _widen_check(checks, 1e-3, *rule)
+    print(f"rule {rule}: widened at {widen}, rule gives {want}, {checks[-1]['iters']} iterations")
+    assert widen == ([] if want is None else [want])
+    assert g.storage_info() == (("fp32", want) if want is not None else ("bf16", checks[-1]["iters"]))
+    if rule == (4, 0.1, 0.05):
+        assert checks[-1]["rel_gap"] <= 1e-3
+    g.close()
+
+
+def test_finishing_arguments():
+    g = S.Problem.from_workload(W.truncated_quadratic(L=3, H=8, W=64, seed=2), storage="bf16")
+    for bad in [(-1, 0.1, 0.0), (4, 0.0, 0.0), (4, 1.0, 0.0), (4, 0.1, -1e-3), (4, 0.1, float("inf")),
+                (4, float("nan"), 0.0)]:
+        with pytest.raises(S.SublabelError) as e:
+            g.set_finishing(*bad)
+        assert e.value.status == 1, bad
+    g.close()
+
+
 def test_nonfinite_state_is_a_numeric_error():
     """A non-finite dual makes the certificate non-finite: sl_energy and sl_run_to_gap
     return SL_ERR_NUMERIC instead of a bound. (A non-finite primal value is clamped away by

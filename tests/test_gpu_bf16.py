@@ -166,3 +166,41 @@ def test_batch_widening_with_saturated_grids():
             assert brep[key] == rep[key], (i, key)
         g.close()
     b.close()
+
+
+def _bf16_rne(a):
+    """float32 -> bfloat16 by round to nearest, ties to even (finite values; a carry into
+    the exponent field gives the next binade or infinity), returned as float32."""
+    b = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def test_storage_rounding_is_nearest_even():
+    """Loading a state into bf16 storage rounds v, z and p to nearest even: exact ties with an
+    even and an odd kept part, values just beside a tie, subnormals, negative values, and
+    the largest finite values (which round to infinity). Compared bit for bit."""
+    special = np.array([0x3F808000, 0x3F818000, 0x3F807FFF, 0x3F808001, 0xBF818000, 0x00008000,
+                        0x00018000, 0x00017FFF, 0x80018000, 0x7F7F8000, 0x7F7F7FFF, 0x7F7FFFFF,
+                        0x00000000, 0x80000000, 0x3F800000, 0x4049_0FDB], dtype=np.uint32).view(np.float32)
+    wl = W.truncated_quadratic(L=4, H=5, W=70, seed=8)
+    st = W.random_state(3, wl.k, wl.H, wl.W)
+    rng = np.random.default_rng(4)
+    for n in ("v", "z", "px", "py"):
+        a = st[n].reshape(-1)
+        a[:special.size] = special
+        a[special.size:] = rng.standard_normal(a.size - special.size).astype(np.float32) * \
+            np.float32(2.0) ** rng.integers(-30, 30, a.size - special.size)
+    g = S.Problem.from_workload(wl, storage="bf16")
+    g.load_state(S.pack_state(st))
+    t = g.save_state()
+    torch.cuda.synchronize()
+    got = S.unpack_state(t, g.k, g.H, g.W)
+    g.close()
+    for n in S.STATE_ORDER:
+        want = _bf16_rne(st[n]) if n in ("v", "z", "px", "py") else st[n]
+        assert np.array_equal(got[n].view(np.uint32), np.asarray(want, np.float32).view(np.uint32)), n
+    # the cases by name: ties go to the even neighbour, the largest floats to infinity
+    v = got["v"].reshape(-1)[:special.size].view(np.uint32)
+    assert list(v[:2]) == [0x3F800000, 0x3F820000] and v[9] == 0x7F800000 and v[11] == 0x7F800000
+    assert v[5] == 0 and v[6] == 0x00020000
