@@ -148,7 +148,7 @@ __device__ __forceinline__ void flat_vjp(float nu, float g0, float g1, float ig0
   w0b = 0.f;
 }
 
-// Piecewise-linear projection with the same region logic as PLProj, remembering the part
+// Piecewise-linear projection with the same region logic as PLScan, remembering the part
 // it lands on together with the derivatives of that part's offset r and kink position b
 // with respect to the data centre c.
 struct PLVjp {

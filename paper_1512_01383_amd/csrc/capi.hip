@@ -116,7 +116,7 @@ Layout make_layout(const sl_problem_desc *d, int nb_mon) {
   L.off_sinfod = take(d->rho == SL_RHO_TRUNC_QUAD ? pf : 0);
   L.off_w = take((!sampled && d->samples) ? (size_t)d->L * pf : 0);
   L.off_cost = take(sampled ? (size_t)2 * d->M * pf : 0);
-  L.off_tau = take(sampled ? (size_t)d->M * 4 : 0);
+  L.off_tau = take(sampled ? (size_t)d->M * 16 : 0);
   L.off_taud = take(sampled ? (size_t)d->M * 8 : 0);
   L.off_monu = take((size_t)k * L.ps * 8);
   L.off_monb = take((size_t)L.ps * 8);
@@ -241,7 +241,7 @@ struct sl_problem_ {
   bool have_best = false;
   int check_every = 50;
   int nb_mon = 0;
-  float tau_host[SLI_MAXM] = {};
+  float tau_tab[SLI_MAXM][4] = {};   // per sample: position, 1/(1+t^2), 1/(t_m - t_{m-1}), 0
   double taud_host[SLI_MAXM] = {};
   double fin[SLI_NMON];
   // pinned host staging for the small device-to-host copies of the monitor and residual
@@ -390,7 +390,11 @@ void fill_args(sl_problem_ *P) {
   } else {
     for (int m = 0; m < d->M; m++) {
       P->taud_host[m] = (tau[m] - P->shift) / P->scale;
-      P->tau_host[m] = (float)P->taud_host[m];
+      const double t = (double)(float)P->taud_host[m];   // the position the iteration uses
+      P->tau_tab[m][0] = (float)t;
+      P->tau_tab[m][1] = (float)(1.0 / (1.0 + t * t));
+      P->tau_tab[m][2] = m > 0 ? (float)(1.0 / (t - (double)P->tau_tab[m - 1][0])) : 0.f;
+      P->tau_tab[m][3] = 0.f;
     }
     for (int j = 0; j < L; j++)
       for (int m = 0; m < d->M; m++)
@@ -413,7 +417,7 @@ IterPtrs<float> iter_ptrs_f(sl_problem_ *P) {
   Q.fn = (const float *)(P->ws + P->lay.off_fn);
   Q.wadd = (const float *)(P->ws + P->lay.off_w);
   Q.cost = (const float *)(P->ws + P->lay.off_cost);
-  Q.tau = (const float *)(P->ws + P->lay.off_tau);
+  Q.tau = (const float4 *)(P->ws + P->lay.off_tau);
   Q.sinfo = (const unsigned *)(P->ws + P->lay.off_sinfo);
   Q.spi = Q.sp;
   Q.vi = Q.v;
@@ -1290,7 +1294,7 @@ static sl_status init_impl(sl_problem_ *P, const sl_problem_desc *desc, void *ws
   } else {
     float *tau_d = (float *)(P->ws + lay.off_tau);
     double *taud_d = (double *)(P->ws + lay.off_taud);
-    if ((e = hipMemcpyAsync(tau_d, P->tau_host, 4 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
+    if ((e = hipMemcpyAsync(tau_d, P->tau_tab, 16 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
       return hip_fail(e, "copy tau");
     if ((e = hipMemcpyAsync(taud_d, P->taud_host, 8 * desc->M, hipMemcpyHostToDevice, P->st)) != hipSuccess)
       return hip_fail(e, "copy tau");

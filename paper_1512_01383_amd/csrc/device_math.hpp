@@ -197,70 +197,123 @@ __device__ __forceinline__ void proj_quad(float a, float ia, float c, float g0, 
 // ill-conditioned in FP32 for points far below the graph. Where rounding puts a point on
 // a region boundary, both neighbouring answers coincide up to rounding.
 
-struct PLProj {
-  float y0, w0, gmax, bd, by, bw, tp, cp, lo, ay, aw;
-  bool has, found;
+// A part's wave-uniform constants come from a per-sample table: its slope t, 1/(1 + t^2)
+// (the foot of the perpendicular) and 1/(t - t_prev) (the kink with the previous part).
+// The scan decides the region and keeps the conjugate's value at y0 (the maximum over the
+// parts: is the point below the graph?); the nearest-point fallback for a point that
+// rounding leaves in no region runs as a second pass over the parts (PLNear). Each region
+// test is one comparison of a three-way minimum and its outcome a select, so the scan runs
+// on the vector unit alone (no lane-mask arithmetic or branches per part); the regions are
+// disjoint, so a later hit replaces an earlier one only where rounding puts the point on a
+// shared boundary, where both answers agree up to rounding.
+struct PLScan {
+  float y0, w0, gmax, lo, tp, cp, irp, ay, aw, fnd;
+  bool has;
   __device__ __forceinline__ void init(float y, float w) {
     y0 = y;
     w0 = w;
     gmax = -SL_INF;
-    bd = SL_INF;
-    by = ay = y;
-    bw = aw = w;
     lo = -SL_INF;
-    has = found = false;
-    tp = cp = 0.f;
+    tp = cp = irp = 0.f;
+    ay = y;
+    aw = w;
+    fnd = 0.f;
+    has = false;
   }
-  // linear part of slope t through (., -r) restricted to [l, hi]
-  __device__ __forceinline__ void seg(float t, float r, float l, float hi) {
-    float mu = (t * y0 - r - w0) * frcp(1.f + t * t);   // >= 0: point below the line
-    float yr = y0 - mu * t;                          // perpendicular foot
-    if (!found && mu >= 0.f && yr >= l && yr <= hi) {
-      found = true;
-      ay = yr;
-      aw = t * yr - r;
+  // the previous part (slope tp through (., -cp)) on [lo, hi]: does the point lie in its
+  // strip (foot on the part, point below the line)?
+  __device__ __forceinline__ void seg(float hi) {
+    const float mu = (tp * y0 - cp - w0) * irp;   // >= 0: point below the line
+    const float yr = y0 - mu * tp;                // perpendicular foot
+    const bool hit = fminf(fminf(mu, yr - lo), hi - yr) >= 0.f;
+    ay = hit ? yr : ay;
+    aw = hit ? tp * yr - cp : aw;
+    fnd = hit ? 1.f : fnd;
+  }
+  // kink at y = b between the previous part and the part of slope t1: its normal cone is
+  // {(b, g(b)) + a (tp, -1) + c (t1, -1) : a, c >= 0}
+  __device__ __forceinline__ void kink(float b, float t1) {
+    const float gb = tp * b - cp;
+    const float dw = gb - w0, dy = y0 - b;
+    const bool hit = fminf(fminf(dw, dy - tp * dw), t1 * dw - dy) >= 0.f;
+    ay = hit ? b : ay;
+    aw = hit ? gb : aw;
+    fnd = hit ? 1.f : fnd;
+  }
+  __device__ __forceinline__ void push(const float4 &T, float r) {
+    gmax = fmaxf(gmax, T.x * y0 - r);
+    if (has) {
+      const float b = (r - cp) * T.z;
+      seg(b);
+      kink(b, T.x);
+      lo = b;
     }
-    float yf = fminf(fmaxf(yr, l), hi);              // fallback: nearest point of the part
-    float wf = t * yf - r;
-    float d = (yf - y0) * (yf - y0) + (wf - w0) * (wf - w0);
+    tp = T.x;
+    cp = r;
+    irp = T.y;
+    has = true;
+  }
+  // true when the point lies below the graph but in no region (the caller then runs PLNear)
+  __device__ __forceinline__ bool finish(float &y, float &w) {
+    seg(SL_INF);
+    const bool out = w0 < gmax;
+    y = out ? ay : y;
+    w = out ? aw : w;
+    return out && fnd == 0.f;
+  }
+};
+
+// An entry of a read-only table at a wave-uniform index, read through the constant address
+// space: the load goes through the scalar cache into registers shared by the wave and its
+// wait does not cover the vector loads in flight (a plain global pointer gives a vector
+// load, since nothing tells the compiler that the kernel does not write the table).
+typedef float sl_f32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) sl_f32x4 sl_const_f32x4;
+__device__ __forceinline__ float4 ldtab(const float4 *tab, int m) {
+  const sl_f32x4 v = ((sl_const_f32x4 *)tab)[m];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// nearest point of the graph among the nearest points of its parts
+struct PLNear {
+  float y0, w0, bd, by, bw, lo, tp, cp, irp;
+  bool has;
+  __device__ __forceinline__ void init(float y, float w) {
+    y0 = y;
+    w0 = w;
+    bd = SL_INF;
+    by = y;
+    bw = w;
+    lo = -SL_INF;
+    tp = cp = irp = 0.f;
+    has = false;
+  }
+  __device__ __forceinline__ void part(float hi) {
+    const float mu = (tp * y0 - cp - w0) * irp;
+    const float yf = fminf(fmaxf(y0 - mu * tp, lo), hi);
+    const float wf = tp * yf - cp;
+    const float d = (yf - y0) * (yf - y0) + (wf - w0) * (wf - w0);
     if (d < bd) {
       bd = d;
       by = yf;
       bw = wf;
     }
   }
-  // kink at y = b between parts of slopes t0 < t1: its normal cone is
-  // {(b, g(b)) + a (t0, -1) + c (t1, -1) : a, c >= 0}
-  __device__ __forceinline__ void kink(float b, float t0, float r0, float t1) {
-    float gb = t0 * b - r0;
-    float dw = gb - w0, dy = y0 - b;
-    if (!found && dw >= 0.f && t0 * dw <= dy && dy <= t1 * dw) {
-      found = true;
-      ay = b;
-      aw = gb;
-    }
-  }
-  // next vertex (t, r) with the kink b between it and the previous vertex given
-  __device__ __forceinline__ void push_k(float t, float r, float b) {
-    gmax = fmaxf(gmax, t * y0 - r);
+  __device__ __forceinline__ void push(const float4 &T, float r) {
     if (has) {
-      seg(tp, cp, lo, b);
-      kink(b, tp, cp, t);
+      const float b = (r - cp) * T.z;
+      part(b);
       lo = b;
     }
-    tp = t;
+    tp = T.x;
     cp = r;
+    irp = T.y;
     has = true;
   }
-  __device__ __forceinline__ void push(float t, float r) {
-    push_k(t, r, has ? (r - cp) * frcp(t - tp) : 0.f);
-  }
   __device__ __forceinline__ void finish(float &y, float &w) {
-    seg(tp, cp, lo, SL_INF);
-    if (w0 < gmax) {
-      y = found ? ay : by;
-      w = found ? aw : bw;
-    }
+    part(SL_INF);
+    y = by;
+    w = bw;
   }
 };
 

@@ -13,7 +13,7 @@
 //   fn[1]       data image mapped to normalised label coordinates (QUAD, TRUNC_QUAD)
 //   w[L]        per-label additive values (optional)
 //   cost[M]     per-interval convex envelopes of the sampled costs (SAMPLED)
-//   tau[M]      normalised sample positions (SAMPLED)
+//   tau[M][4]   per sample (SAMPLED): normalised position t_m, 1/(1+t_m^2), 1/(t_m - t_{m-1}), 0
 //   mon_u[k], mon_b[1]  monitor scratch (repaired lifted u, back-projected u)
 //   partials    per-block FP64 partial sums of the monitor, final sums
 #pragma once
@@ -60,7 +60,8 @@ struct IterPtrs {
   const DT *pin;
   DT *pout;
   float *qd;
-  const float *fn, *wadd, *cost, *tau;
+  const float *fn, *wadd, *cost;
+  const float4 *tau;      // sample table (SAMPLED): t_m, 1/(1+t_m^2), 1/(t_m - t_{m-1}), 0
   const unsigned *sinfo;  // straddling intervals per pixel (TRUNC_QUAD)
   // read side of sp, v, z, qd: the same planes for an iteration in place; distinct ones
   // when a replay keeps every state (the new values go to the slot of the next state)

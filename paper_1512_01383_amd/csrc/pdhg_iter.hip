@@ -362,10 +362,14 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   }
   const unsigned em = ev ? (unsigned)((long long)er * W + ec) * 4u : kOOB;
   const unsigned eml = (tx == 0 && c0 > 0 && r < H) ? (unsigned)((long long)r * W + c0 - 1) * (unsigned)sizeof(DT) : kOOB;
+  // sampled costs: the first kSmp envelope samples after the interval's lower label ride
+  // with the step's other loads
+  constexpr int kSmp = PIECE == SLI_SAMPLED ? 8 : 1;
   struct Step {
     float u[PX], up[PX], uu[PX], uup[PX], ud[PX], udp[PX], px[PX], py[PX], pxu[PX], pyu[PX], v[PX], z[PX],
         wh[PX];
     float eu, eup, epx, epy;
+    float smp[PX][kSmp];
   };
   // past the chunk the planes have size 0 (nothing is read)
   auto load_step = [&](int i, Step &o) {
@@ -394,10 +398,20 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
 #pragma unroll
       for (int e = 0; e < PX; e++) o.wh[e] = 0.f;
     }
+    if (PIECE == SLI_SAMPLED) {
+      const int m0 = __builtin_amdgcn_readfirstlane(i < i1 ? A.sidx[i] : 0);
+      const int m1 = __builtin_amdgcn_readfirstlane(i < i1 ? A.sidx[i + 1] : 0);
+#pragma unroll
+      for (int e = 0; e < PX; e++)
+#pragma unroll
+        for (int q = 0; q < kSmp; q++)
+          o.smp[e][q] = m0 + 1 + q <= m1 ? bld(P.cost + (size_t)(m0 + 1 + q) * ps, b4, xm + 4u * (unsigned)e) : 0.f;
+    }
   };
   float pre[PX], wlo[PX];           // sum of the chunk's new v so far; additive value at label i
+  float rlast[PX];                  // sampled costs: envelope value at the last label's upper sample
 #pragma unroll
-  for (int e = 0; e < PX; e++) pre[e] = wlo[e] = 0.f;
+  for (int e = 0; e < PX; e++) pre[e] = wlo[e] = rlast[e] = 0.f;
   if (ADD && i0 < i1) bldn<PX>(wlo, P.wadd + (size_t)(i0) * ps, nb4, xm);
 
   auto label_step = [&](int i, const Step &cu, Step &nx) {
@@ -483,12 +497,40 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
           else
             proj_flat(A.nu, g0, g1, A.ig0[i], A.ig1[i], y, w);
         } else {
-          PLProj pl;
+          // the interval's envelope samples m0 .. m1: m0 is the previous label step's last
+          // (the shared label sample), carried over; the next kSmp came with this step's
+          // loads; any further ones are loaded eight at a time
+          const int m0 = __builtin_amdgcn_readfirstlane(A.sidx[i]);
+          const int m1 = __builtin_amdgcn_readfirstlane(A.sidx[i + 1]);
+          const unsigned xe = xm + 4u * (unsigned)e;
+          PLScan pl;
           pl.init(y, w);
-          const int m0 = A.sidx[i], m1 = A.sidx[i + 1];
-          for (int m = m0; m <= m1; m++)
-            pl.push(P.tau[m], bld(P.cost + (size_t)(m) * ps, nb4, xm + 4u * (unsigned)e));
-          pl.finish(y, w);
+          pl.push(ldtab(P.tau, m0), i > i0 ? rlast[e] : bld(P.cost + (size_t)(m0) * ps, nb4, xe));
+          float4 tq[kSmp];   // table entries, all requested before the first is used
+#pragma unroll
+          for (int q = 0; q < kSmp; q++) tq[q] = ldtab(P.tau, min(m0 + 1 + q, m1));
+#pragma unroll
+          for (int q = 0; q < kSmp; q++)
+            if (m0 + 1 + q <= m1) pl.push(tq[q], cu.smp[e][q]);
+          for (int mb = m0 + 1 + kSmp; mb <= m1; mb += 8) {
+            float rr[8];
+            float4 tr[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+              rr[q] = bld(P.cost + (size_t)(min(mb + q, m1)) * ps, nb4, xe);
+              tr[q] = ldtab(P.tau, min(mb + q, m1));
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++)
+              if (mb + q <= m1) pl.push(tr[q], rr[q]);
+          }
+          rlast[e] = pl.cp;
+          if (pl.finish(y, w)) {   // rare: no region holds the point (rounding)
+            PLNear nn;
+            nn.init(y, w);
+            for (int m = m0; m <= m1; m++) nn.push(ldtab(P.tau, m), bld(P.cost + (size_t)(m) * ps, nb4, xe));
+            nn.finish(y, w);
+          }
         }
         if (ADD) {
           y += bs;
