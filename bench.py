@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="batch",
-                    choices=["tq", "stereo", "phase", "batch", "diff", "labels", "cpu"],
+                    choices=["tq", "stereo", "phase", "batch", "diff", "labels", "cpu", "temporal"],
                     help="batch: 64 mixed instances in one persistent launch per iteration "
                          "(default); tq: one truncated-quadratic instance; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
@@ -121,6 +121,8 @@ def main():
         return bench_labels(args)
     if args.workload == "cpu":
         return bench_cpu(args)
+    if args.workload == "temporal":
+        return bench_temporal(args)
 
     if args.workload == "stereo":
         wl = W.stereo()            # sampled costs, 384x288, 64 disparities, L = 8
@@ -856,6 +858,86 @@ def bench_cpu(args):
         "cpu": {"cores": ncores, "cpu_model": cpu_model(), "kind": "oracle"},
         "workloads": rows,
     }
+    print(json.dumps(out))
+
+
+BAND_IX, BAND_IY, BAND_RING = 60, 12, 2   # interior and ring of the two-iteration kernel's tiles
+
+
+def band_bytes_per_pass(wl) -> int:
+    """Bytes one two-iteration pass reads and writes: every tile loads its interior plus the
+    ring (clipped to the image) of the 8k+1 state planes and the data plane (and the
+    straddle table for truncated quadratics), and writes the interior's 8k+1 planes."""
+    H, Wd, k = wl.H, wl.W, wl.k
+    loaded = 0
+    for r0 in range(0, H, BAND_IY):
+        rows = min(H, r0 + BAND_IY + BAND_RING) - max(0, r0 - BAND_RING)
+        for c0 in range(0, Wd, BAND_IX):
+            loaded += rows * (min(Wd, c0 + BAND_IX + BAND_RING) - max(0, c0 - BAND_RING))
+    read_planes = 8 * k + 2 + (1 if wl.rho == 1 else 0)
+    return 4 * (read_planes * loaded + (8 * k + 1) * H * Wd)
+
+
+def bench_temporal(args):
+    """Temporal blocking (two iterations per pass over the state, k <= 3) against the
+    one-pass kernel on the same problems: HIP-event time per iteration of each (the
+    one-pass kernel in its automatic and in its one-group configuration, the two-iteration
+    passes in groups of four iterations), the one-pass algorithmic bytes per iteration and
+    the bytes a two-iteration pass moves (reported apart: temporal blocking changes the
+    accounting). Value: pixel-label-iterations/s of the two-iteration path on the largest
+    instance."""
+    import torch
+    import paper_1512_01383_amd as S
+    import workloads as W
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def timed(g, iters):
+        g.run(8)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        g.run(iters)
+        e1.record(g.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / iters
+
+    cases = [("rof_64_L2", W.rof(), 2000),
+             ("rof_2048_L2", W.rof(H=2048, W=2048, seed=11), 200),
+             ("tq_2048_L2", W.truncated_quadratic(L=2, H=2048, W=2048, seed=12), 200),
+             ("tq_2048_L3", W.truncated_quadratic(L=3, H=2048, W=2048, seed=13), 200),
+             ("tq_2048_L4", W.truncated_quadratic(L=4, H=2048, W=2048, seed=14), 200),
+             ("tq_512_L2", W.truncated_quadratic(L=2, H=512, W=512, seed=15), 1000),
+             ("tq_512_L4", W.truncated_quadratic(L=4, H=512, W=512, seed=16), 1000)]
+    rows = {}
+    for name, wl, iters in cases:
+        g = S.Problem.from_workload(wl, device=dev)
+        auto_ms = timed(g, iters)
+        auto_tiling = list(g.get_tiling())
+        g.set_tiling(1, 4, 64)
+        one_ms = timed(g, iters)
+        g.set_temporal(True)
+        band_ms = timed(g, iters)
+        g.close()
+        nb1 = algorithmic_bytes_per_pixel(wl.k, wl.rho, wl.M, False, False) * wl.H * wl.W
+        nbb = band_bytes_per_pass(wl)
+        rows[name] = {"H": wl.H, "W": wl.W, "L": wl.L, "iters": iters,
+                      "one_pass_ms": auto_ms, "one_pass_tiling": auto_tiling, "one_group_ms": one_ms,
+                      "two_iteration_ms": band_ms, "speedup": auto_ms / band_ms,
+                      "one_pass_bytes_per_iteration": nb1, "two_iteration_bytes_per_pass": nbb,
+                      "one_pass_GBs": nb1 / (auto_ms * 1e-3) / 1e9,
+                      "two_iteration_GBs": nbb / (2 * band_ms * 1e-3) / 1e9}
+        print(f"{name}: one-pass {auto_ms * 1e3:.1f} us, two-iteration {band_ms * 1e3:.1f} us per iteration",
+              file=sys.stderr, flush=True)
+    big = rows["tq_2048_L2"]
+    out = {"metric": "lifted PDHG pixel-label-iter/s", "unit": "pixel-label-iter/s",
+           "value": big["H"] * big["W"] * (big["L"] - 1) / (big["two_iteration_ms"] * 1e-3),
+           "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": big["two_iteration_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "temporal blocking: two iterations per pass over the state against "
+                                  "one per pass, k <= 3; value on truncated quadratic 2048x2048, L=2"},
+           "roofline": None, "cpu_baseline": None, "cases": rows}
     print(json.dumps(out))
 
 

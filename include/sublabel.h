@@ -294,6 +294,23 @@ sl_status sl_set_balance_rule(sl_problem p, int32_t scaled, double s);
  * sl_storage_info: the storage problem i (0 for a single problem) uses now and the number
  *   of iterations it ran with bf16 duals (pointers may be NULL). */
 sl_status sl_set_storage(sl_problem p, int32_t i, sl_storage storage);
+
+/* Temporal blocking (the iteration of Sec. 4 run twice per pass over the state): for a
+ * single problem with L <= 4 labels (k <= 3), quadratic or truncated-quadratic data
+ * without additive values and FP32 storage, sl_run and sl_run_to_gap may execute groups
+ * of four iterations as two passes that each read the state once and write it once,
+ * through a shadow copy of the state in a caller-owned workspace. The iterates are
+ * bitwise those of the one-pass kernel with one label group (launch configurations with
+ * G = 1); other configurations differ in rounding only. Iterations of the unrolled
+ * forward pass and of sl_autotune keep the one-pass kernel.
+ * sl_temporal_workspace_size: bytes of that workspace ((8k+1) planes of 4 H*W bytes,
+ *   rounded as the state's planes are).
+ * sl_set_temporal: ws (device, 256-byte aligned, owned by the caller and kept valid while
+ *   set) enables the two-iteration passes, ws = NULL disables them. Errors:
+ *   SL_ERR_UNSUPPORTED for batches, k > 3, sampled data, additive values and bf16
+ *   storage; SL_ERR_WORKSPACE if ws is misaligned or too small. */
+sl_status sl_temporal_workspace_size(sl_problem p, size_t *bytes);
+sl_status sl_set_temporal(sl_problem p, void *ws, size_t bytes);
 sl_status sl_set_finishing(sl_problem p, int32_t stall_checks, double stall_progress, double widen_gap);
 sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *iters_bf16);
 

@@ -107,6 +107,8 @@ def lib():
         L.sl_set_storage.argtypes = [vp, C.c_int32, C.c_int32]
         L.sl_set_finishing.argtypes = [vp, C.c_int32, C.c_double, C.c_double]
         L.sl_storage_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.sl_temporal_workspace_size.argtypes = [vp, C.POINTER(sz)]
+        L.sl_set_temporal.argtypes = [vp, vp, sz]
         L.sl_solve_static.argtypes = [C.POINTER(Desc), C.c_double, C.c_int32, vp, vp,
                                       C.POINTER(Report), vp]
         L.sl_destroy.argtypes = [vp]
@@ -118,7 +120,8 @@ def lib():
                      "sl_autotune", "sl_unrolled_workspace_size", "sl_unrolled_forward",
                      "sl_unrolled_backward", "sl_set_step_balance", "sl_get_step_balance",
                      "sl_residuals", "sl_set_residual_target", "sl_solve_static",
-                     "sl_set_storage", "sl_set_finishing", "sl_storage_info", "sl_set_balance_rule"):
+                     "sl_set_storage", "sl_set_finishing", "sl_storage_info", "sl_set_balance_rule",
+                     "sl_temporal_workspace_size", "sl_set_temporal"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -283,6 +286,22 @@ class Problem:
         """Adaptive balance: raw residual norms (scaled=False) or residuals relative to
         |K^T y| and |K x| (scaled=True), compared with target ratio s."""
         _check(lib().sl_set_balance_rule(self.h, 1 if scaled else 0, float(s)))
+
+    def set_temporal(self, on: bool = True):
+        """Run groups of four iterations as two two-iteration passes (k <= 3, FP32,
+        quadratic or truncated-quadratic data); the shadow workspace is allocated here and
+        kept until set_temporal(False) or close."""
+        if not on:
+            _check(lib().sl_set_temporal(self.h, None, 0))
+            self._band_ws = None
+            return
+        n = C.c_size_t()
+        _check(lib().sl_temporal_workspace_size(self.h, C.byref(n)))
+        torch = _torch()
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        _check(lib().sl_set_temporal(self.h, C.c_void_p(ws.data_ptr() + off), n.value))
+        self._band_ws = ws
 
     def widen(self, i: int = -1):
         """Widen bf16 duals to float in place (problem i of a batch, -1: all)."""

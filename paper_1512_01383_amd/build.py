@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsublabel.so")
-SOURCES = ["capi.hip", "pdhg_iter.hip", "aux.hip", "adjoint.hip", "steps.hip", "stereo.hip"]
+SOURCES = ["capi.hip", "pdhg_iter.hip", "aux.hip", "adjoint.hip", "steps.hip", "stereo.hip", "temporal.hip"]
 ARCH = os.environ.get("SUBLABEL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

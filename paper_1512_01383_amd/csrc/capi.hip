@@ -250,6 +250,8 @@ struct sl_problem_ {
   size_t pin_n = 0;
   // allocation-free problems stage those copies in this fixed host array instead
   bool no_alloc = false;
+  // two iterations per pass (temporal blocking): the caller's shadow state, 8k+1 planes
+  char *band_ws = nullptr;
   double stage_fixed[16];
 
   // batch handles: sub-problems advance together in one persistent launch per iteration
@@ -426,7 +428,69 @@ IterPtrs<float> iter_ptrs_f(sl_problem_ *P) {
   return Q;
 }
 
-sl_status enqueue_iters(sl_problem_ *P, int iters) {
+// Four iterations as two passes of the two-iteration kernel: the state at n (main
+// workspace) to the shadow at n+2, and back to the main workspace at n+4 in the buffers the
+// rotation assigns to n+4 (u: slots iu and iu+1; s and p: the slots they hold now).
+sl_status band_quad(sl_problem_ *P) {
+  const size_t kps = (size_t)P->A.k * P->lay.ps;
+  float *sh = (float *)P->band_ws;
+  float *const sup = sh, *const su = sh + kps, *const ssp = sh + 2 * kps, *const ss = sh + 3 * kps,
+               *const sv = sh + 4 * kps, *const sz = sh + 5 * kps, *const sp = sh + 6 * kps, *const sq = sh + 8 * kps;
+  float *const v = (float *)(P->ws + P->lay.off_v), *const z = (float *)(P->ws + P->lay.off_z);
+  float *const q = (float *)(P->ws + P->lay.off_qd), *const pm = (float *)P->pbuf(P->ip);
+  BandPtrs a{};
+  a.u = P->ubuf(P->iu);
+  a.up = P->ubuf((P->iu + 2) % 3);
+  a.s = P->sbuf(P->is);
+  a.sp = P->sbuf(1 - P->is);
+  a.v = v;
+  a.z = z;
+  a.p = pm;
+  a.q = q;
+  a.uo = su;
+  a.upo = sup;
+  a.so = ss;
+  a.spo = ssp;
+  a.vo = sv;
+  a.zo = sz;
+  a.po = sp;
+  a.qo = sq;
+  a.fn = (const float *)(P->ws + P->lay.off_fn);
+  a.sinfo = (const unsigned *)(P->ws + P->lay.off_sinfo);
+  BandPtrs b = a;
+  b.u = su;
+  b.up = sup;
+  b.s = ss;
+  b.sp = ssp;
+  b.v = sv;
+  b.z = sz;
+  b.p = sp;
+  b.q = sq;
+  b.uo = P->ubuf((P->iu + 1) % 3);
+  b.upo = P->ubuf(P->iu);
+  b.so = P->sbuf(P->is);
+  b.spo = P->sbuf(1 - P->is);
+  b.vo = v;
+  b.zo = z;
+  b.po = pm;
+  b.qo = q;
+  hipError_t e = launch_pdhg_band(P->piece, a, P->A, P->st);
+  if (e == hipSuccess) e = launch_pdhg_band(P->piece, b, P->A, P->st);
+  if (e != hipSuccess) return hip_fail(e, "two-iteration launch");
+  P->iu = (P->iu + 1) % 3;
+  P->iters += 4;
+  return SL_OK;
+}
+
+// `iters` iterations; with a shadow workspace set (and band_ok) in groups of four by the
+// two-iteration kernel, the rest one at a time
+sl_status enqueue_iters(sl_problem_ *P, int iters, bool band_ok = true) {
+  if (band_ok && P->band_ws) {
+    for (; iters >= 4; iters -= 4) {
+      const sl_status s = band_quad(P);
+      if (s != SL_OK) return s;
+    }
+  }
   for (int n = 0; n < iters; n++) {
     IterPtrs<float> Q = iter_ptrs_f(P);
     hipError_t e;
@@ -1614,10 +1678,10 @@ sl_status sl_autotune(sl_problem P, int32_t iters, const char *cache_path, int32
       if (!cfg_fits(P, c)) continue;
       P->cfg = c;
       if (P->is_batch && batch_rebuild_items(P) != SL_OK) continue;
-      sl_status s = P->is_batch ? batch_enqueue(P, 6) : enqueue_iters(P, 2);
+      sl_status s = P->is_batch ? batch_enqueue(P, 6) : enqueue_iters(P, 2, false);
       if (s != SL_OK) return s;
       HIPCHK(hipEventRecord(e0, P->st), "event record");
-      s = P->is_batch ? batch_enqueue(P, iters) : enqueue_iters(P, iters);
+      s = P->is_batch ? batch_enqueue(P, iters) : enqueue_iters(P, iters, false);
       if (s != SL_OK) return s;
       HIPCHK(hipEventRecord(e1, P->st), "event record");
       HIPCHK(hipEventSynchronize(e1), "event sync");
@@ -1679,7 +1743,7 @@ sl_status sl_unrolled_forward(sl_problem P, int32_t K, int32_t C, void *ws, size
       ck += np[g] * pl;
     }
     HIPCHK(hipMemcpyAsync(ck, P->pbuf(P->ip), 2 * k * pl, hipMemcpyDeviceToDevice, P->st), "checkpoint");
-    s = enqueue_iters(P, std::min(C, K - c * C));
+    s = enqueue_iters(P, std::min(C, K - c * C), false);   // the replay's configuration
     if (s != SL_OK) return s;
   }
   P->uws = w;
@@ -1802,6 +1866,39 @@ sl_status sl_set_step_balance(sl_problem P, double c) {
   }
   P->step_c = P->step_c0 = c;
   fill_args(P);
+  return SL_OK;
+}
+
+// the cases the two-iteration kernel covers (SL_OK) or the reason it does not
+static sl_status temporal_check(const sl_problem_ *P) {
+  if (P->is_batch) return fail(SL_ERR_UNSUPPORTED, "two-iteration passes are for single problems");
+  if (P->A.k > SLI_BAND_MAXK) return fail(SL_ERR_UNSUPPORTED, "two-iteration passes need L <= %d", SLI_BAND_MAXK + 1);
+  if (P->piece == SLI_SAMPLED || P->add)
+    return fail(SL_ERR_UNSUPPORTED, "two-iteration passes cover quadratic and truncated-quadratic data without additive values");
+  if (P->bf16) return fail(SL_ERR_UNSUPPORTED, "two-iteration passes need FP32 storage");
+  return SL_OK;
+}
+
+sl_status sl_temporal_workspace_size(sl_problem P, size_t *bytes) {
+  if (!P || !bytes) return fail(SL_ERR_INVALID_ARG, "need a handle and bytes");
+  const sl_status s = temporal_check(P);
+  if (s != SL_OK) return s;
+  *bytes = (size_t)(8 * P->A.k + 1) * P->lay.ps * 4;
+  return SL_OK;
+}
+
+sl_status sl_set_temporal(sl_problem P, void *ws, size_t bytes) {
+  if (!P) return fail(SL_ERR_INVALID_ARG, "handle is NULL");
+  if (!ws) {
+    P->band_ws = nullptr;
+    return SL_OK;
+  }
+  const sl_status s = temporal_check(P);
+  if (s != SL_OK) return s;
+  const size_t need = (size_t)(8 * P->A.k + 1) * P->lay.ps * 4;
+  if ((uintptr_t)ws & 255) return fail(SL_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (bytes < need) return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, need);
+  P->band_ws = (char *)ws;
   return SL_OK;
 }
 

@@ -106,6 +106,16 @@ __device__ __forceinline__ void proj_K(float &px, float &py, float rad, bool ani
     ball(px, py, rad);
 }
 
+// p <- Proj_K(p + sigma_p (gx, gy)), K the disc or box of radius rad: one expression
+// wherever a p is formed, so that a p recomputed for a neighbour is bitwise the one its
+// owner stores
+__device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx, float gy, float rad,
+                                       bool aniso) {
+  px = px + spg * gx;
+  py = py + spg * gy;
+  proj_K(px, py, rad, aniso);
+}
+
 // ---------------------------------------------------------------- quadratic pieces
 
 // Centre of the quadratic piece on [g0, g1]: the data centre fc, or for periodic pieces the

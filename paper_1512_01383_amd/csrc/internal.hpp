@@ -99,6 +99,19 @@ int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax, int 
 size_t pdhg_iter_lds_bytes(int k, int label_groups, int tile_rows, int px);   // dynamic LDS
 size_t pdhg_iter_static_lds(int cfg);
 
+// Two iterations per pass for k <= SLI_BAND_MAXK (temporal.hip): the state at iteration n
+// (read, p = px planes then py planes) and the state at n+2 (written; upo gets n+1), in
+// distinct buffers.
+#define SLI_BAND_MAXK 3
+struct BandPtrs {
+  const float *u, *up, *s, *sp, *v, *z, *p, *q;
+  float *uo, *upo, *so, *spo, *vo, *zo, *po, *qo;
+  const float *fn;
+  const unsigned *sinfo;
+};
+// QUAD and TRUNC pieces without additive values, FP32 storage
+hipError_t launch_pdhg_band(int piece, const BandPtrs &P, const IterArgs &A, hipStream_t st);
+
 // Double-precision problem parameters for the monitor (the certificate is evaluated for
 // the problem defined by the caller's double labels / coefficients and the FP32 data).
 struct MonArgs {

@@ -49,16 +49,6 @@ __device__ __forceinline__ float from_left(float x, float first) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, first),
                                                                __builtin_bit_cast(int, x), 0x138, 0xF, 0xF, false));
 }
-// p <- Proj_K(p + sigma_p (gx, gy)), K the disc or box of radius rad: one expression
-// wherever a p is formed, so that a p recomputed for a neighbour is bitwise the one its
-// owner stores
-__device__ __forceinline__ void p_step(float &px, float &py, float spg, float gx, float gy, float rad,
-                                       bool aniso) {
-  px = px + spg * gx;
-  py = py + spg * gy;
-  proj_K(px, py, rad, aniso);
-}
-
 // PX consecutive pixels of one lane (PX = 1 or 2) at byte offset `off` of a plane: one
 // 32- or 64-bit range-checked buffer access (with PX = 2 the image width is even, so a
 // lane's pair never straddles a row end and its offset is 8-byte aligned, 4 for bf16)

@@ -37,7 +37,7 @@ def S():
 
 def test_library_exports_every_declared_entry_point(lib):
     names = _declared()
-    assert len(names) == 34, names   # the entry points of include/sublabel.h
+    assert len(names) == 36, names   # the entry points of include/sublabel.h
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -118,6 +118,13 @@ def test_argument_checks(lib, S):
     assert status(_desc(S, H=1 << 15, W=1 << 14)) == 2
     assert "2^29" in lib.sl_last_error().decode()
     assert status(_desc(S, H=(1 << 15) - 1, W=1 << 14)) == 0
+
+
+def test_temporal_calls_need_a_handle(lib):
+    n = C.c_size_t(0)
+    assert lib.sl_temporal_workspace_size(None, C.byref(n)) == 1
+    assert lib.sl_set_temporal(None, None, 0) == 1
+    assert lib.sl_set_temporal(None, C.c_void_p(256), 1 << 20) == 1
 
 
 def test_batch_workspace_size(lib, S):

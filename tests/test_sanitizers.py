@@ -39,7 +39,7 @@ def test_oracle_under_asan_ubsan(tmp_path):
 def test_c_abi_host_paths_under_asan_ubsan(tmp_path):
     hipcc = "/opt/rocm/bin/hipcc"
     clang = "/opt/rocm/llvm/bin/clang"
-    objs = [os.path.join(OBJDIR, n) for n in ("pdhg_iter.o", "aux.o", "adjoint.o", "steps.o", "stereo.o")]
+    objs = [os.path.join(OBJDIR, n) for n in ("pdhg_iter.o", "aux.o", "adjoint.o", "steps.o", "stereo.o", "temporal.o")]
     if not (os.path.exists(hipcc) and os.path.exists(clang) and all(os.path.exists(o) for o in objs)):
         pytest.skip("needs hipcc and the objects of a library build (run build() first)")
     from paper_1512_01383_amd import build as B

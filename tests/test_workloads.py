@@ -1,6 +1,7 @@
 """The seeded input generators (CPU): shapes, ranges and the data they promise, so that a
 change in them cannot pass unnoticed through both the oracle and the HIP path."""
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -44,3 +45,11 @@ def test_stereo_pair_and_costs_consistent():
     for d in (0, 5, 11):
         want = np.abs(left - right[:, np.maximum(cols - d, 0)])
         assert np.allclose(st.samples[d], want, atol=1e-6)
+
+
+def test_rectangles_need_room():
+    """The rectangle generator draws sides of at least 4 px: on a smaller image it raises
+    instead of drawing forever."""
+    with pytest.raises(ValueError):
+        W.rof(H=2, W=3)
+    assert W.rof(H=5, W=5).f.shape == (5, 5)

@@ -73,7 +73,9 @@ def rectangles_image(rng: np.random.Generator, H: int, W: int, n_rect: int = 8,
                      noise: float = 0.1) -> np.ndarray:
     """Background 0, ``n_rect`` axis-aligned rectangles (sides >= 4 px) with
     intensities U[0,1], later ones overwriting earlier ones, plus N(0, noise^2).
-    No clipping."""
+    No clipping. Needs H, W >= 5 (a rectangle of side >= 4 spans 5 pixels)."""
+    if H < 5 or W < 5:
+        raise ValueError(f"rectangles of side >= 4 px need an image of at least 5 x 5 pixels, not {H} x {W}")
     img = np.zeros((H, W), np.float64)
     for _ in range(n_rect):
         while True:
