@@ -278,9 +278,10 @@ def main():
                    "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage, "tv": args.tv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (None if args.workload != "tq" else
-                                 measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}"
-                                                  + ("_aniso" if wl.tv else ""))),
+                     "traffic": (measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}" + ("_aniso" if wl.tv else ""))
+                                 if args.workload == "tq" else
+                                 measured_traffic(f"stereo{wl.W}x{wl.H}_L{wl.L}_{args.storage}")
+                                 if args.workload == "stereo" else None),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "kernel_hash": kernel_hash(), "tiling": list(g.get_tiling())},
