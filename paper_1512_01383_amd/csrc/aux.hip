@@ -17,6 +17,7 @@
 
 #include "device_math.hpp"
 #include "internal.hpp"
+#include "checks.hpp"
 
 namespace {
 
@@ -236,13 +237,13 @@ constexpr int MT = MB / 64;
 
 // per-pixel terms: data parts of both primal bounds, dual, nonconvex data term
 template <int PIECE, bool ADD, typename DT>
-__global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPtrs M) {
+__device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long blk) {
   __shared__ double xa[MT][64], xb[MT][64];
   __shared__ int xn[MT][64];
   const long long N = (long long)A.H * A.W;
   const int lane = (int)(threadIdx.x & 63);
   const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const long long x0 = (long long)blockIdx.x * 64 + lane;
+  const long long x0 = blk * 64 + lane;
   const bool in = x0 < N;
   const long long x = in ? x0 : 0;
   const int k = A.k;
@@ -423,15 +424,20 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
     }
     vals[3] = e;
   }
-  block_sum(vals, 4, M.part1 + (long long)blockIdx.x * SLI_NMON);
+  block_sum(vals, 4, M.part1 + blk * SLI_NMON);
+}
+
+template <int PIECE, bool ADD, typename DT>
+__global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPtrs M) {
+  mon_pixel_body<PIECE, ADD, DT>(A, D, M, blockIdx.x);
 }
 
 // TV terms of both primal points and of the back-projected u (64 pixels x MT label chunks)
-__global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs M) {
+__device__ __forceinline__ void mon_tv_body(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long blk) {
   const long long N = (long long)A.H * A.W;
   const int lane = (int)(threadIdx.x & 63);
   const int t = (int)(threadIdx.x >> 6);
-  const long long x = (long long)blockIdx.x * 64 + lane;
+  const long long x = blk * 64 + lane;
   const int ch = (A.k + MT - 1) / MT;
   const int i0 = min(A.k, t * ch), i1 = min(A.k, i0 + ch);
   double vals[3] = {0, 0, 0};
@@ -474,14 +480,13 @@ __global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs 
       vals[2] = tv_norm(A, bx, by);
     }
   }
-  block_sum(vals, 3, M.part2 + (long long)blockIdx.x * SLI_NMON);
+  block_sum(vals, 3, M.part2 + blk * SLI_NMON);
 }
+__global__ __launch_bounds__(MB) void monitor_tv(IterArgs A, MonArgs D, MonPtrs M) { mon_tv_body(A, D, M, blockIdx.x); }
 
 // fixed-order reduction of per-block partials: block q reduces column q
-__global__ __launch_bounds__(MB) void monitor_final(const double *part1, const double *part2,
-                                                   int nb, double *out) {
+__device__ __forceinline__ void mon_final_body(const double *part1, const double *part2, int nb, double *out, int q) {
   __shared__ double red[MB];
-  const int q = blockIdx.x;
   const double *src = q < 4 ? part1 : part2;
   const int col = q < 4 ? q : q - 4;
   double acc = 0.0;
@@ -493,6 +498,41 @@ __global__ __launch_bounds__(MB) void monitor_final(const double *part1, const d
     __syncthreads();
   }
   if (threadIdx.x == 0) out[q] = red[0];
+}
+__global__ __launch_bounds__(MB) void monitor_final(const double *part1, const double *part2, int nb, double *out) {
+  mon_final_body(part1, part2, nb, out, blockIdx.x);
+}
+
+// Batched monitor: the blocks of every member of a list in one launch. first[l] is the first
+// block of list entry l (first[nl] the total), mem[l] its member; each block runs the lone
+// kernel's code on its member's parameters and block index, so every member's partial and
+// final sums are bitwise those of its own launches.
+template <int PIECE, bool ADD, typename DT>
+__global__ __launch_bounds__(MB) void monitor_pixel_batch(const IterArgs *__restrict__ A, const MonArgs *__restrict__ D,
+                                                          const MonPtrs *__restrict__ M, const int *__restrict__ mem,
+                                                          const int *__restrict__ first, int nl) {
+  long long blk;
+  int nb;
+  const int j = member_block(mem, first, nl, blk, nb);
+  mon_pixel_body<PIECE, ADD, DT>(A[j], D[j], M[j], blk);
+}
+
+__global__ __launch_bounds__(MB) void monitor_tv_batch(const IterArgs *__restrict__ A, const MonArgs *__restrict__ D,
+                                                       const MonPtrs *__restrict__ M, const int *__restrict__ mem,
+                                                       const int *__restrict__ first, int nl) {
+  long long blk;
+  int nb;
+  const int j = member_block(mem, first, nl, blk, nb);
+  mon_tv_body(A[j], D[j], M[j], blk);
+}
+
+// grid (7, nl): column blockIdx.x of list entry blockIdx.y
+__global__ __launch_bounds__(MB) void monitor_final_batch(const MonPtrs *__restrict__ M, const int *__restrict__ mem,
+                                                          const int *__restrict__ first) {
+  const int l = (int)blockIdx.y;
+  const int j = __builtin_amdgcn_readfirstlane(mem[l]);
+  const int nb = __builtin_amdgcn_readfirstlane(first[l + 1] - first[l]);
+  mon_final_body(M[j].part1, M[j].part2, nb, M[j].final_, (int)blockIdx.x);
 }
 
 template <int PIECE, bool ADD>
@@ -654,6 +694,33 @@ hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonArgs 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(monitor_final, dim3(7), dim3(MB), 0, st, M.part1, M.part2, nb, M.final_);
   if (nb_out) *nb_out = nb;
+  return hipGetLastError();
+}
+
+template <int PIECE, bool ADD>
+hipError_t launch_mon_batch_t(const MonBatch &B, hipStream_t st) {
+  if (B.n[0] > 0)
+    hipLaunchKernelGGL((monitor_pixel_batch<PIECE, ADD, uint16_t>), dim3(B.nblk[0]), dim3(MB), 0, st, B.A, B.D, B.M,
+                       B.mem[0], B.first[0], B.n[0]);
+  if (B.n[1] > 0)
+    hipLaunchKernelGGL((monitor_pixel_batch<PIECE, ADD, float>), dim3(B.nblk[1]), dim3(MB), 0, st, B.A, B.D, B.M,
+                       B.mem[1], B.first[1], B.n[1]);
+  return hipGetLastError();
+}
+
+hipError_t launch_monitor_batch(int piece, bool add, const MonBatch &B, hipStream_t st) {
+  if (B.n[2] == 0) return hipSuccess;
+  hipError_t e;
+  if (piece == SLI_QUAD)
+    e = add ? launch_mon_batch_t<SLI_QUAD, true>(B, st) : launch_mon_batch_t<SLI_QUAD, false>(B, st);
+  else if (piece == SLI_TRUNC)
+    e = add ? launch_mon_batch_t<SLI_TRUNC, true>(B, st) : launch_mon_batch_t<SLI_TRUNC, false>(B, st);
+  else
+    e = launch_mon_batch_t<SLI_SAMPLED, false>(B, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(monitor_tv_batch, dim3(B.nblk[2]), dim3(MB), 0, st, B.A, B.D, B.M, B.mem[2], B.first[2], B.n[2]);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(monitor_final_batch, dim3(7, B.n[2]), dim3(MB), 0, st, B.M, B.mem[2], B.first[2]);
   return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 
 #include "sublabel.h"
 #include "internal.hpp"
+#include "checks.hpp"
 #include "stereo.hpp"
 
 namespace {
@@ -271,6 +272,19 @@ struct sl_problem_ {
   std::vector<double> bfin_host;
   std::vector<char> ptrs_host;
   std::vector<IterArgs> args_host;
+  // batched monitor: per-member pointer and parameter tables, three member lists (device;
+  // host copies of what was last uploaded)
+  MonPtrs *mon_ptrs_dev = nullptr;
+  MonArgs *mon_args_dev = nullptr;
+  int *mon_list_dev = nullptr;
+  std::vector<MonPtrs> mon_ptrs_host;
+  std::vector<int> mon_list_host;
+  // batched residuals: the same for the residual pass (and where each member's sums go)
+  ResPtrs *res_ptrs_dev = nullptr;
+  double **res_out_dev = nullptr;
+  int *res_list_dev = nullptr;
+  std::vector<ResPtrs> res_ptrs_host;
+  std::vector<int> res_list_host;
   int kmax = 0;
   int64_t biters = 0;       // batch iterations since creation (rotation phase = biters % 6)
   hipStream_t cap = nullptr;
@@ -531,7 +545,7 @@ sl_status enqueue_iters(sl_problem_ *P, int iters, bool band_ok = true) {
 double *mon_out(sl_problem_ *P) { return P->fin_dev ? P->fin_dev : (double *)(P->ws + P->lay.off_fin); }
 
 // FP64 monitor of the current iterate, enqueued (its 7 sums land at mon_out(P))
-sl_status monitor_enqueue(sl_problem_ *P) {
+MonPtrs monitor_ptrs(sl_problem_ *P) {
   MonPtrs M;
   M.u = P->ubuf(P->iu);
   M.s = P->sbuf(P->is);
@@ -551,8 +565,91 @@ sl_status monitor_enqueue(sl_problem_ *P) {
   M.part2 = (double *)(P->ws + P->lay.off_part2);
   M.final_ = mon_out(P);
   M.bf16 = P->bf16;
+  return M;
+}
+
+sl_status monitor_enqueue(sl_problem_ *P) {
+  const MonPtrs M = monitor_ptrs(P);
   HIPCHK(launch_monitor(P->piece, P->add, P->A, P->D, M, P->st, nullptr), "monitor launch");
   return SL_OK;
+}
+
+// Member lists of a batched check launch (0: members with bf16 duals, 1: with float duals,
+// 2: both) over the members for which use(i) holds, each as mem[n] and first[n + 1] (the
+// first block of each entry, blocks(i) per member), packed into 3 (2n + 1) ints.
+template <class U, class NB>
+std::vector<int> member_lists(sl_problem_ *P, U use, NB blocks, int cnt[3], int nblk[3]) {
+  const int n = (int)P->sub.size();
+  std::vector<int> lists((size_t)3 * (2 * n + 1), 0);
+  for (int l = 0; l < 3; l++) {
+    int *mem = lists.data() + (size_t)l * (2 * n + 1), *first = mem + n;
+    int c = 0, b = 0;
+    for (int i = 0; i < n; i++) {
+      if (!use(i) || (l == 0 && !P->sub[i]->bf16) || (l == 1 && P->sub[i]->bf16)) continue;
+      mem[c] = i;
+      first[c] = b;
+      b += blocks(P->sub[i]);
+      c++;
+    }
+    first[c] = b;
+    cnt[l] = c;
+    nblk[l] = b;
+  }
+  return lists;
+}
+
+// upload `host` to `dev` on the batch's stream when it differs from the last upload `last`
+template <class T>
+sl_status upload_if_changed(sl_problem_ *P, const std::vector<T> &host, std::vector<T> &last, void *dev,
+                            const char *what) {
+  if (last.size() == host.size() && memcmp(last.data(), host.data(), host.size() * sizeof(T)) == 0) return SL_OK;
+  last = host;
+  HIPCHK(hipMemcpyAsync(dev, last.data(), last.size() * sizeof(T), hipMemcpyHostToDevice, P->st), what);
+  return SL_OK;
+}
+
+// Tables of the batched monitor for the active members as they stand (pointers follow each
+// member's rotation and storage): uploaded on the batch's stream when they differ from the
+// last upload, outside any captured graph (the graphs hold the tables' fixed addresses).
+sl_status batch_monitor_tables(sl_problem_ *P, MonBatch *B) {
+  const int n = (int)P->sub.size();
+  std::vector<MonPtrs> mp(n);
+  for (int i = 0; i < n; i++) mp[i] = monitor_ptrs(P->sub[i]);
+  const std::vector<int> lists = member_lists(
+      P, [&](int i) { return P->active[i] != 0; }, [](sl_problem_ *q) { return monitor_blocks(q->A); }, B->n,
+      B->nblk);
+  for (int l = 0; l < 3; l++) {
+    B->mem[l] = P->mon_list_dev + (size_t)l * (2 * n + 1);
+    B->first[l] = B->mem[l] + n;
+  }
+  B->A = P->args_dev;
+  B->D = P->mon_args_dev;
+  B->M = P->mon_ptrs_dev;
+  sl_status s = upload_if_changed(P, mp, P->mon_ptrs_host, P->mon_ptrs_dev, "monitor pointers");
+  if (s == SL_OK) s = upload_if_changed(P, lists, P->mon_list_host, P->mon_list_dev, "monitor lists");
+  return s;
+}
+
+ResPtrs residual_ptrs(sl_problem_ *P);
+
+// the same for the residual pass of the members with adaptive steps
+sl_status batch_residual_tables(sl_problem_ *P, ResBatch *B) {
+  const int n = (int)P->sub.size();
+  std::vector<ResPtrs> rp(n);
+  for (int i = 0; i < n; i++) rp[i] = residual_ptrs(P->sub[i]);
+  const std::vector<int> lists = member_lists(
+      P, [&](int i) { return P->active[i] && P->sub[i]->d.adaptive_steps; },
+      [](sl_problem_ *q) { return residual_blocks(q->A); }, B->n, B->nblk);
+  for (int l = 0; l < 3; l++) {
+    B->mem[l] = P->res_list_dev + (size_t)l * (2 * n + 1);
+    B->first[l] = B->mem[l] + n;
+  }
+  B->R = P->res_ptrs_dev;
+  B->A = P->args_dev;
+  B->out = P->res_out_dev;
+  sl_status s = upload_if_changed(P, rp, P->res_ptrs_host, P->res_ptrs_dev, "residual pointers");
+  if (s == SL_OK) s = upload_if_changed(P, lists, P->res_list_host, P->res_list_dev, "residual lists");
+  return s;
 }
 
 // the report from the monitor sums in P->fin (best-so-far bounds updated)
@@ -742,7 +839,10 @@ size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
   size_t items = 0;
   for (int t : maxtiles) items += (size_t)t;
   return 2 * align256(items * sizeof(BatchItem)) + 256 + align256((size_t)n * 6 * sizeof(IterPtrs<float>)) +
-         align256((size_t)n * sizeof(IterArgs)) + align256((size_t)n * 16 * sizeof(double));
+         align256((size_t)n * sizeof(IterArgs)) + align256((size_t)n * 16 * sizeof(double)) +
+         align256((size_t)n * sizeof(MonPtrs)) + align256((size_t)n * sizeof(MonArgs)) +
+         align256((size_t)3 * (2 * n + 1) * sizeof(int)) + align256((size_t)n * sizeof(ResPtrs)) +
+         align256((size_t)n * sizeof(double *)) + align256((size_t)3 * (2 * n + 1) * sizeof(int));
 }
 
 // work lists of the active instances (list 0: bf16 duals, list 1: float duals), each
@@ -982,23 +1082,23 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       });
       if (s != SL_OK) return s;
       if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
+      ResBatch rb{};
+      if ((s = batch_residual_tables(P, &rb)) != SL_OK) return s;
       s = batch_check_graph(P, 1, [&](hipStream_t st) {
-        return fork_members(P, st, active_adaptive, [P](sl_problem_ *q) {
-          size_t i = 0;
-          while (P->sub[i] != q) i++;
-          return residuals_enqueue(q, P->args_dev + i);
-        });
+        HIPCHK(launch_residuals_batch(rb, st), "batched residuals");
+        return SL_OK;
       });
       if (s != SL_OK) return s;
     } else if ((s = batch_enqueue(P, c)) != SL_OK) {
       return s;
     }
     done_n += c;
-    // every active member's monitor, then one copy of all sums and one wait
+    // every active member's monitor in one launch per stage, then one copy of all sums and
+    // one wait
+    MonBatch mb{};
+    if ((s = batch_monitor_tables(P, &mb)) != SL_OK) return s;
     s = batch_check_graph(P, 2, [&](hipStream_t st) {
-      const sl_status r = fork_members(P, st, [&](size_t i) { return P->active[i] != 0; },
-                                       [](sl_problem_ *q) { return monitor_enqueue(q); });
-      if (r != SL_OK) return r;
+      HIPCHK(launch_monitor_batch(P->piece, P->add, mb, st), "batched monitor");
       HIPCHK(hipMemcpyAsync(stage, P->bfin_dev, P->bfin_host.size() * sizeof(double), hipMemcpyDeviceToHost, st),
              "check copy");
       return SL_OK;
@@ -1071,7 +1171,7 @@ double *res_out(sl_problem_ *P) {
 
 // residual norms of the iteration that followed save_duals, enqueued (4 sums at res_out(P):
 // primal, dual, |K^T y|, |K x|); residuals_of_last also waits for them
-sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
+ResPtrs residual_ptrs(sl_problem_ *P) {
   const int k = P->A.k;
   const size_t pdb = (size_t)P->lay.ps * P->esz();
   char *ys = P->ws + P->lay.off_ysave;
@@ -1089,6 +1189,11 @@ sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
   R.p = P->pbuf(P->ip);
   R.po = P->pbuf(1 - P->ip);
   R.part = (double *)(P->ws + P->lay.off_rpart);
+  return R;
+}
+
+sl_status residuals_enqueue(sl_problem_ *P, const IterArgs *A_dev) {
+  const ResPtrs R = residual_ptrs(P);
   HIPCHK(launch_residuals(P->bf16, R, P->A, res_out(P), P->st, A_dev), "residuals");
   return SL_OK;
 }
@@ -1569,6 +1674,38 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->args_dev = (IterArgs *)(base + off);
   off += align256((size_t)n * sizeof(IterArgs));
   B->bfin_dev = (double *)(base + off);
+  off += align256((size_t)n * 16 * sizeof(double));
+  B->mon_ptrs_dev = (MonPtrs *)(base + off);
+  off += align256((size_t)n * sizeof(MonPtrs));
+  B->mon_args_dev = (MonArgs *)(base + off);
+  off += align256((size_t)n * sizeof(MonArgs));
+  B->mon_list_dev = (int *)(base + off);
+  off += align256((size_t)3 * (2 * n + 1) * sizeof(int));
+  B->res_ptrs_dev = (ResPtrs *)(base + off);
+  off += align256((size_t)n * sizeof(ResPtrs));
+  B->res_out_dev = (double **)(base + off);
+  off += align256((size_t)n * sizeof(double *));
+  B->res_list_dev = (int *)(base + off);
+  {
+    std::vector<MonArgs> dh(n);
+    std::vector<double *> ro(n);
+    for (int i = 0; i < n; i++) {
+      dh[i] = B->sub[i]->D;
+      ro[i] = B->bfin_dev + (size_t)i * 16 + 8;   // where the member's residual sums land
+    }
+    if (hipError_t e1 = hipMemcpyAsync(B->mon_args_dev, dh.data(), n * sizeof(MonArgs), hipMemcpyHostToDevice, B->st)) {
+      delete B;
+      return hip_fail(e1, "monitor tables");
+    }
+    if (hipError_t e1 = hipMemcpyAsync(B->res_out_dev, ro.data(), n * sizeof(double *), hipMemcpyHostToDevice, B->st)) {
+      delete B;
+      return hip_fail(e1, "residual tables");
+    }
+    if (hipError_t e1 = hipStreamSynchronize(B->st)) {
+      delete B;
+      return hip_fail(e1, "monitor tables");
+    }
+  }
   B->bfin_host.assign((size_t)n * 16, 0.0);
   for (int i = 0; i < n; i++) B->sub[i]->fin_dev = B->bfin_dev + (size_t)i * 16;
   B->ptrs_host.resize((size_t)n * 6 * sizeof(IterPtrs<float>));

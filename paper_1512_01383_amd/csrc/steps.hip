@@ -10,20 +10,21 @@
 // block adds them).
 #include "device_math.hpp"
 #include "internal.hpp"
+#include "checks.hpp"
 
 namespace {
 
 constexpr int RB = 256;
 
 template <typename DT>
-__device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs &A) {
+__device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs &A, long long blk, long long nblk) {
   __shared__ double sp_[RB], sd_[RB], sx_[RB], sy_[RB];
   const DT *v = (const DT *)R.v, *z = (const DT *)R.z, *vo = (const DT *)R.vo, *zo = (const DT *)R.zo;
   const DT *p = (const DT *)R.p, *po = (const DT *)R.po;
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps, N = (long long)H * W;
   double accp = 0.0, accd = 0.0, acckx = 0.0, accky = 0.0;
-  for (long long x = (long long)blockIdx.x * RB + threadIdx.x; x < N; x += (long long)gridDim.x * RB) {
+  for (long long x = blk * RB + threadIdx.x; x < N; x += nblk * RB) {
     const int r = (int)(x / W), c = (int)(x - (long long)r * W);
     const bool hr = c < W - 1, hl = c > 0, hd = r < H - 1, hu = r > 0;
     const int deg = hr + hl + hd + hu;
@@ -82,29 +83,41 @@ __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    R.part[4 * blockIdx.x] = sp_[0];
-    R.part[4 * blockIdx.x + 1] = sd_[0];
-    R.part[4 * blockIdx.x + 2] = sy_[0];   // |y|, the scale of the primal residual
-    R.part[4 * blockIdx.x + 3] = sx_[0];   // |x|, the scale of the dual residual
+    R.part[4 * blk] = sp_[0];
+    R.part[4 * blk + 1] = sd_[0];
+    R.part[4 * blk + 2] = sy_[0];   // |y|, the scale of the primal residual
+    R.part[4 * blk + 3] = sx_[0];   // |x|, the scale of the dual residual
   }
 }
 
 template <typename DT>
 __global__ __launch_bounds__(RB) void k_residuals(ResPtrs R, IterArgs A) {
-  residuals_body<DT>(R, A);
+  residuals_body<DT>(R, A, blockIdx.x, gridDim.x);
 }
 
 // the same with the problem's parameters read from device memory (a batch's table, which
 // the adaptive balance rewrites between checks while a captured graph keeps its arguments)
 template <typename DT>
 __global__ __launch_bounds__(RB) void k_residuals_tab(ResPtrs R, const IterArgs *__restrict__ Ap) {
-  residuals_body<DT>(R, *Ap);
+  residuals_body<DT>(R, *Ap, blockIdx.x, gridDim.x);
+}
+
+// every member of a list in one launch: each block runs the lone kernel's code with its
+// member's pointers, parameters, block index and block count, so the partial sums are
+// bitwise those of the member's own launch
+template <typename DT>
+__global__ __launch_bounds__(RB) void k_residuals_batch(const ResPtrs *__restrict__ R, const IterArgs *__restrict__ A,
+                                                        const int *__restrict__ mem, const int *__restrict__ first,
+                                                        int nl) {
+  long long blk;
+  int nb;
+  const int j = member_block(mem, first, nl, blk, nb);
+  residuals_body<DT>(R[j], A[j], blk, nb);
 }
 
 // block q (0..3) adds column q of the per-block quadruples, in block order
-__global__ __launch_bounds__(RB) void k_sum_quads(const double *part, int nb, double *out) {
+__device__ __forceinline__ void sum_quads_body(const double *part, int nb, double *out, int q) {
   __shared__ double a[RB];
-  const int q = blockIdx.x;
   double x = 0.0;
   for (int j = threadIdx.x; j < nb; j += RB) x += part[4 * j + q];
   a[threadIdx.x] = x;
@@ -115,8 +128,31 @@ __global__ __launch_bounds__(RB) void k_sum_quads(const double *part, int nb, do
   }
   if (threadIdx.x == 0) out[q] = a[0];
 }
+__global__ __launch_bounds__(RB) void k_sum_quads(const double *part, int nb, double *out) {
+  sum_quads_body(part, nb, out, blockIdx.x);
+}
+// grid (4, nl): column blockIdx.x of list entry blockIdx.y
+__global__ __launch_bounds__(RB) void k_sum_quads_batch(const ResPtrs *__restrict__ R, double *const *__restrict__ out,
+                                                        const int *__restrict__ mem, const int *__restrict__ first) {
+  const int l = (int)blockIdx.y;
+  const int j = __builtin_amdgcn_readfirstlane(mem[l]);
+  const int nb = __builtin_amdgcn_readfirstlane(first[l + 1] - first[l]);
+  sum_quads_body(R[j].part, nb, out[j], (int)blockIdx.x);
+}
 
 }  // namespace
+
+hipError_t launch_residuals_batch(const ResBatch &B, hipStream_t st) {
+  if (B.n[2] == 0) return hipSuccess;
+  if (B.n[0] > 0)
+    hipLaunchKernelGGL(k_residuals_batch<uint16_t>, dim3(B.nblk[0]), dim3(RB), 0, st, B.R, B.A, B.mem[0], B.first[0],
+                       B.n[0]);
+  if (B.n[1] > 0)
+    hipLaunchKernelGGL(k_residuals_batch<float>, dim3(B.nblk[1]), dim3(RB), 0, st, B.R, B.A, B.mem[1], B.first[1],
+                       B.n[1]);
+  hipLaunchKernelGGL(k_sum_quads_batch, dim3(4, B.n[2]), dim3(RB), 0, st, B.R, B.out, B.mem[2], B.first[2]);
+  return hipGetLastError();
+}
 
 int residual_blocks(const IterArgs &A) {
   const long long N = (long long)A.H * A.W;

@@ -197,3 +197,29 @@ def test_batch_rejects_mixed_kinds():
     wls = [_mixed_tq()[0], _mixed_sampled()[0]]
     with pytest.raises(S.SublabelError):
         S.BatchProblem(wls)
+
+
+def test_batched_monitor_matches_each_members_monitor(tmp_path, monkeypatch):
+    """The checks of a batch solve run every active member's certificate in one launch per
+    stage (members with bf16 and with float duals, both TV kinds); each member's bounds must
+    equal those of its own monitor on the same state, bit for bit. Every member retires at
+    the first check (tolerance 10), where the trace records the batched bounds."""
+    import json
+    trace = tmp_path / "trace.jsonl"
+    monkeypatch.setenv("SL_TRACE", str(trace))
+    wls = [W.truncated_quadratic(L=2, H=24, W=64, seed=91), W.truncated_quadratic(L=4, H=40, W=70, seed=92),
+           W.truncated_quadratic(L=6, H=17, W=130, seed=93), W.truncated_quadratic(L=3, H=64, W=64, seed=94)]
+    wls[3].tv = S.TV_ANISO
+    b = S.BatchProblem(wls, storage="bf16", check_every=48)
+    b.widen(1)
+    b.widen(3)
+    b.run(30)
+    b.run_to_gap(10.0, 48)
+    rows = [json.loads(line) for line in open(trace) if line.strip()]
+    retired = {r["member"]: r for r in rows if r["event"] == "retire"}
+    assert sorted(retired) == [0, 1, 2, 3]
+    for i in range(4):
+        e = b.energy_of(i)
+        assert e["primal_ub"] == retired[i]["primal"] and e["dual_lb"] == retired[i]["dual"], i
+    assert [b.storage_info(i)[0] for i in range(4)] == ["bf16", "fp32", "bf16", "fp32"]
+    b.close()
