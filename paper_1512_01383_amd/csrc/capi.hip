@@ -547,6 +547,7 @@ double *mon_out(sl_problem_ *P) { return P->fin_dev ? P->fin_dev : (double *)(P-
 // FP64 monitor of the current iterate, enqueued (its 7 sums land at mon_out(P))
 MonPtrs monitor_ptrs(sl_problem_ *P) {
   MonPtrs M;
+  memset(&M, 0, sizeof M);   // padding too: the batched check compares these tables bytewise
   M.u = P->ubuf(P->iu);
   M.s = P->sbuf(P->is);
   M.v = P->ws + P->lay.off_v;
@@ -1176,6 +1177,7 @@ ResPtrs residual_ptrs(sl_problem_ *P) {
   const size_t pdb = (size_t)P->lay.ps * P->esz();
   char *ys = P->ws + P->lay.off_ysave;
   ResPtrs R;
+  memset(&R, 0, sizeof R);   // padding too: the batched check compares these tables bytewise
   R.u = P->ubuf(P->iu);
   R.up = P->ubuf((P->iu + 2) % 3);
   R.s = P->sbuf(P->is);
