@@ -2,7 +2,7 @@
 
 Workload (default, --workload batch): 64 truncated-quadratic instances of mixed size
 (U{64,128,256,512}^2) and label count (U{2,4,8,16}), lambda = 0.25, solved together by one
-persistent launch per iteration with the duals stored in bf16 (FP32 arithmetic, FP64
+launch per iteration with the duals stored in bf16 (FP32 arithmetic, FP64
 certificate). One step is one check interval of the gap-controlled batch solve: 48 batched
 iterations followed by every member's FP64 certified-gap monitor and step balance, with
 inputs and state resident in HBM.
@@ -90,7 +90,7 @@ def main():
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--workload", default="batch",
                     choices=["tq", "stereo", "phase", "batch", "diff", "labels", "cpu", "temporal"],
-                    help="batch: 64 mixed instances in one persistent launch per iteration "
+                    help="batch: 64 mixed instances in one launch per iteration "
                          "(default); tq: one truncated-quadratic instance; diff: forward and "
                          "backward of 200 unrolled iterations (256x256, L=8)")
     ap.add_argument("--study", default="tq", choices=["tq", "phase", "stereo", "norm"],
@@ -547,7 +547,7 @@ def single_kernel_timing(S, wl, storage, dev, iters=200):
 
 def bench_batch(args):
     """Batched, mixed-precision solve: 64 truncated-quadratic instances of mixed size
-    (U{64,128,256,512}^2) and label count (U{2,4,8,16}) advanced together by one persistent
+    (U{64,128,256,512}^2) and label count (U{2,4,8,16}) advanced together by one
     launch per iteration (graph-replayed rotation period, autotuned tiling), duals stored in
     bf16 (FP32 arithmetic, FP64 certificate). One step is one check interval of the
     gap-controlled batch solve: CHECK_BATCH batched iterations, every member's FP64 monitor
@@ -721,7 +721,7 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": "batched mixed precision: 64 truncated-quadratic instances, sizes "
                                "U{64,128,256,512}^2, L U{2,4,8,16}, lambda=0.25, nu=0.025, in one "
-                               f"persistent launch per iteration; step = {CHECK_BATCH} batched "
+                               f"launch per iteration; step = {CHECK_BATCH} batched "
                                "iterations + every member's FP64 gap monitor and step balance",
                    "instances": len(wls), "pixel_label_per_iter": pli_it, "storage": storage,
                    "tiling": list(tiling)},

@@ -175,10 +175,10 @@ sl_status sl_load_state(sl_problem p, const void *dev_src, size_t bytes);
 
 /* Batched solve (many independent problems of uneven size and label count). All n
  * problems share the data-term kind, the storage and whether additive values are given;
- * each keeps its own labels, lambda, coefficients and image size. One persistent launch
- * per iteration advances every active problem: its blocks pull (problem, tile) work items
- * from a device counter, costliest problems first, and read each problem's parameters and
- * buffers from device tables. Runs of 6 iterations (one period of the buffer rotation)
+ * each keeps its own labels, lambda, coefficients and image size. One launch per
+ * iteration advances every active problem: one block per (problem, tile) work item,
+ * costliest problems first, each reading its problem's parameters and buffers from device
+ * tables. Runs of 6 iterations (one period of the buffer rotation)
  * are captured once in a hipGraph and replayed. sl_run and sl_run_to_gap accept the
  * batch handle; sl_run_to_gap checks every problem each check interval (rounded up to a
  * multiple of 6) and drops problems that reached the gap from the work list (their state
@@ -319,7 +319,8 @@ sl_status sl_storage_info(sl_problem p, int32_t i, int32_t *storage, int64_t *it
  * of the labels; with tile_cols = 128 every lane handles two horizontally adjacent pixels
  * (64- and 32-bit accesses instead of 32- and 16-bit ones: half the memory instructions per
  * pixel; the image width must be even, in a batch every member's). Supported (label_groups,
- * tile_rows): (1,4), (1,8), (2,4), (2,8), (4,4), each with tile_cols 64 or 128; (0,0,0)
+ * tile_rows): (1,4), (1,8), (2,4), (2,8), (4,4), each with tile_cols 64 or 128, and (1,2)
+ * with tile_cols 64; (0,0,0)
  * restores the automatic choice made by sl_create. The iterates differ between tilings only
  * by FP32 rounding of the label-chunk partial sums (tilings with the same label_groups give
  * bitwise the same iterates). Returns SL_ERR_UNSUPPORTED if the tiling needs more LDS than a

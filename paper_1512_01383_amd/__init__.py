@@ -361,7 +361,7 @@ class Problem:
 
 
 class BatchProblem(Problem):
-    """Many independent problems advanced together by one persistent launch per
+    """Many independent problems advanced together by one launch per
     iteration (sl_batch_create). ``instances`` are ``workloads.Workload``-like objects."""
 
     def __init__(self, instances, storage: str = "fp32", normalize: bool = True,

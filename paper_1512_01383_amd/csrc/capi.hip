@@ -255,7 +255,7 @@ struct sl_problem_ {
   char *band_ws = nullptr;
   double stage_fixed[16];
 
-  // batch handles: sub-problems advance together in one persistent launch per iteration
+  // batch handles: sub-problems advance together in one launch per iteration (and storage)
   bool is_batch = false;
   std::vector<sl_problem_ *> sub;
   std::vector<char> active;
@@ -265,7 +265,7 @@ struct sl_problem_ {
   int nlist[2] = {0, 0};    // items per list
   size_t list_cap = 0;      // list 1 starts at items_dev + list_cap (fixed)
   BatchItem *items_dev = nullptr;
-  int *count_dev = nullptr, *counter_dev = nullptr;   // per list, 16 ints apart
+  int *count_dev = nullptr;   // item count per list, 16 ints apart
   void *ptrs_dev = nullptr;
   IterArgs *args_dev = nullptr;
   double *bfin_dev = nullptr;      // 16 doubles per member: monitor sums, residual sums
@@ -834,6 +834,17 @@ int batch_tiles(const sl_problem_ *q, int cfg) {
   return ((q->A.H + th - 1) / th) * ((q->A.W + tw - 1) / tw);
 }
 
+// the most tiles an H x W member can have in any launch configuration (the work lists
+// are sized for it)
+int max_tiles(int H, int W) {
+  int m = 0;
+  for (int c = 0; c < SLI_NCFG; c++) {
+    const int th = kIterCfg[c][1], tw = 64 * kIterCfg[c][2];
+    m = std::max(m, ((H + th - 1) / th) * ((W + tw - 1) / tw));
+  }
+  return m;
+}
+
 // two work lists, each with room for every tile of every member (list 1 starts at a fixed
 // offset, so the pointers captured in a graph stay valid whatever the lists hold)
 size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
@@ -863,6 +874,8 @@ sl_status batch_rebuild_items(sl_problem_ *P) {
     for (int i : order)
       for (int t = 0; t < batch_tiles(P->sub[i], cfg); t++) P->items_host.push_back({i, t});
     P->nlist[list] = (int)(P->items_host.size() - before);
+    if ((size_t)P->nlist[list] > P->list_cap)   // the list region holds every member's tiles at most
+      return fail(SL_ERR_WORKSPACE, "work list of %d items exceeds its region of %zu", P->nlist[list], P->list_cap);
   }
   P->members_version++;
   int counts[32] = {};
@@ -885,7 +898,6 @@ BatchLaunch batch_launch(sl_problem_ *P, int list, int phase) {
   BatchLaunch L;
   L.items = P->items_dev + (list == 0 ? 0 : P->list_cap);
   L.count = P->count_dev + 16 * list;
-  L.counter = P->counter_dev + 16 * list;
   L.ptrs = P->ptrs_dev;
   L.args = P->args_dev;
   L.phase = phase;
@@ -893,11 +905,7 @@ BatchLaunch batch_launch(sl_problem_ *P, int list, int phase) {
   L.tvk = SLI_TV_DISC;
   for (size_t i = 0; i < P->sub.size(); i++)
     if (P->sub[i]->A.aniso) L.tvk = SLI_TV_PER_PROBLEM;
-  int dev = 0, ncu = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int occ = std::max(1, pdhg_batch_occupancy(P->piece, P->add, list == 0, P->cfg, P->kmax, L.tvk));
-  L.grid = (int)std::max(1LL, std::min((long long)occ * ncu, (long long)P->nlist[list]));
+  L.grid = std::max(1, P->nlist[list]);   // one block per item
   return L;
 }
 
@@ -1608,7 +1616,7 @@ sl_status sl_batch_workspace_size(const sl_problem_desc *descs, int32_t n, size_
     A.H = descs[i].H;
     A.W = descs[i].W;
     total += align256(make_layout(&descs[i], monitor_blocks(A)).total);
-    maxtiles.push_back(((descs[i].H + 3) / 4) * ((descs[i].W + 63) / 64));
+    maxtiles.push_back(max_tiles(descs[i].H, descs[i].W));
   }
   *bytes = total + batch_table_bytes(maxtiles, n);
   return SL_OK;
@@ -1652,7 +1660,7 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
     }
     B->sub.push_back(q);
     B->kmax = std::max(B->kmax, q->A.k);
-    maxtiles.push_back(((descs[i].H + 3) / 4) * ((descs[i].W + 63) / 64));
+    maxtiles.push_back(max_tiles(descs[i].H, descs[i].W));
     off += sz;
   }
   B->maxlds = B->sub[0]->maxlds;
@@ -1665,10 +1673,9 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->list_cap = align256(items_bytes) / sizeof(BatchItem);
   off += 2 * align256(items_bytes);
   B->count_dev = (int *)(base + off);
-  B->counter_dev = (int *)(base + off + 128);   // per list: next item, blocks done (zero between launches)
   if (hipError_t e0 = launch_fill_zero(base + off, 256, B->st)) {
     delete B;
-    return hip_fail(e0, "work counters");
+    return hip_fail(e0, "work list counts");
   }
   off += 256;
   B->ptrs_dev = base + off;

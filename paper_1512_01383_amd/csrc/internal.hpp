@@ -74,7 +74,7 @@ struct IterPtrs {
 // Launch configurations of the fused iteration: kIterCfg[c] = {label groups, tile rows,
 // pixels per lane}; a tile is 64 * pixels-per-lane columns wide. Two pixels per lane need an
 // even image width.
-#define SLI_NCFG 10
+#define SLI_NCFG 11
 extern const int kIterCfg[SLI_NCFG][3];
 hipError_t launch_pdhg_iter(int piece, bool add, bool bf16, int cfg, const IterArgs &A,
                             const void *ptrs, hipStream_t st);
@@ -86,8 +86,7 @@ struct BatchItem {
 };
 struct BatchLaunch {
   const BatchItem *items;
-  const int *count;
-  int *counter;
+  const int *count;       // the number of items (the grid has one block per item)
   const void *ptrs;
   const IterArgs *args;
   int phase, grid, kmax;
@@ -95,7 +94,6 @@ struct BatchLaunch {
 };
 hipError_t launch_pdhg_batch(int piece, bool add, bool bf16, int cfg, const BatchLaunch &L,
                              hipStream_t st);
-int pdhg_batch_occupancy(int piece, bool add, bool bf16, int cfg, int kmax, int tvk);  // blocks per CU
 size_t pdhg_iter_lds_bytes(int k, int label_groups, int tile_rows, int px);   // dynamic LDS
 size_t pdhg_iter_static_lds(int cfg);
 

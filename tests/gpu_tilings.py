@@ -2,7 +2,7 @@
 tile rows, tile columns); 128 columns = two pixels per lane, which needs an even width."""
 import pytest
 
-TILINGS = [(g, t, c) for c in (64, 128) for (g, t) in ((1, 4), (1, 8), (2, 4), (2, 8), (4, 4))]
+TILINGS = [(g, t, c) for c in (64, 128) for (g, t) in ((1, 4), (1, 8), (2, 4), (2, 8), (4, 4))] + [(1, 2, 64)]
 TILING_IDS = [f"g{g}t{t}c{c}" for g, t, c in TILINGS]
 
 

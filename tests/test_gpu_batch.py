@@ -1,4 +1,4 @@
-"""Batched solves (many independent problems per persistent launch, hipGraph replay of the
+"""Batched solves (many independent problems per launch, hipGraph replay of the
 iteration period, autotuned tiling) through the C-ABI. GPU only.
 
 The batch kernel runs the same per-tile code as the single-instance kernel, so a batch
