@@ -47,9 +47,9 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str, kernel: str = "pdhg_iter"):
+def measured_traffic(workload_key: str, kernel: str = "pdhg_iter", tiling=None):
     """HBM bytes per launch from the committed counter profile of this workload, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel sources and, when given, the same tiling (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_key}_traffic.json")
     try:
         with open(path) as f:
@@ -57,6 +57,8 @@ def measured_traffic(workload_key: str, kernel: str = "pdhg_iter"):
     except OSError:
         return None
     if prof.get("kernel_hash") != kernel_hash():
+        return None
+    if tiling is not None and prof.get("tiling") is not None and list(prof["tiling"]) != list(tiling):
         return None
     return prof.get("hbm_bytes_per_launch")
 
@@ -96,6 +98,9 @@ def main():
     ap.add_argument("--study", default="tq", choices=["tq", "phase", "stereo", "norm"],
                     help="data of the label-count study: truncated quadratic or phase unwrapping")
     ap.add_argument("--batch-iters", type=int, default=240)
+    ap.add_argument("--tiling", default=None,
+                    help="batch tiling 'groups,rows,cols' instead of the autotuned one (counter runs, "
+                         "whose serialised dispatches skew the autotuner's timings)")
     ap.add_argument("--no-extra", action="store_true",
                     help="batch mode: skip the single-instance kernel timings")
     args = ap.parse_args()
@@ -278,9 +283,10 @@ def main():
                    "H": wl.H, "W": wl.W, "L": wl.L, "storage": args.storage, "tv": args.tv},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}" + ("_aniso" if wl.tv else ""))
+                     "traffic": (measured_traffic(f"tq{wl.H}_L{wl.L}_{args.storage}" + ("_aniso" if wl.tv else ""),
+                                                  tiling=g.get_tiling())
                                  if args.workload == "tq" else
-                                 measured_traffic(f"stereo{wl.W}x{wl.H}_L{wl.L}_{args.storage}")
+                                 measured_traffic(f"stereo{wl.W}x{wl.H}_L{wl.L}_{args.storage}", tiling=g.get_tiling())
                                  if args.workload == "stereo" else None),
                      "kernel": "pdhg_iter_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -568,7 +574,11 @@ def bench_batch(args):
     pli_it = sum(w.H * w.W * w.k for w in wls)
 
     b = S.BatchProblem(wls, storage=storage, device=dev, adaptive=True, check_every=CHECK_BATCH)
-    tiling = b.autotune(iters=12)
+    if args.tiling:
+        tiling = tuple(int(x) for x in args.tiling.split(","))
+        b.set_tiling(*tiling)
+    else:
+        tiling = b.autotune(iters=12)
     b.set_finishing(0)            # the throughput steps stay in the requested storage
     stream = b.stream
 
@@ -727,7 +737,7 @@ def bench_batch(args):
                    "tiling": list(tiling)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"batch64_{storage}", kernel="pdhg_batch"),
+                     "traffic": measured_traffic(f"batch64_{storage}", kernel="pdhg_batch", tiling=tiling),
                      "kernel": "pdhg_batch_kernel", "kernel_ms": kern_ms,
                      "algorithmic_bytes_per_launch": bytes_launch, "kernel_hash": kernel_hash()},
         "cpu_baseline": cpu,
