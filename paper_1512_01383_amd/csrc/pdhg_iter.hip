@@ -106,9 +106,14 @@ __device__ __forceinline__ void bstvn(uint16_t *base, unsigned bytes, unsigned o
 // adjacent pixels of its row (PX = 2 halves the memory and address instructions per pixel;
 // the arithmetic per pixel and its order are the same, so the iterates are bitwise those
 // of PX = 1 with the same label groups).
-template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
+// SLD (one label group only): the walk loads s again with the step's other inputs instead
+// of keeping the phase-A copy in LDS. That halves the LDS per block, so more blocks fit on a
+// CU, which pays in batches of many small, latency-bound items; on a large lone image the
+// reloads come from beyond L2 and the kernel keeps the copy.
+template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX, bool SLD>
 __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs &A, int tile,
                                           float *dyn) {
+  static_assert(!SLD || G == 1, "s reloads need one label group");
   constexpr int NL = TW * TH;     // lanes of a label group
   constexpr int NP = NL * PX;     // pixels of a tile; LDS index of (pixel e of a lane, lane) is e*NL+lt
   constexpr int TWX = TW * PX;    // tile width in pixels
@@ -116,7 +121,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   __shared__ float ex[G][NP];      // per-chunk partial sums (reused: sbar sums, then v sums)
   __shared__ float stv[REG ? 1 : 2][REG ? 1 : NP], stz[REG ? 1 : 2][REG ? 1 : NP];  // straddle results
   float *lsb = dyn;               // [k][NP] sbar
-  float *lsa = dyn + A.k * NP;    // [k][NP] s, then the partial s update
+  float *lsa = dyn + A.k * NP;    // [k][NP] s, then the partial s update (not with SLD)
 
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps;
@@ -176,7 +181,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     for (int e = 0; e < PX; e++) {
       const float sb = 2.f * s[e] - sp[e];
       Tc[e] += A.h[i] * sb;
-      lsa[i * NP + e * NL + lt] = s[e];
+      if (!SLD) lsa[i * NP + e * NL + lt] = s[e];
       lsb[i * NP + e * NL + lt] = sb;
     }
   }
@@ -358,6 +363,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
   struct Step {
     float u[PX], up[PX], uu[PX], uup[PX], ud[PX], udp[PX], px[PX], py[PX], pxu[PX], pyu[PX], v[PX], z[PX],
         wh[PX];
+    float s[SLD ? PX : 1];
     float eu, eup, epx, epy;
     float smp[PX][kSmp];
   };
@@ -378,6 +384,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
     bldvn<PX>(o.pyu, ppy, bd, dm_up);
     bldvn<PX>(o.v, P.vi + (size_t)i * ps, bd, dm);
     bldvn<PX>(o.z, P.zi + (size_t)i * ps, bd, dm);
+    if constexpr (SLD) bldn<PX>(o.s, P.s + (size_t)i * ps, b4, xm);
     o.eu = bld(pu, b4, em);
     o.eup = bld(pup, b4, em);
     o.epx = bldv(ppx, bd, eml);
@@ -457,7 +464,7 @@ __device__ __forceinline__ void iter_tile(const IterPtrs<DT> &P, const IterArgs 
       if (c > 0) dv -= pxl;
       if (r < H - 1) dv += py[e];
       if (r > 0) dv -= pyu[e];
-      const float s = lsa[i * NP + e * NL + lt];
+      const float s = SLD ? cu.s[SLD ? e : 0] : lsa[i * NP + e * NL + lt];
       const float sb = lsb[i * NP + e * NL + lt];
       suf[e] -= hi * sb;
       const float whi = cu.wh[e];
@@ -597,7 +604,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_iter_kernel(IterPtrs<DT> P, 
   const int b = (int)blockIdx.x, xcd = b & 7, idx = b >> 3;
   const int per = nb >> 3, rem = nb & 7;
   const int tile = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-  iter_tile<PIECE, ADD, DT, G, TH, TVK, PX>(P, A, tile, dyn);
+  iter_tile<PIECE, ADD, DT, G, TH, TVK, PX, false>(P, A, tile, dyn);
 }
 
 // Batched iteration: one block per (instance, tile) work item of the list, in list order
@@ -614,7 +621,7 @@ __global__ __launch_bounds__(64 * TH * G) void pdhg_batch_kernel(
   if (it >= *count) return;
   const int inst = __builtin_amdgcn_readfirstlane(items[it].inst);
   const int tile = __builtin_amdgcn_readfirstlane(items[it].tile);
-  iter_tile<PIECE, ADD, DT, G, TH, TVK, PX>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
+  iter_tile<PIECE, ADD, DT, G, TH, TVK, PX, G == 1>(ptrs[inst * 6 + phase], args[inst], tile, dyn);
 }
 
 template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
@@ -627,10 +634,15 @@ hipError_t launch_t(const IterArgs &A, const void *ptrs, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dynamic LDS of the batch kernel: sbar, and s with several label groups (SLD otherwise)
+size_t pdhg_batch_lds_bytes(int k, int g, int th, int px) {
+  return (size_t)(g == 1 ? 1 : 2) * k * TW * th * px * sizeof(float);
+}
+
 template <int PIECE, bool ADD, typename DT, int G, int TH, int TVK, int PX>
 hipError_t launch_bt(const BatchLaunch &L, hipStream_t st) {
   hipLaunchKernelGGL((pdhg_batch_kernel<PIECE, ADD, DT, G, TH, TVK, PX>), dim3(L.grid), dim3(64 * TH * G),
-                     pdhg_iter_lds_bytes(L.kmax, G, TH, PX), st, L.items, L.count,
+                     pdhg_batch_lds_bytes(L.kmax, G, TH, PX), st, L.items, L.count,
                      (const IterPtrs<DT> *)L.ptrs, L.args, L.phase);
   return hipGetLastError();
 }
@@ -701,7 +713,7 @@ const int kIterCfg[SLI_NCFG][3] = {{1, 4, 1}, {1, 8, 1}, {2, 4, 1}, {2, 8, 1}, {
 
 size_t pdhg_iter_lds_bytes(int k, int g, int th, int px) {
   (void)g;
-  return (size_t)2 * k * TW * th * px * sizeof(float);
+  return (size_t)2 * k * TW * th * px * sizeof(float);   // sbar and s
 }
 
 size_t pdhg_iter_static_lds(int cfg) {
