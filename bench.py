@@ -579,7 +579,7 @@ def bench_batch(args):
         b.set_tiling(*tiling)
     else:
         tiling = b.autotune(iters=12)
-    b.set_finishing(0)            # the throughput steps stay in the requested storage
+    b.set_finishing(0, widen_gap=0.0)   # no widening: the throughput steps stay in the requested storage
     stream = b.stream
 
     def step():
