@@ -197,9 +197,11 @@ sl_status sl_batch_info(sl_problem p, int32_t i, int64_t *iters, int32_t *active
 /* Graph replay of batched iterations on (default) or off; results are identical. */
 sl_status sl_set_graphs(sl_problem p, int32_t enable);
 
-/* Tile-shape autotuner: times `iters` iterations with every tiling that fits, keeps the
- * fastest, then resets the iteration state (and the adaptive step balance) to its initial
- * value (call it before iterating). With a cache file (may be NULL) a tiling measured
+/* Tile-shape autotuner: times `iters` iterations with every tiling that fits, in two rounds
+ * (each tiling keeps its faster time, so the costlier first iterations from a fresh state
+ * do not count against the tiling timed first), keeps the fastest (a later tiling only if
+ * it is faster by more than 2 %), then resets the iteration state (and the adaptive step
+ * balance) to its initial value (call it before iterating). With a cache file (may be NULL) a tiling measured
  * before for the same device, kernel variant (data term, storage, TV kind), label count and
  * size bucket (power of two of the pixel count) is reused without timing, and new
  * measurements are appended as lines "key|tiling". The chosen (label_groups, tile_rows,

@@ -170,6 +170,33 @@ def test_batch_run_to_gap_retires_members():
     b.close()
 
 
+def test_batch_finishing_rule_off_and_immediate():
+    """With the finishing rule off (no stall count, widen gap 0) every member keeps bf16 duals
+    through any number of checks (the throughput measurement relies on it); with a widen gap
+    above every reachable gap each member widens at its first check, on its own, and keeps
+    counting its bf16 iterations."""
+    wls = _mixed_tq()[:5]
+    b = S.BatchProblem(wls, storage="bf16", adaptive=True, check_every=12)
+    b.set_finishing(0, widen_gap=0.0)
+    for _ in range(6):
+        b.run_to_gap(0.0, 12)            # a zero gap is never met: every member stays active
+    for i in range(len(wls)):
+        n, active = b.info_of(i)
+        assert active and n == 72
+        assert b.storage_info(i) == ("bf16", 72), i
+    b.close()
+    b = S.BatchProblem(wls, storage="bf16", adaptive=True, check_every=12)
+    b.set_finishing(0, widen_gap=1e30)
+    b.run_to_gap(0.0, 12)
+    for i in range(len(wls)):
+        assert b.storage_info(i) == ("fp32", 12), i
+    b.run_to_gap(0.0, 12)
+    for i in range(len(wls)):
+        assert b.storage_info(i) == ("fp32", 12), i
+        assert b.info_of(i)[0] == 24
+    b.close()
+
+
 def test_autotune_resets_state_and_uses_cache(tmp_path):
     wl = W.truncated_quadratic(L=10, H=64, W=128, seed=11)
     g = S.Problem.from_workload(wl)
