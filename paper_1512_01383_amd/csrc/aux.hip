@@ -228,12 +228,19 @@ __device__ void block_sum(double *vals, int nv, double *out_row) {
     for (int q = 0; q < nv; q++) out_row[q] = red[q][0];
 }
 
-// A monitor block covers 64 consecutive pixels (one wavefront) times MT label chunks (one
-// wavefront per chunk): with one thread per pixel a 256 x 256 image would leave one
-// wavefront per SIMD. Per-pixel couplings across labels (the simplex threshold, the
-// suffix of the repaired weights, the prefix of div p, the max over labels, the
+// A monitor block has MT wavefronts: groups of 64 consecutive pixels times label chunks
+// (one wavefront per chunk and group; more than one chunk only where a thread's registers
+// cannot hold the labels): with one thread per pixel and all labels a 256 x 256 image would
+// leave one wavefront per SIMD. Per-pixel couplings across labels (the simplex threshold,
+// the suffix of the repaired weights, the prefix of div p, the max over labels, the
 // back-projection) go through LDS in a fixed order.
 constexpr int MT = MB / 64;
+constexpr int MC = (SLI_MAXK + MT - 1) / MT;   // labels per thread at most (registers)
+
+// Label chunks per pixel: as few as the per-thread registers allow, so that problems with
+// few labels do not leave waves idle; the block's MT waves cover MT / chunks groups of 64
+// pixels (wave t: pixel group t / chunks, chunk t % chunks).
+__host__ __device__ inline int mon_chunks(int k) { return k <= MC ? 1 : k <= 2 * MC ? 2 : MT; }
 
 // per-pixel terms: data parts of both primal bounds, dual, nonconvex data term
 template <int PIECE, bool ADD, typename DT>
@@ -243,12 +250,14 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
   const long long N = (long long)A.H * A.W;
   const int lane = (int)(threadIdx.x & 63);
   const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const long long x0 = blk * 64 + lane;
+  const int k = A.k;
+  const int nc = mon_chunks(k);
+  const int pg = t / nc, tc = t - pg * nc, g0w = pg * nc;   // pixel group, chunk, its first wave
+  const long long x0 = (blk * (MT / nc) + pg) * 64 + lane;
   const bool in = x0 < N;
   const long long x = in ? x0 : 0;
-  const int k = A.k;
-  const int ch = (k + MT - 1) / MT;
-  const int i0 = min(k, t * ch), i1 = min(k, i0 + ch);
+  const int ch = (k + nc - 1) / nc;
+  const int i0 = min(k, tc * ch), i1 = min(k, i0 + ch);
   const int r = (int)(x / A.W), cc = (int)(x % A.W);
   double vals[4] = {0, 0, 0, 0};
   PieceD P;
@@ -261,7 +270,6 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
   // chunk of x (at most MC labels) is loaded once into registers; a block repeats a pass
   // while any of its pixels still removes labels (a pass that removes nothing leaves the
   // threshold unchanged).
-  constexpr int MC = (SLI_MAXK + MT - 1) / MT;
   double xv[MC];
 #pragma unroll
   for (int q = 0; q < MC; q++)
@@ -281,8 +289,7 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
     __syncthreads();
     double S = 0.0;
     int Nn = 0;
-#pragma unroll
-    for (int g = 0; g < MT; g++) {
+    for (int g = g0w; g < g0w + nc; g++) {
       S += xa[g][lane];
       Nn += xn[g][lane];
     }
@@ -301,9 +308,7 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
   xa[t][lane] = tw;
   __syncthreads();
   double lo = 0.0;
-#pragma unroll
-  for (int g = MT - 1; g >= 0; g--)
-    if (g > t) lo += xa[g][lane];
+  for (int g = g0w + nc - 1; g > t; g--) lo += xa[g][lane];
   double dat = 0.0;
   if (in) {
     // the chunk's u, all in flight at once; x_i = -h_i s_i is still in xv
@@ -384,10 +389,9 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
   __shared__ double xu[MT][64];
   xu[t][lane] = ub;
   __syncthreads();
-  if (t == 0 && in) {
+  if (tc == 0 && in) {
     double base = 0.0, mx = -INFINITY, tsum = D.gam[0];
-#pragma unroll
-    for (int g = 0; g < MT; g++) {
+    for (int g = g0w; g < g0w + nc; g++) {
       mx = max_nan(mx, base + xa[g][lane]);
       base += xb[g][lane];
       tsum += xu[g][lane];
@@ -432,14 +436,16 @@ __global__ __launch_bounds__(MB) void monitor_pixel(IterArgs A, MonArgs D, MonPt
   mon_pixel_body<PIECE, ADD, DT>(A, D, M, blockIdx.x);
 }
 
-// TV terms of both primal points and of the back-projected u (64 pixels x MT label chunks)
+// TV terms of both primal points and of the back-projected u (pixel groups x label chunks)
 __device__ __forceinline__ void mon_tv_body(const IterArgs &A, const MonArgs &D, const MonPtrs &M, long long blk) {
   const long long N = (long long)A.H * A.W;
   const int lane = (int)(threadIdx.x & 63);
-  const int t = (int)(threadIdx.x >> 6);
-  const long long x = blk * 64 + lane;
-  const int ch = (A.k + MT - 1) / MT;
-  const int i0 = min(A.k, t * ch), i1 = min(A.k, i0 + ch);
+  const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nc = mon_chunks(A.k);
+  const int pg = t / nc, tc = t - pg * nc;                  // pixel group, label chunk
+  const long long x = (blk * (MT / nc) + pg) * 64 + lane;
+  const int ch = (A.k + nc - 1) / nc;
+  const int i0 = min(A.k, tc * ch), i1 = min(A.k, i0 + ch);
   double vals[3] = {0, 0, 0};
   if (x < N) {
     const int r = (int)(x / A.W), cc = (int)(x % A.W);
@@ -449,7 +455,6 @@ __device__ __forceinline__ void mon_tv_body(const IterArgs &A, const MonArgs &D,
     double tr = 0.0, tg = 0.0;
     // the chunk's repaired u at the pixel and its right and lower neighbours, all loads in
     // flight at once, then the sums in label order
-    constexpr int MC = (SLI_MAXK + MT - 1) / MT;
     double u0[MC], ur[MC], ud[MC];
 #pragma unroll
     for (int q = 0; q < MC; q++) {
@@ -475,7 +480,7 @@ __device__ __forceinline__ void mon_tv_body(const IterArgs &A, const MonArgs &D,
     }
     vals[0] = tr;
     vals[1] = tg;
-    if (t == 0) {
+    if (tc == 0) {
       double bx = hx ? b[x + 1] - b[x] : 0.0, by = hy ? b[x + A.W] - b[x] : 0.0;
       vals[2] = tv_norm(A, bx, by);
     }
@@ -677,7 +682,8 @@ inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, 64); }
+int monitor_blocks(const IterArgs &A) { return (int)nblk((long long)A.H * A.W, 64 * (MT / mon_chunks(A.k))); }
+int monitor_blocks_max(long long N) { return (int)nblk(N, 64); }   // one group of 64 pixels per block
 
 hipError_t launch_monitor(int piece, bool add, const IterArgs &A, const MonArgs &D,
                           const MonPtrs &M, hipStream_t st, int *nb_out) {

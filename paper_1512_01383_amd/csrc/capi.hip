@@ -241,7 +241,7 @@ struct sl_problem_ {
   double best_P = 0, best_D = 0;
   bool have_best = false;
   int check_every = 50;
-  int nb_mon = 0;
+  int nb_mon = 0;   // capacity of the monitor's partial-sum regions, in blocks
   float tau_tab[SLI_MAXM][4] = {};   // per sample: position, 1/(1+t^2), 1/(t_m - t_{m-1}), 0
   double taud_host[SLI_MAXM] = {};
   double fin[SLI_NMON];
@@ -1392,10 +1392,7 @@ sl_status sl_workspace_size(const sl_problem_desc *desc, size_t *bytes) {
   if (!bytes) return fail(SL_ERR_INVALID_ARG, "bytes is NULL");
   sl_status s = validate(desc);
   if (s != SL_OK) return s;
-  IterArgs A{};
-  A.H = desc->H;
-  A.W = desc->W;
-  *bytes = make_layout(desc, monitor_blocks(A)).total;
+  *bytes = make_layout(desc, monitor_blocks_max((long long)desc->H * desc->W)).total;
   return SL_OK;
 }
 
@@ -1406,10 +1403,7 @@ static sl_status init_impl(sl_problem_ *P, const sl_problem_desc *desc, void *ws
   sl_status s = validate(desc);
   if (s != SL_OK) return s;
   if (!ws || ((uintptr_t)ws & 255)) return fail(SL_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
-  IterArgs A0{};
-  A0.H = desc->H;
-  A0.W = desc->W;
-  const int nb_mon = monitor_blocks(A0);
+  const int nb_mon = monitor_blocks_max((long long)desc->H * desc->W);
   Layout lay = make_layout(desc, nb_mon);
   if (bytes < lay.total)
     return fail(SL_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", bytes, lay.total);
@@ -1612,10 +1606,7 @@ sl_status sl_batch_workspace_size(const sl_problem_desc *descs, int32_t n, size_
   for (int i = 0; i < n; i++) {
     sl_status s = validate(&descs[i]);
     if (s != SL_OK) return fail(s, "instance %d: %s", i, g_err.c_str());
-    IterArgs A{};
-    A.H = descs[i].H;
-    A.W = descs[i].W;
-    total += align256(make_layout(&descs[i], monitor_blocks(A)).total);
+    total += align256(make_layout(&descs[i], monitor_blocks_max((long long)descs[i].H * descs[i].W)).total);
     maxtiles.push_back(max_tiles(descs[i].H, descs[i].W));
   }
   *bytes = total + batch_table_bytes(maxtiles, n);
@@ -1648,10 +1639,7 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   size_t off = 0;
   std::vector<int> maxtiles;
   for (int i = 0; i < n; i++) {
-    IterArgs A{};
-    A.H = descs[i].H;
-    A.W = descs[i].W;
-    const size_t sz = align256(make_layout(&descs[i], monitor_blocks(A)).total);
+    const size_t sz = align256(make_layout(&descs[i], monitor_blocks_max((long long)descs[i].H * descs[i].W)).total);
     sl_problem q = nullptr;
     s = create_impl(&descs[i], base + off, sz, stream, &q);
     if (s != SL_OK) {

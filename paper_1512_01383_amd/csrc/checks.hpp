@@ -4,6 +4,12 @@
 #pragma once
 
 #include "internal.hpp"
+
+// A monitor launch has monitor_blocks(A) blocks, fewer for small label counts (a block
+// then covers several groups of 64 pixels); the partial-sum regions of a workspace hold
+// monitor_blocks_max(H * W), the most any label count needs.
+int monitor_blocks_max(long long N);
+
 // The monitors of several problems of one kind (piece, additive values) in one launch per
 // stage: per-member parameter and pointer tables (device), and three lists of members
 // (0: bf16 duals, 1: float duals, 2: all), each as mem[n] (member index) and first[n + 1]
