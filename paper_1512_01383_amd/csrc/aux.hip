@@ -558,6 +558,35 @@ __global__ void k_fill_zero(uint4 *dst, size_t n16) {
   for (; i < n16; i += stride) dst[i] = make_uint4(0, 0, 0, 0);
 }
 
+// segment copies of a batch's dual save: block b copies its share of the segment whose
+// first block is the last one <= b
+__global__ __launch_bounds__(256) void k_copy_batch(const CopySeg *__restrict__ seg, const int *__restrict__ first,
+                                                    int n) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const uint4 *src = seg[lo].src;
+  uint4 *dst = seg[lo].dst;
+  const long long n16 = seg[lo].n16;
+  const long long u0 = (long long)(b - first[lo]) * kCopyUnits + threadIdx.x;
+  uint4 v[kCopyUnits / 256];
+#pragma unroll
+  for (int q = 0; q < kCopyUnits / 256; q++) {
+    const long long u = u0 + q * 256;
+    if (u < n16) v[q] = src[u];
+  }
+#pragma unroll
+  for (int q = 0; q < kCopyUnits / 256; q++) {
+    const long long u = u0 + q * 256;
+    if (u < n16) dst[u] = v[q];
+  }
+}
+
 // bf16 values widened to float (exact); src and dst must not overlap
 __global__ void k_widen_bf16(const uint16_t *__restrict__ src, float *__restrict__ dst, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -727,6 +756,12 @@ hipError_t launch_monitor_batch(int piece, bool add, const MonBatch &B, hipStrea
   hipLaunchKernelGGL(monitor_tv_batch, dim3(B.nblk[2]), dim3(MB), 0, st, B.A, B.D, B.M, B.mem[2], B.first[2], B.n[2]);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(monitor_final_batch, dim3(7, B.n[2]), dim3(MB), 0, st, B.M, B.mem[2], B.first[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_batch(const CopyBatch &B, hipStream_t st) {
+  if (B.n == 0 || B.nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_batch, dim3(B.nblk), dim3(256), 0, st, B.seg, B.first, B.n);
   return hipGetLastError();
 }
 

@@ -285,6 +285,11 @@ struct sl_problem_ {
   int *res_list_dev = nullptr;
   std::vector<ResPtrs> res_ptrs_host;
   std::vector<int> res_list_host;
+  // batched dual save: segment table and first blocks (device; host copies of the last upload)
+  CopySeg *copy_seg_dev = nullptr;
+  int *copy_first_dev = nullptr;
+  std::vector<CopySeg> copy_seg_host;
+  std::vector<int> copy_first_host;
   int kmax = 0;
   int64_t biters = 0;       // batch iterations since creation (rotation phase = biters % 6)
   hipStream_t cap = nullptr;
@@ -653,6 +658,43 @@ sl_status batch_residual_tables(sl_problem_ *P, ResBatch *B) {
   return s;
 }
 
+// the dual save (v, z, q before the interval's last iteration) of every active member with
+// adaptive steps as one segment table, uploaded like the tables above; three segments per
+// member, in member order
+sl_status batch_copy_tables(sl_problem_ *P, CopyBatch *B) {
+  std::vector<CopySeg> segs;
+  std::vector<int> first;
+  int nb = 0;
+  auto add = [&](const char *src, char *dst, size_t bytes) {
+    CopySeg c;
+    memset(&c, 0, sizeof c);
+    c.src = (const uint4 *)src;
+    c.dst = (uint4 *)dst;
+    c.n16 = (long long)(bytes / 16);
+    first.push_back(nb);
+    nb += (int)((c.n16 + kCopyUnits - 1) / kCopyUnits);
+    segs.push_back(c);
+  };
+  for (size_t i = 0; i < P->sub.size(); i++) {
+    if (!P->active[i] || !P->sub[i]->d.adaptive_steps) continue;
+    sl_problem_ *q = P->sub[i];
+    const int k = q->A.k;
+    const size_t pdb = (size_t)q->lay.ps * q->esz(), pfb = (size_t)q->lay.ps * 4;
+    char *ys = q->ws + q->lay.off_ysave;
+    add(q->ws + q->lay.off_v, ys, k * pdb);
+    add(q->ws + q->lay.off_z, ys + k * pdb, k * pdb);
+    add(q->ws + q->lay.off_qd, ys + 2 * k * pdb, pfb);
+  }
+  first.push_back(nb);
+  B->seg = P->copy_seg_dev;
+  B->first = P->copy_first_dev;
+  B->n = (int)segs.size();
+  B->nblk = nb;
+  sl_status s = upload_if_changed(P, segs, P->copy_seg_host, P->copy_seg_dev, "dual save segments");
+  if (s == SL_OK) s = upload_if_changed(P, first, P->copy_first_host, P->copy_first_dev, "dual save blocks");
+  return s;
+}
+
 // the report from the monitor sums in P->fin (best-so-far bounds updated)
 sl_status monitor_finish(sl_problem_ *P, sl_report *out) {
   const double lam = P->lam;
@@ -854,7 +896,8 @@ size_t batch_table_bytes(const std::vector<int> &maxtiles, int n) {
          align256((size_t)n * sizeof(IterArgs)) + align256((size_t)n * 16 * sizeof(double)) +
          align256((size_t)n * sizeof(MonPtrs)) + align256((size_t)n * sizeof(MonArgs)) +
          align256((size_t)3 * (2 * n + 1) * sizeof(int)) + align256((size_t)n * sizeof(ResPtrs)) +
-         align256((size_t)n * sizeof(double *)) + align256((size_t)3 * (2 * n + 1) * sizeof(int));
+         align256((size_t)n * sizeof(double *)) + align256((size_t)3 * (2 * n + 1) * sizeof(int)) +
+         align256((size_t)3 * n * sizeof(CopySeg)) + align256((size_t)(3 * n + 1) * sizeof(int));
 }
 
 // work lists of the active instances (list 0: bf16 duals, list 1: float duals), each
@@ -1086,8 +1129,11 @@ sl_status batch_run_to_gap(sl_problem_ *P, double tol, int32_t max_iters, int32_
       // as for a single problem: the interval's last iteration measures each member's
       // residuals, which rebalance that member's steps
       if ((s = batch_enqueue(P, c - 1)) != SL_OK) return s;
+      CopyBatch cb{};
+      if ((s = batch_copy_tables(P, &cb)) != SL_OK) return s;
       s = batch_check_graph(P, 0, [&](hipStream_t st) {
-        return fork_members(P, st, active_adaptive, [](sl_problem_ *q) { return save_duals(q); });
+        HIPCHK(launch_copy_batch(cb, st), "batched dual save");
+        return SL_OK;
       });
       if (s != SL_OK) return s;
       if ((s = batch_enqueue(P, 1)) != SL_OK) return s;
@@ -1683,6 +1729,10 @@ sl_status sl_batch_create(const sl_problem_desc *descs, int32_t n, void *ws, siz
   B->res_out_dev = (double **)(base + off);
   off += align256((size_t)n * sizeof(double *));
   B->res_list_dev = (int *)(base + off);
+  off += align256((size_t)3 * (2 * n + 1) * sizeof(int));
+  B->copy_seg_dev = (CopySeg *)(base + off);
+  off += align256((size_t)3 * n * sizeof(CopySeg));
+  B->copy_first_dev = (int *)(base + off);
   {
     std::vector<MonArgs> dh(n);
     std::vector<double *> ro(n);

@@ -52,3 +52,20 @@ __device__ __forceinline__ int member_block(const int *__restrict__ mem, const i
   nb = __builtin_amdgcn_readfirstlane(first[lo + 1]) - f0;
   return __builtin_amdgcn_readfirstlane(mem[lo]);
 }
+
+// The dual save of a batch check (v, z and q of every member with adaptive steps, before
+// the interval's last iteration, for the residuals) in one launch: segments of 16-byte
+// units {src, dst, n16}; first[j] is the first block of segment j (first[n] = nblk), and a
+// block copies kCopyUnits units of its segment.
+struct CopySeg {
+  const uint4 *src;
+  uint4 *dst;
+  long long n16;
+};
+constexpr int kCopyUnits = 2048;   // 256 threads x 8
+struct CopyBatch {
+  const CopySeg *seg;
+  const int *first;
+  int n, nblk;
+};
+hipError_t launch_copy_batch(const CopyBatch &B, hipStream_t st);
