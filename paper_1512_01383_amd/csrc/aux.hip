@@ -190,6 +190,16 @@ __device__ void make_piece(const IterArgs &A, const MonArgs &D, const MonPtrs &M
   }
 }
 
+// a truncated-quadratic interval that straddles a band edge (the classification of
+// make_piece): its piece is the hull of the interval's samples
+template <int PIECE>
+__device__ __forceinline__ bool straddles(const IterArgs &A, float fc, int i) {
+  if (PIECE != SLI_TRUNC) return false;
+  const float lo = fc - A.del, hb = fc + A.del;
+  const float g0 = A.gam[i], g1 = A.gam[i + 1];
+  return !(lo <= g0 && g1 <= hb) && !(g1 <= lo || g0 >= hb);
+}
+
 // maximum that keeps a NaN operand (fmax drops it): a non-finite dual point must give a
 // non-finite bound, not the maximum over its finite labels
 __device__ __forceinline__ double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
@@ -309,8 +319,13 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
   __syncthreads();
   double lo = 0.0;
   for (int g = g0w + nc - 1; g > t; g--) lo += xa[g][lane];
+  // The pieces of straddling truncated-quadratic intervals (at most two per pixel) are
+  // evaluated after the label loops below: inside them a wave would scan a hull at every
+  // label where one of its 64 pixels straddles, outside it scans two.
   double dat = 0.0;
   if (in) {
+    int sa = -1, sb = -1;
+    double wa = 0.0, aa = 0.0, wb = 0.0, ab = 0.0;
     // the chunk's u, all in flight at once; x_i = -h_i s_i is still in xv
     float uq[MC];
 #pragma unroll
@@ -325,10 +340,28 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
       if (wi > 0.0) al = fmin(fmax((uq[q] - lo) / wi, 0.0), 1.0);
       M.mon_u[i * A.ps + x] = lo + wi * al;
       if (wi > 0.0) {
-        make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
-        dat += wi * val_full(P, D.gam[i] + D.h[i] * al);
+        if (straddles<PIECE>(A, pfc, i) && sa < 0) {
+          sa = i;
+          wa = wi;
+          aa = al;
+        } else if (straddles<PIECE>(A, pfc, i) && sb < 0) {
+          sb = i;
+          wb = wi;
+          ab = al;
+        } else {
+          make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
+          dat += wi * val_full(P, D.gam[i] + D.h[i] * al);
+        }
       }
       lo += wi;
+    }
+    if (sa >= 0) {
+      make_piece<PIECE, ADD>(A, D, M, x, sa, pfc, pc, P);
+      dat += wa * val_full(P, D.gam[sa] + D.h[sa] * aa);
+    }
+    if (sb >= 0) {
+      make_piece<PIECE, ADD>(A, D, M, x, sb, pfc, pc, P);
+      dat += wb * val_full(P, D.gam[sb] + D.h[sb] * ab);
     }
   }
   vals[0] = dat;
@@ -355,6 +388,8 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
     o.u = M.u[b + x];
   };
   if (in && i0 < i1) {
+    int sa = -1, sb = -1;   // straddling intervals, evaluated after the loop
+    double pa = 0.0, ya = 0.0, pb = 0.0, yb = 0.0;
     PIn cur, nxt;
     pload(i0, cur);
     for (int i = i0; i < i1; i++) {
@@ -375,12 +410,30 @@ __device__ __forceinline__ void mon_pixel_body(const IterArgs &A, const MonArgs 
         proj_K_d(A, rad, qx, qy);
         vh -= qy;
       }
-      make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
       const double y = vh * D.ih[i];
-      mloc = max_nan(mloc, pre - D.gam[i] * y + conj_full(P, y));
+      if (straddles<PIECE>(A, pfc, i) && sa < 0) {
+        sa = i;
+        pa = pre;
+        ya = y;
+      } else if (straddles<PIECE>(A, pfc, i) && sb < 0) {
+        sb = i;
+        pb = pre;
+        yb = y;
+      } else {
+        make_piece<PIECE, ADD>(A, D, M, x, i, pfc, pc, P);
+        mloc = max_nan(mloc, pre - D.gam[i] * y + conj_full(P, y));
+      }
       pre += vh;
       ub += D.h[i] * fmin(fmax((double)cur.u, 0.0), 1.0);
       cur = nxt;
+    }
+    if (sa >= 0) {
+      make_piece<PIECE, ADD>(A, D, M, x, sa, pfc, pc, P);
+      mloc = max_nan(mloc, pa - D.gam[sa] * ya + conj_full(P, ya));
+    }
+    if (sb >= 0) {
+      make_piece<PIECE, ADD>(A, D, M, x, sb, pfc, pc, P);
+      mloc = max_nan(mloc, pb - D.gam[sb] * yb + conj_full(P, yb));
     }
   }
   __syncthreads();   // every read of xa above is done
