@@ -24,11 +24,13 @@ __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs 
   const int H = A.H, W = A.W, k = A.k;
   const long long ps = A.ps, N = (long long)H * W;
   double accp = 0.0, accd = 0.0, acckx = 0.0, accky = 0.0;
+  // steps enter as reciprocals: one division per step instead of one per residual entry
+  const float isig_p = 1.f / A.sig_p;
   for (long long x = blk * RB + threadIdx.x; x < N; x += nblk * RB) {
     const int r = (int)(x / W), c = (int)(x - (long long)r * W);
     const bool hr = c < W - 1, hl = c > 0, hd = r < H - 1, hu = r > 0;
     const int deg = hr + hl + hd + hu;
-    const float tau_u = A.tau_c / (1.f + (float)deg);
+    const float itau_u = (1.f + (float)deg) / A.tau_c;
     float T = 0.f;
     for (int i = 0; i < k; i++) {
       const size_t o = (size_t)i * ps;
@@ -52,12 +54,13 @@ __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs 
       const float gx = hr ? (R.up[o + x + 1] - R.u[o + x + 1]) - du : 0.f;
       const float gy = hd ? (R.up[o + x + W] - R.u[o + x + W]) - du : 0.f;
       suf -= A.h[i] * ds;
-      const float rpu = du / tau_u - (dv - div);
-      const float rps = ds / A.taus[i] - (dz - A.h[i] * dq + A.h[i] * pre - A.gam[i] * dv);
+      const float itaus = 1.f / A.taus[i], isig = 1.f / A.sig[i];
+      const float rpu = du * itau_u - (dv - div);
+      const float rps = ds * itaus - (dz - A.h[i] * dq + A.h[i] * pre - A.gam[i] * dv);
       pre += dv;
-      const float rdv = dv / A.sig[i] - (du - A.gam[i] * ds + suf);
-      const float rdz = dz / A.sig[i] - ds;
-      const float rdx = dpx / A.sig_p - gx, rdy = dpy / A.sig_p - gy;
+      const float rdv = dv * isig - (du - A.gam[i] * ds + suf);
+      const float rdz = dz * isig - ds;
+      const float rdx = dpx * isig_p - gx, rdy = dpy * isig_p - gy;
       accp += (double)fabsf(rpu) + (double)fabsf(rps);
       accd += (double)fabsf(rdv) + (double)fabsf(rdz) + (double)fabsf(rdx) + (double)fabsf(rdy);
       // the variables at the new iterate: x = (u, s), y = (v, z, p, q)
@@ -65,7 +68,7 @@ __device__ __forceinline__ void residuals_body(const ResPtrs &R, const IterArgs 
       accky += (double)fabsf(ldv(v, o + x)) + (double)fabsf(ldv(z, o + x)) + (double)fabsf(ldv(p, o + x)) +
                (double)fabsf(ldv(p, oy + x));
     }
-    accd += (double)fabsf(dq / A.sig_q + T);
+    accd += (double)fabsf(dq * (1.f / A.sig_q) + T);
     accky += (double)fabsf(R.q[x]);
   }
   sp_[threadIdx.x] = accp;
