@@ -131,6 +131,26 @@ def test_monitor_on_identical_state(orc, name, wl):
     assert _rel(eg["e_nonconvex"], eo["e_nc"]) < 1e-9
 
 
+# label counts at the monitor's chunk boundaries (a block covers 4, 2 or 1 groups of 64
+# pixels for k <= 8, <= 16 and above), on sizes whose pixel count leaves the last block
+# partly empty; truncated quadratics exercise the straddle pieces evaluated after the loops
+CHUNK_CASES = [(f"tq_k{L - 1}_{H}x{Wd}", W.truncated_quadratic(L=L, H=H, W=Wd, seed=300 + L))
+               for (L, H, Wd) in ((9, 7, 83), (10, 5, 131), (17, 9, 45), (18, 3, 101), (2, 1, 1), (28, 2, 70))]
+
+
+@pytest.mark.parametrize("name,wl", CHUNK_CASES, ids=[c[0] for c in CHUNK_CASES])
+def test_monitor_at_chunk_boundaries(orc, name, wl):
+    g, o = _pair(wl, orc)
+    st = W.random_state(13, wl.k, wl.H, wl.W, scale=0.3)
+    _load_same_state(g, o, st)
+    eg = g.energy()
+    eo = o.monitor()
+    assert _rel(eg["primal_ub"], eo["primal"]) < 1e-9
+    assert _rel(eg["dual_lb"], eo["dual"]) < 1e-9
+    assert _rel(eg["e_nonconvex"], eo["e_nc"]) < 1e-9
+    g.close()
+
+
 def test_rof_2000_iterations(orc):
     """ROF 64x64, L = 2, lambda = 0.2, 2000 iterations: max |du| <= 1e-4, energies 1e-5."""
     wl = W.rof()
